@@ -1,0 +1,407 @@
+"""Seeded synthetic random-feature-method problems.
+
+This module only *describes* problems: the box partition, the fixed random
+feature parameters, the collocation point groups with their data, the PDE
+operator as a list of terms, and a manufactured solution with its closed-form
+derivatives.  It contains none of the solver's arithmetic (no feature
+evaluation, no residual, no Jacobian, no sketch), so it can feed both the GPU
+library and the CPU oracle without coupling them.
+
+Problem setting (paper, Sec. 2.1 and Sec. 2.2): P(u) = lambda*L u + mu*N(u) = f
+in Omega and B u = g on the boundary; the box Omega_c is split into
+non-overlapping boxes, each carrying J tanh features whose weights and biases
+are drawn uniformly from [-R, R] and then frozen.  Collocation follows Sec. 5:
+uniform grids that include the end points, interface grids that carry C^0 and
+C^1 continuity rows, and boundary grids on the outer faces.
+
+Row order.  Every ``PointGroup`` shares one owner box (and one neighbour box
+for continuity groups).  Groups are listed in the order
+[PDE groups; continuity groups; outer-boundary groups; hole-surface groups],
+i.e. F = [R_pde; R_con; R_bdy] of Alg. 3, and a consumer expands each group
+into rows ordered (equation or component, continuity order, point).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# point kinds
+KIND_PDE = 0
+KIND_DIRICHLET = 1
+KIND_NEUMANN = 2
+KIND_CONTINUITY = 3
+
+# derivative selectors of a linear term
+D_ID = 0                 # the value itself
+D_X0, D_X1, D_X2, D_X3 = 1, 2, 3, 4   # first derivative along axis k is 1 + k
+D_LAPLACE = 8            # sum of second derivatives over all axes
+D_LAPLACE_SPACE = 9      # sum of second derivatives over all axes but the last (time)
+
+
+@dataclass
+class PointGroup:
+    kind: int
+    x: np.ndarray                       # [npts, dim] float64
+    owner: int                          # box that owns every point of the group
+    neighbor: int = -1                  # second box (continuity groups only)
+    normal: Optional[np.ndarray] = None  # [npts, dim] (Neumann, continuity)
+    comp: int = -1                      # -1: all components/equations, else one
+    cont_order: int = 1                 # continuity groups: 1 -> C0, 2 -> C0 + C1
+    data: Optional[np.ndarray] = None   # PDE: [npts, neq]; Dirichlet/Neumann: [npts, ncomp_sel]
+
+    @property
+    def npts(self) -> int:
+        return int(self.x.shape[0])
+
+
+@dataclass
+class Problem:
+    name: str
+    dim: int
+    ncomp: int
+    lo: np.ndarray
+    hi: np.ndarray
+    nsub: np.ndarray                   # boxes per axis, axis 0 fastest in the box index
+    J: int                             # features per box and component
+    W: np.ndarray                      # [Mp, ncomp, J, dim]
+    b: np.ndarray                      # [Mp, ncomp, J]
+    groups: List[PointGroup]
+    lin_terms: List[Tuple[int, int, float, int]]            # (eq, comp, coeff, deriv)
+    poly_terms: List[Tuple[int, float, Tuple[int, ...]]]    # (eq, coeff, powers per component)
+    exact: Callable[[np.ndarray], np.ndarray]               # u*(x) -> [npts, ncomp]
+    test_x: np.ndarray                 # [ntest, dim] points for the relative L2 error
+    test_owner: np.ndarray             # [ntest] int32
+    params: dict = field(default_factory=dict)
+
+    @property
+    def nbox(self) -> int:
+        return int(np.prod(self.nsub))
+
+    @property
+    def n(self) -> int:
+        return self.nbox * self.ncomp * self.J
+
+    @property
+    def neq(self) -> int:
+        return self.ncomp
+
+    def group_rows(self, g: PointGroup) -> int:
+        if g.kind == KIND_PDE:
+            return g.npts * (self.neq if g.comp < 0 else 1)
+        nc = self.ncomp if g.comp < 0 else 1
+        if g.kind == KIND_CONTINUITY:
+            return g.npts * nc * g.cont_order
+        return g.npts * nc
+
+    @property
+    def m(self) -> int:
+        return int(sum(self.group_rows(g) for g in self.groups))
+
+
+# ----------------------------------------------------------------------------
+# geometry helpers
+# ----------------------------------------------------------------------------
+
+def box_index(multi: Sequence[int], nsub: Sequence[int]) -> int:
+    e, stride = 0, 1
+    for a, i in enumerate(multi):
+        e += int(i) * stride
+        stride *= int(nsub[a])
+    return e
+
+
+def box_multi(e: int, nsub: Sequence[int]) -> Tuple[int, ...]:
+    out = []
+    for a in range(len(nsub)):
+        out.append(e % int(nsub[a]))
+        e //= int(nsub[a])
+    return tuple(out)
+
+
+def box_bounds(e: int, lo, hi, nsub) -> Tuple[np.ndarray, np.ndarray]:
+    mi = box_multi(e, nsub)
+    h = (np.asarray(hi, float) - np.asarray(lo, float)) / np.asarray(nsub, float)
+    blo = np.asarray(lo, float) + np.asarray(mi, float) * h
+    return blo, blo + h
+
+
+def tensor_grid(axes: Sequence[np.ndarray]) -> np.ndarray:
+    """Cartesian product of 1-D point sets, first axis varying fastest."""
+    mesh = np.meshgrid(*axes[::-1], indexing="ij")
+    return np.stack([mm.ravel() for mm in mesh[::-1]], axis=1)
+
+
+def box_grid(blo, bhi, q: Sequence[int]) -> np.ndarray:
+    return tensor_grid([np.linspace(blo[a], bhi[a], q[a]) for a in range(len(q))])
+
+
+def face_grid(blo, bhi, axis: int, coord: float, qf: int) -> np.ndarray:
+    d = len(blo)
+    axes = []
+    for a in range(d):
+        if a == axis:
+            axes.append(np.array([coord]))
+        else:
+            axes.append(np.linspace(blo[a], bhi[a], qf))
+    return tensor_grid(axes)
+
+
+def cell_centres(blo, bhi, per_dim: int) -> np.ndarray:
+    axes = []
+    for a in range(len(blo)):
+        h = (bhi[a] - blo[a]) / per_dim
+        axes.append(blo[a] + (np.arange(per_dim) + 0.5) * h)
+    return tensor_grid(axes)
+
+
+def draw_features(seed: int, nbox: int, ncomp: int, J: int, dim: int, R: float):
+    """Feature weights then biases, each uniform on [-R, R] (Sec. 2.2)."""
+    rng = np.random.default_rng(seed)
+    W = rng.uniform(-R, R, size=(nbox, ncomp, J, dim))
+    b = rng.uniform(-R, R, size=(nbox, ncomp, J))
+    return W, b
+
+
+# ----------------------------------------------------------------------------
+# manufactured solutions: value, gradient, full and spatial Laplacian
+# ----------------------------------------------------------------------------
+
+Jet = Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]  # val[n,K], grad[n,K,d], lap[n,K], lap_space[n,K]
+
+
+def jet_config1(x: np.ndarray) -> Jet:
+    X, Y = x[:, 0], x[:, 1]
+    pi = math.pi
+    sx, sy, cx, cy = np.sin(pi * X), np.sin(pi * Y), np.cos(pi * X), np.cos(pi * Y)
+    val = sx * sy + 0.5 * X * Y
+    gx = pi * cx * sy + 0.5 * Y
+    gy = pi * sx * cy + 0.5 * X
+    lap = -2.0 * pi * pi * sx * sy
+    return val[:, None], np.stack([gx, gy], 1)[:, None, :], lap[:, None], lap[:, None]
+
+
+def jet_config2(x: np.ndarray, amp: float = 0.5) -> Jet:
+    pi = math.pi
+    s = [np.sin(pi * x[:, a]) for a in range(3)]
+    c = [np.cos(pi * x[:, a]) for a in range(3)]
+    sss = s[0] * s[1] * s[2]
+    ccc = c[0] * c[1] * c[2]
+    u = 1.0 - amp * sss
+    v = 0.25 * ccc
+    gu = np.stack([-amp * pi * c[0] * s[1] * s[2], -amp * pi * s[0] * c[1] * s[2], -amp * pi * s[0] * s[1] * c[2]], 1)
+    gv = np.stack([-0.25 * pi * s[0] * c[1] * c[2], -0.25 * pi * c[0] * s[1] * c[2], -0.25 * pi * c[0] * c[1] * s[2]], 1)
+    lu = 3.0 * pi * pi * amp * sss
+    lv = -0.75 * pi * pi * ccc
+    val = np.stack([u, v], 1)
+    grad = np.stack([gu, gv], 1)
+    lap = np.stack([lu, lv], 1)
+    return val, grad, lap, lap
+
+
+def jet_config3(x: np.ndarray, kappa: float = 8.0) -> Jet:
+    w = kappa / math.sqrt(3.0)
+    s = [np.sin(w * x[:, a]) for a in range(3)]
+    c = [np.cos(w * x[:, a]) for a in range(3)]
+    val = s[0] * s[1] * s[2]
+    grad = np.stack([w * c[0] * s[1] * s[2], w * s[0] * c[1] * s[2], w * s[0] * s[1] * c[2]], 1)
+    lap = -3.0 * w * w * val
+    return val[:, None], grad[:, None, :], lap[:, None], lap[:, None]
+
+
+def jet_config4(x: np.ndarray) -> Jet:
+    X, Y, T = x[:, 0], x[:, 1], x[:, 2]
+    pi = math.pi
+    th = np.tanh((X - 0.3 - 0.4 * T) / 0.1)
+    sech2 = 1.0 - th * th
+    cy, sy = np.cos(pi * Y), np.sin(pi * Y)
+    val = th * cy
+    gx = 10.0 * sech2 * cy
+    gy = -pi * th * sy
+    gt = -4.0 * sech2 * cy
+    uxx = -200.0 * th * sech2 * cy
+    uyy = -pi * pi * th * cy
+    utt = 16.0 * (-2.0 * th * sech2) * cy
+    lap_space = uxx + uyy
+    lap = lap_space + utt
+    return val[:, None], np.stack([gx, gy, gt], 1)[:, None, :], lap[:, None], lap_space[:, None]
+
+
+def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int) -> np.ndarray:
+    """Right-hand side f = P(u*) at the points, one column per equation."""
+    val, grad, lap, lap_space = jet
+    n = val.shape[0]
+    f = np.zeros((n, neq))
+    for (q, c, coeff, deriv) in lin_terms:
+        if deriv == D_ID:
+            term = val[:, c]
+        elif D_X0 <= deriv <= D_X3:
+            term = grad[:, c, deriv - 1]
+        elif deriv == D_LAPLACE:
+            term = lap[:, c]
+        elif deriv == D_LAPLACE_SPACE:
+            term = lap_space[:, c]
+        else:
+            raise ValueError(deriv)
+        f[:, q] += coeff * term
+    for (q, coeff, pw) in poly_terms:
+        term = np.ones(n)
+        for c, p in enumerate(pw):
+            if p:
+                term = term * val[:, c] ** p
+        f[:, q] += coeff * term
+    return f
+
+
+# ----------------------------------------------------------------------------
+# generic box-partition builder
+# ----------------------------------------------------------------------------
+
+def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_terms, poly_terms,
+           seed=0, dirichlet_faces=None, test_per_dim=None, inside=None, extra_groups=None,
+           params=None):
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    nsub = np.asarray(nsub, np.int64)
+    nbox = int(np.prod(nsub))
+    W, b = draw_features(seed, nbox, ncomp, J, dim, R)
+    exact = lambda x: jet_fn(x)[0]
+    groups: List[PointGroup] = []
+    keep = (lambda p: np.ones(p.shape[0], bool)) if inside is None else inside
+
+    # PDE groups, box by box
+    for e in range(nbox):
+        blo, bhi = box_bounds(e, lo, hi, nsub)
+        pts = box_grid(blo, bhi, [q_int] * dim)
+        pts = pts[keep(pts)]
+        if pts.shape[0] == 0:
+            continue
+        f = apply_operator_to_jet(jet_fn(pts), lin_terms, poly_terms, ncomp)
+        groups.append(PointGroup(KIND_PDE, pts, e, data=f))
+
+    # continuity groups: direction, plane, transverse box (axis 0 fastest)
+    for a in range(dim):
+        for p in range(int(nsub[a]) - 1):
+            for e in range(nbox):
+                mi = box_multi(e, nsub)
+                if mi[a] != p:
+                    continue
+                mj = list(mi)
+                mj[a] = p + 1
+                e2 = box_index(mj, nsub)
+                blo, bhi = box_bounds(e, lo, hi, nsub)
+                pts = face_grid(blo, bhi, a, bhi[a], q_face)
+                pts = pts[keep(pts)]
+                if pts.shape[0] == 0:
+                    continue
+                nrm = np.zeros_like(pts)
+                nrm[:, a] = 1.0
+                groups.append(PointGroup(KIND_CONTINUITY, pts, e, neighbor=e2, normal=nrm, comp=-1, cont_order=2))
+
+    # outer faces: x=lo, x=hi, y=lo, y=hi, ...; boxes on the face axis-0 fastest
+    faces = dirichlet_faces if dirichlet_faces is not None else [(a, s) for a in range(dim) for s in (0, 1)]
+    for (a, side) in faces:
+        for e in range(nbox):
+            mi = box_multi(e, nsub)
+            if mi[a] != (0 if side == 0 else int(nsub[a]) - 1):
+                continue
+            blo, bhi = box_bounds(e, lo, hi, nsub)
+            coord = lo[a] if side == 0 else hi[a]
+            pts = face_grid(blo, bhi, a, coord, q_face)
+            pts = pts[keep(pts)]
+            if pts.shape[0] == 0:
+                continue
+            g = jet_fn(pts)[0]
+            groups.append(PointGroup(KIND_DIRICHLET, pts, e, comp=-1, data=g))
+
+    if extra_groups is not None:
+        groups.extend(extra_groups(lo, hi, nsub, jet_fn))
+
+    # relative-L2 test set: cell centres, 2*q_int per axis per box, inside Omega
+    tpd = test_per_dim if test_per_dim is not None else 2 * q_int
+    tx, to = [], []
+    for e in range(nbox):
+        blo, bhi = box_bounds(e, lo, hi, nsub)
+        pts = cell_centres(blo, bhi, tpd)
+        pts = pts[keep(pts)]
+        tx.append(pts)
+        to.append(np.full(pts.shape[0], e, np.int32))
+    return Problem(name=name, dim=dim, ncomp=ncomp, lo=lo, hi=hi, nsub=nsub, J=J, W=W, b=b,
+                   groups=groups, lin_terms=list(lin_terms), poly_terms=list(poly_terms),
+                   exact=exact, test_x=np.concatenate(tx), test_owner=np.concatenate(to),
+                   params=dict(params or {}, seed=seed, R=R, q_int=q_int, q_face=q_face))
+
+
+# ----------------------------------------------------------------------------
+# the workloads
+# ----------------------------------------------------------------------------
+
+def config1(nsub=(2, 2), J=200, q=20, seed=0, R=1.0, test_per_dim=None) -> Problem:
+    """2-D  -Lap u + u^3 = f on [0,1]^2, u* = sin(pi x) sin(pi y) + x y / 2, Dirichlet."""
+    lin = [(0, 0, -1.0, D_LAPLACE)]
+    poly = [(0, 1.0, (3,))]
+    return _build("poisson_cubic_2d", 2, 1, (0, 0), (1, 1), nsub, J, R, q, q, jet_config1, lin, poly,
+                  seed=seed, test_per_dim=test_per_dim)
+
+
+GS_F, GS_K = 0.04, 0.06
+
+
+def gray_scott_terms(F=GS_F, k=GS_K, Du=1.0, Dv=0.5):
+    lin = [(0, 0, -Du, D_LAPLACE), (0, 0, F, D_ID),
+           (1, 1, -Dv, D_LAPLACE), (1, 1, F + k, D_ID)]
+    # u v^2 enters equation 0 with + and equation 1 with -;  the constant -F of
+    # -F(1-u) is carried by the data of equation 0
+    poly = [(0, 1.0, (1, 2)), (1, -1.0, (1, 2))]
+    return lin, poly
+
+
+def config2(nsub=(4, 4, 4), J=300, q=10, seed=0, R=1.5, F=GS_F, k=GS_K, amp=0.5,
+            test_per_dim=None) -> Problem:
+    """3-D steady Gray-Scott on the unit cube with a manufactured pair (u*, v*)."""
+    lin, poly = gray_scott_terms(F, k)
+    jet = lambda x: jet_config2(x, amp)
+    return _build("gray_scott_3d", 3, 2, (0, 0, 0), (1, 1, 1), nsub, J, R, q, q, jet, lin, poly,
+                  seed=seed, test_per_dim=test_per_dim, params=dict(F=F, k=k, amp=amp))
+
+
+def config3_nohole(nsub=(8, 8, 8), J=250, q=8, seed=0, R=1.0, test_per_dim=None) -> Problem:
+    """3-D nonlinear Helmholtz  -Lap u - kappa^2 u + u^3 = f  (kappa = 8) on the full cube."""
+    kap = 8.0
+    lin = [(0, 0, -1.0, D_LAPLACE), (0, 0, -kap * kap, D_ID)]
+    poly = [(0, 1.0, (3,))]
+    return _build("helmholtz_3d", 3, 1, (0, 0, 0), (1, 1, 1), nsub, J, R, q, q, jet_config3, lin, poly,
+                  seed=seed, test_per_dim=test_per_dim)
+
+
+def config4_nohole(nsub=(4, 4, 8), J=400, q=12, seed=0, R=1.0, test_per_dim=None) -> Problem:
+    """Space-time Allen-Cahn u_t - 0.01 Lap u - u + u^3 = f on [0,1]^2 x [0,1].
+
+    Time is the last coordinate (Sec. 2.1): the initial condition is a Dirichlet
+    face at t = 0 and there is no row at t = 1.
+    """
+    lin = [(0, 0, 1.0, D_X2), (0, 0, -0.01, D_LAPLACE_SPACE), (0, 0, -1.0, D_ID)]
+    poly = [(0, 1.0, (3,))]
+    faces = [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0)]
+    return _build("allen_cahn_st", 3, 1, (0, 0, 0), (1, 1, 1), nsub, J, R, q, q, jet_config4, lin, poly,
+                  seed=seed, dirichlet_faces=faces, test_per_dim=test_per_dim)
+
+
+def make_config(i: int, **kw) -> Problem:
+    return [config1, config2, config3_nohole, config4_nohole][i](**kw)
+
+
+def jet_of(problem: Problem):
+    """Closed-form jet of the problem's manufactured solution."""
+    name = problem.name
+    if name == "poisson_cubic_2d":
+        return jet_config1
+    if name == "gray_scott_3d":
+        return lambda x: jet_config2(x, problem.params.get("amp", 0.5))
+    if name == "helmholtz_3d":
+        return jet_config3
+    if name == "allen_cahn_st":
+        return jet_config4
+    raise KeyError(name)

@@ -1,0 +1,425 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test targets a mistake that could plausibly sit in the oracle: a dropped
+term, a wrong sign, a transposed operand or an off-by-one in the row layout.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import rfm_workloads as W
+from oracle import philox as P
+from oracle import rfm as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# row layout: counts printed in the paper
+# ---------------------------------------------------------------------------
+
+def _golden_rows():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "row_counts.txt")):
+        line = line.split("#")[0].split()
+        if line:
+            rows.append(line)
+    return rows
+
+
+def _cube_problem(q, J, ncomp, cont_orders, dirichlet_comps, nsub=(2, 2, 2)):
+    """(2,2,2) boxes on the unit cube with the paper's uniform grids, built from
+    the workload helpers; no data (row counting only)."""
+    lo, hi = np.zeros(3), np.ones(3)
+    nsub = np.array(nsub)
+    nbox = int(np.prod(nsub))
+    groups = []
+    for e in range(nbox):
+        blo, bhi = W.box_bounds(e, lo, hi, nsub)
+        groups.append(W.PointGroup(W.KIND_PDE, W.box_grid(blo, bhi, [q] * 3), e))
+    for a in range(3):
+        for e in range(nbox):
+            mi = W.box_multi(e, nsub)
+            if mi[a] != 0:
+                continue
+            mj = list(mi)
+            mj[a] = 1
+            blo, bhi = W.box_bounds(e, lo, hi, nsub)
+            pts = W.face_grid(blo, bhi, a, bhi[a], q)
+            for c in range(ncomp):
+                groups.append(W.PointGroup(W.KIND_CONTINUITY, pts, e, W.box_index(mj, nsub),
+                                           comp=c, cont_order=cont_orders[c]))
+    for a in range(3):
+        for side in (0, 1):
+            for e in range(nbox):
+                if W.box_multi(e, nsub)[a] != side:
+                    continue
+                blo, bhi = W.box_bounds(e, lo, hi, nsub)
+                pts = W.face_grid(blo, bhi, a, float(side), q)
+                for c in dirichlet_comps:
+                    groups.append(W.PointGroup(W.KIND_DIRICHLET, pts, e, comp=c))
+    return W.Problem("count", 3, ncomp, lo, hi, nsub, J, np.zeros((nbox, ncomp, 1, 3)),
+                     np.zeros((nbox, ncomp, 1)), groups, [], [], lambda x: x, np.zeros((0, 3)),
+                     np.zeros(0, np.int32))
+
+
+@pytest.mark.parametrize("entry", _golden_rows(), ids=lambda r: "-".join(r[:3]))
+def test_row_counts_match_paper(entry):
+    label, q, J = entry[0], int(entry[1]), int(entry[2])
+    if label == "overflow":
+        prob = _cube_problem(q, J, 1, [2], [0])
+        _, m = O.row_table(prob)
+        assert m * prob.n == int(entry[4])
+    else:
+        prob = _cube_problem(q, J, 3, [2, 2, 1], [0, 1])
+        _, m = O.row_table(prob)
+        assert (m, prob.n) == (int(entry[4]), int(entry[5]))
+
+
+def test_config_row_counts():
+    p1 = W.config1()
+    assert (O.row_table(p1)[1], p1.n) == (1920, 800)
+    p2 = W.config2(test_per_dim=2)
+    assert (O.row_table(p2)[1], p2.n) == (204800, 38400)
+
+
+# ---------------------------------------------------------------------------
+# Philox and Gaussian entries
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ctr,key", [((0, 0, 0, 0), (0, 0)), ((5, 7, 0, 0), (11, 13)),
+                                     ((2**64 - 2, 3, 9, 1), (2**63 + 5, 77))])
+def test_philox_matches_numpy_library(ctr, key):
+    # numpy's Philox (4x64, 10 rounds) bumps its counter before each block
+    bg = np.random.Philox(counter=np.array(ctr, np.uint64), key=np.array(key, np.uint64))
+    ref = bg.random_raw(4)
+    c1 = list(ctr)
+    c1[0] = (c1[0] + 1) % 2**64
+    mine = P.philox4x64(np.array([c1], np.uint64), key)[0]
+    assert [int(v) for v in mine] == [int(v) for v in ref]
+
+
+def test_gaussian_moments_and_scaling():
+    S = P.sketch_matrix(3, 1, 400, 500)
+    g = S.ravel() * math.sqrt(400)
+    n = g.size
+    assert abs(g.mean()) < 5 / math.sqrt(n)
+    assert abs(g.var() - 1) < 6 * math.sqrt(2 / n)
+    kurt = np.mean(g ** 4)
+    assert abs(kurt - 3) < 0.05
+    # E[S^T S] = I: column norms concentrate at 1
+    cn = np.linalg.norm(S, axis=0)
+    assert abs(cn.mean() - 1) < 0.01
+    # entries are random-access by (i, r)
+    i = np.array([0, 7, 399, 123])
+    r = np.array([0, 3, 499, 250])
+    assert np.allclose(P.gaussian_entries(3, 1, i, r) / math.sqrt(400), S[i, r], rtol=0, atol=0)
+    # different Jacobian index -> independent matrix
+    S2 = P.sketch_matrix(3, 2, 400, 500)
+    assert abs(np.corrcoef(S.ravel(), S2.ravel())[0, 1]) < 0.01
+
+
+# ---------------------------------------------------------------------------
+# manufactured data vs finite differences of u*
+# ---------------------------------------------------------------------------
+
+def _fd_jet(exact, x, h=1e-4):
+    d = x.shape[1]
+    val = exact(x)
+    grad = np.zeros(val.shape + (d,))
+    sec = np.zeros(val.shape + (d,))
+    for a in range(d):
+        xp, xm = x.copy(), x.copy()
+        xp[:, a] += h
+        xm[:, a] -= h
+        fp, fm = exact(xp), exact(xm)
+        grad[..., a] = (fp - fm) / (2 * h)
+        sec[..., a] = (fp - 2 * val + fm) / (h * h)
+    return val, grad, sec
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_pde_data_matches_finite_differences(cfg):
+    small = [dict(nsub=(2, 2), J=4, q=5), dict(nsub=(2, 2, 2), J=4, q=4),
+             dict(nsub=(2, 2, 2), J=4, q=4), dict(nsub=(2, 2, 2), J=4, q=4)][cfg]
+    prob = W.make_config(cfg, **small)
+    g = prob.groups[1]
+    assert g.kind == W.KIND_PDE
+    x = g.x
+    val, grad, sec = _fd_jet(prob.exact, x)
+    for q in range(prob.ncomp):
+        f = np.zeros(x.shape[0])
+        for (eq, c, coeff, deriv) in prob.lin_terms:
+            if eq != q:
+                continue
+            if deriv == W.D_ID:
+                f += coeff * val[:, c]
+            elif W.D_X0 <= deriv <= W.D_X3:
+                f += coeff * grad[:, c, deriv - 1]
+            elif deriv == W.D_LAPLACE:
+                f += coeff * sec[:, c].sum(-1)
+            elif deriv == W.D_LAPLACE_SPACE:
+                f += coeff * sec[:, c, :-1].sum(-1)
+        for (eq, coeff, pw) in prob.poly_terms:
+            if eq == q:
+                f += coeff * np.prod([val[:, c] ** p for c, p in enumerate(pw)], axis=0)
+        scale = max(1.0, np.abs(g.data[:, q]).max())
+        assert np.abs(f - g.data[:, q]).max() < 2e-5 * scale
+
+
+def test_helmholtz_closed_form_rhs_is_cube():
+    # -Lap u* = kappa^2 u* for the product of sines, so f = u*^3 exactly
+    prob = W.config3_nohole(nsub=(2, 2, 2), J=4, q=5)
+    g = prob.groups[3]
+    ustar = prob.exact(g.x)[:, 0]
+    assert np.allclose(g.data[:, 0], ustar ** 3, rtol=1e-12, atol=1e-12)
+
+
+def test_boundary_data_is_exact_solution():
+    prob = W.config2(nsub=(2, 2, 2), J=4, q=4)
+    for g in prob.groups:
+        if g.kind == W.KIND_DIRICHLET:
+            assert np.array_equal(g.data, prob.exact(g.x))
+
+
+# ---------------------------------------------------------------------------
+# features and Jacobian
+# ---------------------------------------------------------------------------
+
+def test_feature_derivatives_by_finite_differences():
+    prob = W.config2(nsub=(2, 2, 2), J=6, q=3)
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, 0.5, size=(7, 3))
+    phi, dphi, d2phi = O.feature_jet(prob, 0, 1, x)
+    h = 1e-5
+    for a in range(3):
+        xp, xm = x.copy(), x.copy()
+        xp[:, a] += h
+        xm[:, a] -= h
+        fp, fm = O.feature_jet(prob, 0, 1, xp)[0], O.feature_jet(prob, 0, 1, xm)[0]
+        assert np.abs((fp - fm) / (2 * h) - dphi[:, :, a]).max() < 1e-8
+        assert np.abs((fp - 2 * phi + fm) / h ** 2 - d2phi[:, :, a]).max() < 1e-4
+    # phi is tanh of an affine map of the box-normalised coordinate
+    mu, sig = O.box_centre_radius(prob, 0)
+    z = ((x - mu) / sig) @ prob.W[0, 1].T + prob.b[0, 1]
+    assert np.allclose(phi, np.tanh(z), rtol=0, atol=1e-15)
+
+
+def _with_neumann(prob):
+    """Add a Neumann group (a slanted normal) so every row kind is exercised."""
+    rng = np.random.default_rng(5)
+    e = 1
+    blo, bhi = W.box_bounds(e, prob.lo, prob.hi, prob.nsub)
+    x = rng.uniform(blo, bhi, size=(5, prob.dim))
+    nrm = rng.normal(size=(5, prob.dim))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    jet = W.jet_of(prob)(x)
+    data = np.einsum("pcd,pd->pc", jet[1], nrm)
+    prob.groups.append(W.PointGroup(W.KIND_NEUMANN, x, e, normal=nrm, comp=-1, data=data))
+    return prob
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 3])
+def test_jacobian_matches_central_differences(cfg):
+    small = [dict(nsub=(2, 2), J=5, q=3), dict(nsub=(2, 1, 2), J=4, q=3), dict(nsub=(1, 2, 2), J=4, q=3)][
+        [0, 1, 3].index(cfg)]
+    prob = _with_neumann(W.make_config(cfg, **small))
+    rng = np.random.default_rng(1)
+    u = rng.normal(size=prob.n)
+    F, J = O.assemble(prob, u)
+    assert J.shape == (O.row_table(prob)[1], prob.n)
+    Jfd = np.zeros_like(J)
+    for j in range(prob.n):
+        h = 1e-6 * max(1.0, abs(u[j]))
+        up, um = u.copy(), u.copy()
+        up[j] += h
+        um[j] -= h
+        Jfd[:, j] = (O.residual(prob, up) - O.residual(prob, um)) / (2 * h)
+    err = np.abs(J - Jfd).max() / np.abs(J).max()
+    assert err < 1e-7
+    # F is the residual evaluated directly
+    assert np.allclose(F, O.residual(prob, u), rtol=0, atol=1e-13 * np.abs(F).max())
+
+
+def test_linear_rows_do_not_depend_on_u():
+    prob = W.config2(nsub=(2, 1, 1), J=4, q=3)
+    rng = np.random.default_rng(2)
+    _, J1 = O.assemble(prob, rng.normal(size=prob.n))
+    _, J2 = O.assemble(prob, rng.normal(size=prob.n))
+    npde = sum(O.group_nrows(prob, g) for g in prob.groups if g.kind == W.KIND_PDE)
+    assert np.array_equal(J1[npde:], J2[npde:])
+    assert not np.allclose(J1[:npde], J2[:npde])
+
+
+def test_assemble_rows_matches_full():
+    prob = W.config2(nsub=(2, 1, 2), J=4, q=3)
+    u = np.random.default_rng(3).normal(size=prob.n)
+    F, J = O.assemble(prob, u)
+    rows = np.array([0, 5, F.size // 2, F.size - 1])
+    Fr, Jr = O.assemble_rows(prob, u, rows)
+    assert np.array_equal(Fr, F[rows]) and np.array_equal(Jr, J[rows])
+
+
+# ---------------------------------------------------------------------------
+# row scaling, QR, conditioning
+# ---------------------------------------------------------------------------
+
+def test_row_scale():
+    J = np.array([[1.0, -4.0, 2.0], [0.0, 0.0, 0.0], [1e-8, 0, 3e-9]])
+    D = O.row_scale(J, 100.0)
+    assert np.allclose(np.abs(D[:, None] * J).max(1), [100, 0, 100])
+    assert D[1] == 1.0
+
+
+def test_qr_r_invariants_and_cholesky_route():
+    rng = np.random.default_rng(4)
+    B = rng.normal(size=(60, 25)) @ np.diag(np.logspace(0, 3, 25))
+    R = O.qr_r(B)
+    assert np.all(np.diag(R) > 0)
+    assert np.allclose(np.tril(R, -1), 0)
+    G = B.T @ B
+    assert np.abs(R.T @ R - G).max() < 1e-12 * np.abs(G).max()
+    # unique factor: equals the Cholesky factor of B^T B for well-conditioned B
+    L = np.linalg.cholesky(G)
+    assert np.allclose(R, L.T, rtol=1e-9, atol=1e-9 * np.abs(R).max())
+
+
+def test_qr_singular_detected():
+    B = np.random.default_rng(0).normal(size=(10, 4))
+    B[:, 2] = 0
+    with pytest.raises(O.SingularPreconditioner):
+        O.qr_r(B)
+
+
+def test_sketch_preconditioning_drops_condition_number():
+    """kappa(D J R^-1) is O(1) and independent of kappa(D J) (the bound quoted
+    in Sec. 4.1).  For a Gaussian S with s = 2n the singular values of S Q lie
+    near the Marchenko-Pastur edges 1 -/+ sqrt(n/s), so those of D J R^-1 lie
+    near 1/(1 + sqrt(1/2)) = 0.586 and 1/(1 - sqrt(1/2)) = 3.41 (kappa ~ 5.8)."""
+    prob = W.config1(nsub=(2, 2), J=100, q=14)
+    u = np.zeros(prob.n)
+    F, J = O.assemble(prob, u)
+    D = O.row_scale(J)
+    DJ = D[:, None] * J
+    s = O.sketch_rows(prob.n, 2.0)
+    R = O.qr_r(O.sketch(DJ, s, 1, 0))
+    sv = np.linalg.svd(DJ, compute_uv=False)
+    assert sv[0] / sv[-1] > 1e8
+    A = DJ @ np.linalg.inv(R)
+    sa = np.linalg.svd(A, compute_uv=False)
+    kap = sa[0] / sa[-1]
+    assert 3.0 < kap < 10.0
+    r = math.sqrt(prob.n / s)
+    assert abs(sa[-1] * (1 + r) - 1) < 0.2
+    assert abs(sa[0] * (1 - r) - 1) < 0.25
+
+
+# ---------------------------------------------------------------------------
+# LSQR and line search
+# ---------------------------------------------------------------------------
+
+def test_lsqr_matches_dense_lstsq():
+    rng = np.random.default_rng(7)
+    A = rng.normal(size=(80, 30)) @ np.diag(np.linspace(1, 5, 30))
+    b = rng.normal(size=80)
+    res = O.lsqr(lambda v: A @ v, lambda w: A.T @ w, b, 30, 1e-12, 500)
+    x = np.linalg.lstsq(A, b, rcond=None)[0]
+    assert res.istop == 2
+    assert np.linalg.norm(res.x - x) < 1e-9 * np.linalg.norm(x)
+    # consistent system stops by rule 1
+    b2 = A @ rng.normal(size=30)
+    res2 = O.lsqr(lambda v: A @ v, lambda w: A.T @ w, b2, 30, 1e-12, 500)
+    assert res2.istop == 1
+    assert np.linalg.norm(A @ res2.x - b2) < 1e-10 * np.linalg.norm(b2)
+
+
+def test_preconditioned_lsqr_step_matches_lstsq_step():
+    prob = W.config1(nsub=(2, 2), J=40, q=10)
+    u = np.random.default_rng(8).normal(size=prob.n) * 0.1
+    F, J = O.assemble(prob, u)
+    D = O.row_scale(J)
+    DJ, DF = D[:, None] * J, D * F
+    R = O.qr_r(O.sketch(DJ, O.sketch_rows(prob.n, 2.0), 1, 0))
+    st = O.Stats()
+    pc = O.Precond(DJ, D, R)
+    du = O.newton_direction(pc, DF, O.Opts(lsqr_tol=1e-10), st)
+    du_ref = np.linalg.lstsq(DJ, -DF, rcond=None)[0]
+    assert np.linalg.norm(DJ @ (du - du_ref)) / np.linalg.norm(DF) < 1e-9
+    assert 20 < st.lsqr_iters[0] < 150
+
+
+def test_golden_section_on_unimodal_functions():
+    a, f, _ = O.golden_section(lambda t: (t - 0.3) ** 2 + 1.0, 1.09, iters=25)
+    assert abs(a - 0.3) < 1e-5 and f < 1.0 + 1e-9
+    # decreasing function: the full step is taken at once
+    a, f, nev = O.golden_section(lambda t: 2.0 - t, 2.0)
+    assert a == 1.0 and nev == 1
+    # increasing function: no decrease, no step
+    a, f, _ = O.golden_section(lambda t: 1.0 + t, 1.0)
+    assert a == 0.0 and f == 1.0
+    # minimum at the right end but below the sufficient-decrease factor
+    a, f, _ = O.golden_section(lambda t: 1.0 - 1e-6 * t, 1.0)
+    assert a > 0.99999
+
+
+# ---------------------------------------------------------------------------
+# Newton solvers
+# ---------------------------------------------------------------------------
+
+def test_linear_problem_converges_in_one_full_step():
+    """With mu = 0 the Newton step solves the linear least-squares problem exactly."""
+    prob = W.config1(nsub=(2, 2), J=40, q=10)
+    # drop the cubic term and give the data of -Lap u* only
+    prob.poly_terms = []
+    for g in prob.groups:
+        if g.kind == W.KIND_PDE:
+            jet = W.jet_config1(g.x)
+            g.data = -jet[2]
+    u, st = O.ipn(prob, opts=O.Opts(max_outer=3))
+    F, J = O.assemble(prob, np.zeros(prob.n))
+    D = O.row_scale(J)
+    ref = np.linalg.lstsq(D[:, None] * J, -D * F, rcond=None)[0]
+    assert st.alphas[0] == 1.0
+    assert np.linalg.norm(D * (J @ (u - ref))) < 1e-8 * np.linalg.norm(D * F)
+
+
+def test_ipn_and_amipn_reach_manufactured_solution_config1():
+    prob = W.config1()
+    u, st = O.ipn(prob)
+    assert st.status == "ok"
+    e_ipn = O.rel_l2(prob, u)
+    assert e_ipn[0] < 1e-6
+    ua, sta = O.amipn(prob, opts=O.Opts(method="amipn", m_max=5))
+    assert sta.status == "ok"
+    assert O.rel_l2(prob, ua)[0] < 1e-6
+    assert sta.jac_evals <= sta.outer_iters + 1
+    assert sta.jac_evals < st.jac_evals
+    # the two solvers agree on the field
+    fi = O.eval_field(prob, u, prob.test_x, prob.test_owner)
+    fa = O.eval_field(prob, ua, prob.test_x, prob.test_owner)
+    assert np.linalg.norm(fi - fa) / np.linalg.norm(fi) < 1e-8
+
+
+def test_exact_and_replica_modes_agree():
+    prob = W.config2(nsub=(2, 1, 1), J=30, q=5)
+    ur, sr = O.ipn(prob, opts=O.Opts(mode="replica"))
+    ue, se = O.ipn(prob, opts=O.Opts(mode="exact"))
+    fr = O.eval_field(prob, ur, prob.test_x, prob.test_owner)
+    fe = O.eval_field(prob, ue, prob.test_x, prob.test_owner)
+    assert np.linalg.norm(fr - fe) / np.linalg.norm(fe) < 1e-7
+
+
+@pytest.mark.parametrize("cfg,kw,tol", [
+    (1, dict(nsub=(1, 1, 1), J=250, q=8), 0.03),      # Gray-Scott pair
+    (2, dict(nsub=(1, 1, 1), J=300, q=9), 0.05),      # Helmholtz kappa = 8
+    (3, dict(nsub=(2, 2, 2), J=120, q=6), 0.15),      # space-time Allen-Cahn
+])
+def test_operator_signs_by_manufactured_solution(cfg, kw, tol):
+    """The exact-Newton iteration approaches u*; a flipped sign or a dropped
+    term in any operator would leave an O(1) error."""
+    prob = W.make_config(cfg, **kw)
+    u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
+    assert st.status == "ok"
+    assert np.all(O.rel_l2(prob, u) < tol)
