@@ -1,0 +1,233 @@
+/*
+ * rfm.h -- C ABI of librfmnewton.so: randomized inexact preconditioned Newton
+ * solvers (IPN and AMIPN) for random-feature-method (RFM) discretisations of
+ * nonlinear PDEs, on one AMD Instinct MI355X (gfx950).
+ *
+ * Paper: "Robust and efficient solvers for nonlinear PDEs based on the random
+ * feature method" (arXiv 2510.04170).
+ *
+ * Conventions for every call:
+ *  - The return value is an rfm_status: 0 success, < 0 error (nothing useful
+ *    was written), > 0 warning (outputs are written and usable).
+ *  - rfm_last_error() gives a thread-local message for the last failing call.
+ *  - Array arguments may be host or device pointers (checked with
+ *    hipPointerGetAttributes); the library copies inputs during the call and
+ *    never keeps a caller pointer.  Outputs go to caller buffers of the stated
+ *    size.  All device work is ordered on the stream given to rfm_create, and
+ *    every call that returns data to a host pointer synchronises that stream.
+ *  - One problem object must not be used from two threads at once.
+ *  - No C++ exception crosses this boundary.
+ */
+#ifndef RFM_H
+#define RFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RFM_OK = 0,
+  RFM_EINVAL = -1,     /* bad argument, shape or call order; nothing done */
+  RFM_ENOMEM = -2,     /* device allocation failed */
+  RFM_EDEVICE = -3,    /* a HIP call failed */
+  RFM_ESINGULAR = -4,  /* R has a zero or non-finite diagonal entry: no preconditioner */
+  RFM_ENUMERIC = -5,   /* non-finite input data or a non-finite residual */
+  RFM_ENOCONV = 1,     /* warning: the outer iteration limit was reached */
+  RFM_ESTALL = 2       /* warning: the line search found no decrease; u is the last iterate */
+} rfm_status;
+
+/* Message of the last failing call on this thread (never NULL). */
+const char* rfm_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Problem description (Alg. 3 inputs: partition, collocation sets, basis,
+ * operators, data, continuity order).
+ * ---------------------------------------------------------------------- */
+
+typedef struct rfm_problem rfm_problem;
+
+/* Point kinds. */
+enum { RFM_PDE = 0, RFM_DIRICHLET = 1, RFM_NEUMANN = 2, RFM_CONTINUITY = 3 };
+
+/* Derivative selectors of a linear operator term. */
+enum {
+  RFM_D_ID = 0,                 /* the value                                   */
+  RFM_D_X0 = 1, RFM_D_X1 = 2,   /* first derivative along axis k is 1 + k      */
+  RFM_D_X2 = 3, RFM_D_X3 = 4,
+  RFM_D_LAPLACE = 8,            /* sum of second derivatives over every axis   */
+  RFM_D_LAPLACE_SPACE = 9       /* same, leaving out the last (time) axis      */
+};
+
+/* One term coeff * D u_comp of equation eq: the linear part lambda*L u (Sec. 2.1). */
+typedef struct { int32_t eq, comp; double coeff; int32_t deriv; } rfm_lin_term;
+
+/* One term coeff * prod_c u_c^pow[c] of equation eq: the nonlinear part mu*N(u)
+ * restricted to polynomials of the field values.  At most 4 components. */
+typedef struct { int32_t eq; double coeff; int32_t pow[4]; } rfm_poly_term;
+
+/* Create an empty problem on HIP device `device`.  dim: 1..4 coordinates
+ * (time, if any, is the last one, Sec. 2.1); ncomp: 1..4 solution components,
+ * with one equation per component.  hip_stream: a hipStream_t, or NULL for the
+ * null stream. */
+rfm_status rfm_create(rfm_problem** out, int32_t dim, int32_t ncomp, int32_t device, void* hip_stream);
+
+/* Free everything the problem owns.  NULL is allowed. */
+void rfm_destroy(rfm_problem* p);
+
+/* Box Omega_c = prod [lo_a, hi_a] split into nsub[a] equal boxes per axis
+ * (Sec. 2.2); box index e = i_0 + nsub_0 (i_1 + nsub_1 i_2 ...). */
+rfm_status rfm_set_partition(rfm_problem* p, const double* lo, const double* hi, const int32_t* nsub);
+
+/* J tanh features per box and component (Sec. 2.2):
+ *   phi_{e,c,j}(x) = tanh(sum_a W[e][c][j][a] (x_a - mu_{e,a}) / sigma_{e,a} + b[e][c][j]),
+ * with mu, sigma the centre and half-width of box e.  W: [nbox][ncomp][J][dim],
+ * b: [nbox][ncomp][J].  Unknowns are ordered [box][component][feature]:
+ * n = nbox * ncomp * J.  J may be at most 512 (the widest Jacobian row is
+ * ncomp*J for PDE rows and 2*J for continuity rows; both must be <= 1024). */
+rfm_status rfm_set_features(rfm_problem* p, int32_t J, const double* W, const double* b);
+
+/* Append one point group.  Every point of the group belongs to box `owner`
+ * (indicator partition of unity, Sec. 5); continuity groups also name the
+ * box `neighbor` across the interface.  Rows are appended in the order
+ * (equation or component, continuity order, point):
+ *  RFM_PDE:        one row per equation (comp = -1) or for equation comp;
+ *                  residual  sum lin + sum poly - data[p][q]  (Alg. 3 step 1);
+ *                  data: [npts][neq_sel]
+ *  RFM_DIRICHLET:  u_c(x) - data[p][k]            (Alg. 3 step 3), data [npts][ncomp_sel]
+ *  RFM_NEUMANN:    normal . grad u_c(x) - data[p][k],               data [npts][ncomp_sel]
+ *  RFM_CONTINUITY: D^s u_c^{owner}(x) - D^s u_c^{neighbor}(x) for s < cont_order,
+ *                  D^0 the value and D^1 the derivative along normal[p]
+ *                  (eqs. con:1-3, Alg. 3 step 2); data must be NULL.
+ * x: [npts][dim]; normal: [npts][dim] for NEUMANN and CONTINUITY, else NULL;
+ * comp: -1 for all components/equations or one index; cont_order: 1 or 2.
+ * npts may be 0 (nothing is added). */
+rfm_status rfm_add_points(rfm_problem* p, int32_t kind, int64_t npts, const double* x, int32_t owner,
+                          int32_t neighbor, const double* normal, int32_t comp, int32_t cont_order,
+                          const double* data);
+
+/* Operator P(u) = sum of linear terms + sum of polynomial terms (Sec. 2.1). */
+rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nlin,
+                            const rfm_poly_term* nl, int32_t nnl);
+
+/* Finish the description: builds the row and tile layout and uploads it.  Called
+ * implicitly by the first compute call; no points may be added afterwards. */
+rfm_status rfm_finalize(rfm_problem* p);
+
+int64_t rfm_num_unknowns(const rfm_problem* p);  /* n, or -1 before features are set */
+int64_t rfm_num_rows(const rfm_problem* p);      /* m (after rfm_finalize), else -1 */
+
+/* ------------------------------------------------------------------------
+ * Solver (Alg. 1 IPN, Alg. 2 AMIPN)
+ * ---------------------------------------------------------------------- */
+
+enum { RFM_IPN = 0, RFM_AMIPN = 1 };
+enum { RFM_PREC_F64 = 0, RFM_PREC_F32 = 1, RFM_PREC_BF16 = 2, RFM_PREC_FP8 = 3 };
+
+typedef struct {
+  int32_t method;          /* RFM_IPN or RFM_AMIPN                                  */
+  double sketch_factor;    /* gamma: sketch rows s = ceil(gamma * n), gamma > 1      */
+  uint64_t sketch_seed;    /* key word 0 of the Philox4x64-10 sketch generator       */
+  double lsqr_tol;         /* eta: LSQR atol = btol                                  */
+  int32_t lsqr_max_iter;
+  double outer_tol;        /* epsilon of the stop test | ||F_{k+1}|| - ||F_k|| |      */
+  int32_t max_outer;       /* K                                                      */
+  int32_t m_max;           /* AMIPN: inner steps per Jacobian                        */
+  double tau_rel;          /* AMIPN: early-stop threshold                            */
+  double row_scale_c;      /* c of the row scale c / max_j |J_ij| (Sec. 5)            */
+  int32_t gs_iters;        /* golden-section iterations after a rejected full step   */
+  int32_t sketch_prec;     /* RFM_PREC_F64 | RFM_PREC_BF16 | RFM_PREC_FP8            */
+  int32_t lsqr_prec;       /* RFM_PREC_F64 | RFM_PREC_F32 (Jacobian in the LSQR matvecs) */
+  int32_t verbose;         /* 1: one line per outer step on stderr                   */
+} rfm_solve_opts;
+
+#define RFM_MAX_STEPS 64
+typedef struct {
+  int32_t outer_iters;               /* IT */
+  int32_t jac_evals;                 /* NJ: Jacobian + preconditioner evaluations */
+  int32_t lsqr_iters_total;
+  int32_t nsteps;                    /* Newton directions computed (<= RFM_MAX_STEPS logged) */
+  int32_t lsqr_iters[RFM_MAX_STEPS];
+  double alphas[RFM_MAX_STEPS];
+  double resnorms[RFM_MAX_STEPS];    /* ||D F|| after each step */
+  double final_resnorm;
+  /* wall time per stage in seconds (HIP events on the problem's stream) */
+  double t_assemble, t_sketch, t_qr, t_lsqr, t_linesearch, t_total;
+  int32_t status_detail;
+} rfm_solve_stats;
+
+/* Paper values: gamma 3, eta 1e-6, epsilon 1e-10, tau 1e-3, m_max 3, c 100 (Sec. 6). */
+void rfm_solve_opts_default(rfm_solve_opts* o);
+
+/* Solve min ||F(u)|| from the initial coefficients u_inout[n]; the result is
+ * written back to u_inout.  stats may be NULL. */
+rfm_status rfm_solve(rfm_problem* p, const rfm_solve_opts* opts, double* u_inout, rfm_solve_stats* stats);
+
+/* Unscaled residual F(u) (F may be NULL) and ||F||_2. */
+rfm_status rfm_residual(rfm_problem* p, const double* u, double* F, double* norm);
+
+/* Field u_n(x) at npts points of given owner boxes: out [npts][ncomp]. */
+rfm_status rfm_eval(rfm_problem* p, const double* u, int64_t npts, const double* x, const int32_t* owner,
+                    double* out);
+
+/* ------------------------------------------------------------------------
+ * Stage calls.  Each runs one step of the per-Newton-step pipeline on the
+ * problem's internal state so that it can be checked on its own.
+ * ---------------------------------------------------------------------- */
+
+/* Residual and Jacobian at u, row-scaled: D = c / max_j |J_ij| (1 for a zero
+ * row), kept as the current Jacobian (Alg. 3 and Sec. 5 scaling). */
+rfm_status rfm_stage_assemble(rfm_problem* p, const double* u, double row_scale_c);
+
+/* Copies of the current scaled residual D F [m], the scale D [m], and rows
+ * [r0, r0 + nrows) of the scaled Jacobian D J as a dense row-major block
+ * [nrows][n]. */
+rfm_status rfm_get_scaled_residual(rfm_problem* p, double* DF);
+rfm_status rfm_get_row_scale(rfm_problem* p, double* D);
+rfm_status rfm_get_jacobian_rows(rfm_problem* p, int64_t r0, int64_t nrows, double* out);
+
+/* y = (D J) x  [m]   and   x = (D J)^T y  [n] with the current Jacobian. */
+rfm_status rfm_jmul(rfm_problem* p, const double* x, double* y);
+rfm_status rfm_jtmul(rfm_problem* p, const double* y, double* x);
+
+/* Sketch B = S (D J) with s = ceil(gamma n) rows; S[i][r] are N(0,1)/sqrt(s) from
+ * Philox4x64-10 with counter (i/4, r, 0, 0) and key (seed, jac_index), Box-Muller
+ * on the pairs (x0,x1), (x2,x3).  prec: RFM_PREC_F64, _BF16 or _FP8 (the product
+ * runs in that precision with FP32 accumulation; B is kept in FP64). */
+rfm_status rfm_stage_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index, int32_t prec);
+
+/* Columns [c0, c0 + ncols) of the current sketch B, column-major [ncols][s]. */
+rfm_status rfm_get_sketch_cols(rfm_problem* p, int64_t c0, int64_t ncols, double* out);
+int64_t rfm_sketch_rows(const rfm_problem* p);
+
+/* Thin QR of the current sketch (Alg. 1 step 2): keeps R [n][n] upper
+ * triangular with a positive diagonal.  RFM_ESINGULAR if a diagonal entry is
+ * zero or not finite. */
+rfm_status rfm_stage_qr(rfm_problem* p);
+
+/* Columns [c0, c0 + ncols) of R, column-major [ncols][n] (zeros below the diagonal). */
+rfm_status rfm_get_r_cols(rfm_problem* p, int64_t c0, int64_t ncols, double* out);
+
+/* x = R^{-1} y and x = R^{-T} y with the current R ([n] vectors). */
+rfm_status rfm_r_solve(rfm_problem* p, const double* y, double* x);
+rfm_status rfm_rt_solve(rfm_problem* p, const double* y, double* x);
+
+/* LSQR on min || (D J) R^{-1} y - rhs || with tolerance tol (Paige-Saunders rules 1
+ * and 2, atol = btol = tol), y0 = 0; returns y [n], the iteration count and the
+ * stop rule (1, 2, or 0 for the iteration limit). */
+rfm_status rfm_stage_lsqr(rfm_problem* p, const double* rhs, double tol, int32_t max_iter, double* y,
+                          int32_t* iters, int32_t* istop);
+
+/* Golden-section line search on phi(a) = ||D F(u + a du)|| with the current row
+ * scale D: the full step when phi(1) <= (1 - 1e-4) phi(0), else gs_iters golden
+ * iterations on [0, 1]; returns the step (0 when nothing decreases phi) and phi. */
+rfm_status rfm_stage_linesearch(rfm_problem* p, const double* u, const double* du, int32_t gs_iters,
+                                double* alpha, double* phi);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFM_H */

@@ -1,0 +1,324 @@
+"""Python binding of librfmnewton.so (C ABI in include/rfm.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  Arrays may be numpy (host) arrays or torch device tensors; torch is
+used only for device memory and stream handles.  The library must have been
+built (``python -m paper_2510_04170_amd.build``); importing ``lib()`` without it
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librfmnewton.so")
+
+RFM_OK, RFM_EINVAL, RFM_ENOMEM, RFM_EDEVICE, RFM_ESINGULAR, RFM_ENUMERIC = 0, -1, -2, -3, -4, -5
+RFM_ENOCONV, RFM_ESTALL = 1, 2
+RFM_PDE, RFM_DIRICHLET, RFM_NEUMANN, RFM_CONTINUITY = 0, 1, 2, 3
+RFM_IPN, RFM_AMIPN = 0, 1
+RFM_PREC_F64, RFM_PREC_F32, RFM_PREC_BF16, RFM_PREC_FP8 = 0, 1, 2, 3
+RFM_MAX_STEPS = 64
+
+
+class rfm_lin_term(C.Structure):
+    _fields_ = [("eq", C.c_int32), ("comp", C.c_int32), ("coeff", C.c_double), ("deriv", C.c_int32)]
+
+
+class rfm_poly_term(C.Structure):
+    _fields_ = [("eq", C.c_int32), ("coeff", C.c_double), ("pow", C.c_int32 * 4)]
+
+
+class rfm_solve_opts(C.Structure):
+    _fields_ = [("method", C.c_int32), ("sketch_factor", C.c_double), ("sketch_seed", C.c_uint64),
+                ("lsqr_tol", C.c_double), ("lsqr_max_iter", C.c_int32), ("outer_tol", C.c_double),
+                ("max_outer", C.c_int32), ("m_max", C.c_int32), ("tau_rel", C.c_double),
+                ("row_scale_c", C.c_double), ("gs_iters", C.c_int32), ("sketch_prec", C.c_int32),
+                ("lsqr_prec", C.c_int32), ("verbose", C.c_int32)]
+
+
+class rfm_solve_stats(C.Structure):
+    _fields_ = [("outer_iters", C.c_int32), ("jac_evals", C.c_int32), ("lsqr_iters_total", C.c_int32),
+                ("nsteps", C.c_int32), ("lsqr_iters", C.c_int32 * RFM_MAX_STEPS),
+                ("alphas", C.c_double * RFM_MAX_STEPS), ("resnorms", C.c_double * RFM_MAX_STEPS),
+                ("final_resnorm", C.c_double), ("t_assemble", C.c_double), ("t_sketch", C.c_double),
+                ("t_qr", C.c_double), ("t_lsqr", C.c_double), ("t_linesearch", C.c_double),
+                ("t_total", C.c_double), ("status_detail", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        k = min(self.nsteps, RFM_MAX_STEPS)
+        return dict(outer_iters=self.outer_iters, jac_evals=self.jac_evals, lsqr_iters_total=self.lsqr_iters_total,
+                    nsteps=self.nsteps, lsqr_iters=list(self.lsqr_iters[:k]), alphas=list(self.alphas[:k]),
+                    resnorms=list(self.resnorms[:k]), final_resnorm=self.final_resnorm,
+                    t_assemble=self.t_assemble, t_sketch=self.t_sketch, t_qr=self.t_qr, t_lsqr=self.t_lsqr,
+                    t_linesearch=self.t_linesearch, t_total=self.t_total, status=self.status_detail)
+
+
+class RfmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rfm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+_P = C.c_void_p
+_D = C.c_void_p  # double* (host or device)
+_SIGS = {
+    "rfm_last_error": (C.c_char_p, []),
+    "rfm_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+    "rfm_destroy": (None, [_P]),
+    "rfm_set_partition": (C.c_int, [_P, _D, _D, _D]),
+    "rfm_set_features": (C.c_int, [_P, C.c_int32, _D, _D]),
+    "rfm_add_points": (C.c_int, [_P, C.c_int32, C.c_int64, _D, C.c_int32, C.c_int32, _D, C.c_int32, C.c_int32, _D]),
+    "rfm_set_operator": (C.c_int, [_P, C.POINTER(rfm_lin_term), C.c_int32, C.POINTER(rfm_poly_term), C.c_int32]),
+    "rfm_finalize": (C.c_int, [_P]),
+    "rfm_num_unknowns": (C.c_int64, [_P]),
+    "rfm_num_rows": (C.c_int64, [_P]),
+    "rfm_solve_opts_default": (None, [C.POINTER(rfm_solve_opts)]),
+    "rfm_solve": (C.c_int, [_P, C.POINTER(rfm_solve_opts), _D, C.POINTER(rfm_solve_stats)]),
+    "rfm_residual": (C.c_int, [_P, _D, _D, C.POINTER(C.c_double)]),
+    "rfm_eval": (C.c_int, [_P, _D, C.c_int64, _D, _D, _D]),
+    "rfm_stage_assemble": (C.c_int, [_P, _D, C.c_double]),
+    "rfm_get_scaled_residual": (C.c_int, [_P, _D]),
+    "rfm_get_row_scale": (C.c_int, [_P, _D]),
+    "rfm_get_jacobian_rows": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
+    "rfm_jmul": (C.c_int, [_P, _D, _D]),
+    "rfm_jtmul": (C.c_int, [_P, _D, _D]),
+    "rfm_stage_sketch": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64, C.c_int32]),
+    "rfm_get_sketch_cols": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
+    "rfm_sketch_rows": (C.c_int64, [_P]),
+    "rfm_stage_qr": (C.c_int, [_P]),
+    "rfm_get_r_cols": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
+    "rfm_r_solve": (C.c_int, [_P, _D, _D]),
+    "rfm_rt_solve": (C.c_int, [_P, _D, _D]),
+    "rfm_stage_lsqr": (C.c_int, [_P, _D, C.c_double, C.c_int32, _D, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "rfm_stage_linesearch": (C.c_int, [_P, _D, _D, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+}
+
+
+def lib():
+    """Load librfmnewton.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2510_04170_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise RfmError(rc, lib().rfm_last_error().decode())
+    return rc
+
+
+def _ptr(a) -> Tuple[int, object]:
+    """Pointer of a host numpy array (made float64/C-contiguous) or a torch tensor."""
+    if a is None:
+        return None, None
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), a
+    return a.ctypes.data, a
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_opts(**kw) -> rfm_solve_opts:
+    o = rfm_solve_opts()
+    lib().rfm_solve_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class RfmProblem:
+    """An rfm_problem handle; the library owns all device memory behind it."""
+
+    def __init__(self, dim: int, ncomp: int, device: int = 0, stream: Optional[int] = None):
+        h = _P()
+        _check(lib().rfm_create(C.byref(h), dim, ncomp, device, stream))
+        self.h = h
+        self.dim, self.ncomp = dim, ncomp
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rfm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- description -------------------------------------------------------------
+    def set_partition(self, lo, hi, nsub):
+        lo, hi = _f64(lo), _f64(hi)
+        ns = np.ascontiguousarray(nsub, dtype=np.int32)
+        _check(lib().rfm_set_partition(self.h, lo.ctypes.data, hi.ctypes.data, ns.ctypes.data))
+
+    def set_features(self, J: int, W, b):
+        W, b = _f64(W), _f64(b)
+        _check(lib().rfm_set_features(self.h, J, W.ctypes.data, b.ctypes.data))
+
+    def add_points(self, kind, x, owner, neighbor=-1, normal=None, comp=-1, cont_order=1, data=None):
+        x = _f64(x)
+        nrm = None if normal is None else _f64(normal)
+        dat = None if data is None else _f64(data)
+        _check(lib().rfm_add_points(self.h, kind, x.shape[0], x.ctypes.data, int(owner), int(neighbor),
+                                    None if nrm is None else nrm.ctypes.data, int(comp), int(cont_order),
+                                    None if dat is None else dat.ctypes.data))
+
+    def set_operator(self, lin_terms, poly_terms):
+        L = (rfm_lin_term * max(1, len(lin_terms)))()
+        for i, (eq, comp, coeff, deriv) in enumerate(lin_terms):
+            L[i] = rfm_lin_term(eq, comp, coeff, deriv)
+        Pt = (rfm_poly_term * max(1, len(poly_terms)))()
+        for i, (eq, coeff, pw) in enumerate(poly_terms):
+            p4 = (C.c_int32 * 4)(*(list(pw) + [0] * (4 - len(pw))))
+            Pt[i] = rfm_poly_term(eq, coeff, p4)
+        _check(lib().rfm_set_operator(self.h, L, len(lin_terms), Pt, len(poly_terms)))
+
+    def finalize(self):
+        _check(lib().rfm_finalize(self.h))
+
+    @property
+    def n(self) -> int:
+        return int(lib().rfm_num_unknowns(self.h))
+
+    @property
+    def m(self) -> int:
+        return int(lib().rfm_num_rows(self.h))
+
+    # -- solver ------------------------------------------------------------------
+    def solve(self, u0=None, opts: Optional[rfm_solve_opts] = None):
+        """Returns (u, stats dict, status).  u0 may be a numpy array or a device tensor
+        (updated in place); None means the zero guess."""
+        o = opts or default_opts()
+        u = np.zeros(self.n) if u0 is None else (u0 if hasattr(u0, "data_ptr") else _f64(u0).copy())
+        st = rfm_solve_stats()
+        rc = _check(lib().rfm_solve(self.h, C.byref(o), _ptr(u)[0], C.byref(st)))
+        return u, st.as_dict(), rc
+
+    def residual(self, u) -> Tuple[np.ndarray, float]:
+        F = np.zeros(self.m)
+        nrm = C.c_double()
+        _check(lib().rfm_residual(self.h, _ptr(_f64(u) if not hasattr(u, "data_ptr") else u)[0], F.ctypes.data,
+                                  C.byref(nrm)))
+        return F, nrm.value
+
+    def eval(self, u, x, owner) -> np.ndarray:
+        x = _f64(x)
+        ow = np.ascontiguousarray(owner, dtype=np.int32)
+        out = np.zeros((x.shape[0], self.ncomp))
+        uu = u if hasattr(u, "data_ptr") else _f64(u)
+        _check(lib().rfm_eval(self.h, _ptr(uu)[0], x.shape[0], x.ctypes.data, ow.ctypes.data, out.ctypes.data))
+        return out
+
+    # -- stages ------------------------------------------------------------------
+    def stage_assemble(self, u, c: float = 100.0):
+        uu = u if hasattr(u, "data_ptr") else _f64(u)
+        _check(lib().rfm_stage_assemble(self.h, _ptr(uu)[0], c))
+
+    def get_scaled_residual(self) -> np.ndarray:
+        out = np.zeros(self.m)
+        _check(lib().rfm_get_scaled_residual(self.h, out.ctypes.data))
+        return out
+
+    def get_row_scale(self) -> np.ndarray:
+        out = np.zeros(self.m)
+        _check(lib().rfm_get_row_scale(self.h, out.ctypes.data))
+        return out
+
+    def get_jacobian_rows(self, r0: int, nrows: int) -> np.ndarray:
+        out = np.zeros((nrows, self.n))
+        _check(lib().rfm_get_jacobian_rows(self.h, r0, nrows, out.ctypes.data))
+        return out
+
+    def jmul(self, x) -> np.ndarray:
+        x = _f64(x)
+        y = np.zeros(self.m)
+        _check(lib().rfm_jmul(self.h, x.ctypes.data, y.ctypes.data))
+        return y
+
+    def jtmul(self, y) -> np.ndarray:
+        y = _f64(y)
+        x = np.zeros(self.n)
+        _check(lib().rfm_jtmul(self.h, y.ctypes.data, x.ctypes.data))
+        return x
+
+    def stage_sketch(self, gamma: float, seed: int, jac_index: int, prec: int = RFM_PREC_F64):
+        _check(lib().rfm_stage_sketch(self.h, gamma, seed, jac_index, prec))
+
+    @property
+    def s(self) -> int:
+        return int(lib().rfm_sketch_rows(self.h))
+
+    def get_sketch_cols(self, c0: int, ncols: int) -> np.ndarray:
+        """Columns [c0, c0+ncols) of B as an array [s, ncols]."""
+        out = np.zeros((ncols, self.s))
+        _check(lib().rfm_get_sketch_cols(self.h, c0, ncols, out.ctypes.data))
+        return out.T
+
+    def stage_qr(self):
+        _check(lib().rfm_stage_qr(self.h))
+
+    def get_r_cols(self, c0: int, ncols: int) -> np.ndarray:
+        out = np.zeros((ncols, self.n))
+        _check(lib().rfm_get_r_cols(self.h, c0, ncols, out.ctypes.data))
+        return out.T
+
+    def r_solve(self, y) -> np.ndarray:
+        y = _f64(y)
+        x = np.zeros(self.n)
+        _check(lib().rfm_r_solve(self.h, y.ctypes.data, x.ctypes.data))
+        return x
+
+    def rt_solve(self, y) -> np.ndarray:
+        y = _f64(y)
+        x = np.zeros(self.n)
+        _check(lib().rfm_rt_solve(self.h, y.ctypes.data, x.ctypes.data))
+        return x
+
+    def stage_lsqr(self, rhs, tol: float, max_iter: int = 500):
+        rhs = _f64(rhs)
+        y = np.zeros(self.n)
+        it, istop = C.c_int32(), C.c_int32()
+        _check(lib().rfm_stage_lsqr(self.h, rhs.ctypes.data, tol, max_iter, y.ctypes.data, C.byref(it),
+                                    C.byref(istop)))
+        return y, it.value, istop.value
+
+    def stage_linesearch(self, u, du, gs_iters: int = 25):
+        u, du = _f64(u), _f64(du)
+        a, ph = C.c_double(), C.c_double()
+        _check(lib().rfm_stage_linesearch(self.h, u.ctypes.data, du.ctypes.data, gs_iters, C.byref(a), C.byref(ph)))
+        return a.value, ph.value
+
+
+def from_description(desc, device: int = 0, stream: Optional[int] = None) -> RfmProblem:
+    """Pass a problem description (attributes dim, ncomp, lo, hi, nsub, J, W, b,
+    groups, lin_terms, poly_terms) to a new library problem, group by group."""
+    p = RfmProblem(desc.dim, desc.ncomp, device, stream)
+    p.set_partition(desc.lo, desc.hi, desc.nsub)
+    p.set_features(desc.J, desc.W, desc.b)
+    for g in desc.groups:
+        p.add_points(g.kind, g.x, g.owner, g.neighbor, g.normal, g.comp, g.cont_order, g.data)
+    p.set_operator(desc.lin_terms, desc.poly_terms)
+    p.finalize()
+    return p

@@ -1,0 +1,694 @@
+// C-ABI entry points of librfmnewton: problem description, layout building and
+// the stage calls.  Every entry point catches rfm::Error and returns its status.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+#include "rfm_internal.h"
+
+namespace rfm {
+
+static thread_local std::string g_last_error;
+
+static rfm_status fail(rfm_status c, const std::string& m) {
+  g_last_error = m;
+  return c;
+}
+
+template <class F>
+static rfm_status guarded(F&& f) {
+  try {
+    f();
+    return RFM_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(RFM_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(RFM_EDEVICE, e.what());
+  }
+}
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+void copy_in(Problem& P, double* dst, const double* src, size_t count) {
+  if (count == 0) return;
+  RFM_HIP(hipMemcpyAsync(dst, src, count * sizeof(double),
+                         is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, P.stream));
+}
+
+void copy_out(Problem& P, double* dst, const double* src, size_t count) {
+  if (count == 0) return;
+  bool dev = is_device_ptr(dst);
+  RFM_HIP(hipMemcpyAsync(dst, src, count * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         P.stream));
+  if (!dev) RFM_HIP(hipStreamSynchronize(P.stream));
+}
+
+// host copy of a caller array that may live on the device
+static std::vector<double> host_doubles(const double* src, size_t count) {
+  std::vector<double> v(count);
+  if (count == 0) return v;
+  if (is_device_ptr(src))
+    RFM_HIP(hipMemcpy(v.data(), src, count * sizeof(double), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(v.data(), src, count * sizeof(double));
+  return v;
+}
+
+Problem::~Problem() {}
+
+static void set_device(Problem& P) { RFM_HIP(hipSetDevice(P.device)); }
+
+static bool all_finite(const std::vector<double>& v) {
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+// box geometry: identical arithmetic to the description (lo + i h, + h)
+static void box_centre_halfwidth(const GeomDesc& g, int e, double* mu, double* sig) {
+  int rem = e;
+  for (int a = 0; a < g.dim; ++a) {
+    int i = rem % g.nsub[a];
+    rem /= g.nsub[a];
+    double h = (g.hi[a] - g.lo[a]) / g.nsub[a];
+    double blo = g.lo[a] + i * h;
+    double bhi = blo + h;
+    mu[a] = 0.5 * (blo + bhi);
+    sig[a] = 0.5 * (bhi - blo);
+  }
+}
+
+static int row_width_of_group(const Problem& P, const GroupH& g) {
+  if (g.kind == RFM_PDE) return P.ncomp * P.J;
+  if (g.kind == RFM_CONTINUITY) return 2 * P.J;
+  return P.J;
+}
+
+// Build rows, tiles and the column-block contribution lists, then upload.
+static void finalize(Problem& P) {
+  if (P.finalized) return;
+  RFM_CHECK(P.have_partition, RFM_EINVAL, "rfm_finalize: partition not set");
+  RFM_CHECK(P.have_features, RFM_EINVAL, "rfm_finalize: features not set");
+  RFM_CHECK(P.have_operator, RFM_EINVAL, "rfm_finalize: operator not set");
+  RFM_CHECK(!P.groups.empty(), RFM_EINVAL, "rfm_finalize: no points");
+  const int K = P.ncomp, J = P.J;
+  for (const auto& g : P.groups)
+    RFM_CHECK(row_width_of_group(P, g) <= kMaxRowWidth, RFM_EINVAL, "row wider than 1024 values");
+
+  // rows
+  std::vector<RowDesc> rows;
+  rows.reserve(P.m);
+  for (auto& g : P.groups) {
+    g.row0 = (int64_t)rows.size();
+    int nsel = g.comp < 0 ? K : 1;
+    int nord = g.kind == RFM_CONTINUITY ? g.cont_order : 1;
+    for (int k = 0; k < nsel; ++k) {
+      int sel = g.comp < 0 ? k : g.comp;
+      for (int s = 0; s < nord; ++s)
+        for (int64_t p = 0; p < g.npts; ++p) {
+          RowDesc r;
+          r.pt = (int32_t)(g.pt0 + p);
+          r.owner = g.owner;
+          r.neighbor = g.neighbor;
+          r.kind = (uint8_t)g.kind;
+          r.sel = (uint8_t)sel;
+          r.order = (uint8_t)s;
+          r.pad = 0;
+          rows.push_back(r);
+        }
+    }
+    g.nrows = (int64_t)rows.size() - g.row0;
+  }
+  P.m = (int64_t)rows.size();
+  RFM_CHECK(P.m > 0 && P.m < (int64_t)INT32_MAX, RFM_EINVAL, "row count out of range");
+  RFM_CHECK((int64_t)P.rowdata.size() == P.m, RFM_EINVAL, "internal: row data size");
+
+  // tiles: runs of rows with the same support, at most kTileRows rows
+  P.tiles_h.clear();
+  int64_t voff = 0, poff = 0;
+  auto add_run = [&](int64_t r0, int64_t nr, int colA, int wA, int colB, int wB) {
+    for (int64_t t0 = 0; t0 < nr; t0 += kTileRows) {
+      TileDesc t;
+      t.row0 = (int32_t)(r0 + t0);
+      t.nrows = (int32_t)std::min<int64_t>(kTileRows, nr - t0);
+      t.colA = colA;
+      t.wA = wA;
+      t.colB = colB;
+      t.wB = wB;
+      t.val_off = voff;
+      t.part_off = poff;
+      voff += (int64_t)t.nrows * (wA + wB);
+      poff += wA + wB;
+      P.tiles_h.push_back(t);
+    }
+  };
+  for (const auto& g : P.groups) {
+    if (g.npts == 0) continue;
+    int nsel = g.comp < 0 ? K : 1;
+    if (g.kind == RFM_PDE) {
+      add_run(g.row0, g.nrows, g.owner * K * J, K * J, 0, 0);
+    } else if (g.kind == RFM_CONTINUITY) {
+      for (int k = 0; k < nsel; ++k) {
+        int c = g.comp < 0 ? k : g.comp;
+        add_run(g.row0 + (int64_t)k * g.cont_order * g.npts, (int64_t)g.cont_order * g.npts,
+                (g.owner * K + c) * J, J, (g.neighbor * K + c) * J, J);
+      }
+    } else {
+      for (int k = 0; k < nsel; ++k) {
+        int c = g.comp < 0 ? k : g.comp;
+        add_run(g.row0 + (int64_t)k * g.npts, g.npts, (g.owner * K + c) * J, J, 0, 0);
+      }
+    }
+  }
+  P.ntiles = (int)P.tiles_h.size();
+  P.nvals = voff;
+  P.npart = poff;
+
+  // column blocks (e, c) of J columns each: contributing (tile, offset) in tile order
+  const int nblk = P.geom.nbox * K;
+  std::vector<std::vector<std::pair<int, int>>> contrib(nblk);
+  for (int t = 0; t < P.ntiles; ++t) {
+    const TileDesc& td = P.tiles_h[t];
+    for (int o = 0; o < td.wA; o += J) contrib[(td.colA + o) / J].push_back({t, o});
+    if (td.wB) contrib[td.colB / J].push_back({t, td.wA});
+  }
+  P.cb_ptr_h.assign(nblk + 1, 0);
+  P.cb_tile_h.clear();
+  P.cb_off_h.clear();
+  for (int bk = 0; bk < nblk; ++bk) {
+    for (auto& pr : contrib[bk]) {
+      P.cb_tile_h.push_back(pr.first);
+      P.cb_off_h.push_back(pr.second);
+    }
+    P.cb_ptr_h[bk + 1] = (int32_t)P.cb_tile_h.size();
+  }
+  std::vector<int32_t> rowtile(P.m);
+  for (int t = 0; t < P.ntiles; ++t)
+    for (int r = 0; r < P.tiles_h[t].nrows; ++r) rowtile[P.tiles_h[t].row0 + r] = t;
+
+  // feature table
+  const int dim = P.dim;
+  const int64_t nf = (int64_t)P.geom.nbox * K * J;
+  std::vector<double> ft((size_t)(2 * dim + 3) * nf);
+  for (int e = 0; e < P.geom.nbox; ++e) {
+    double mu[kMaxDim], sig[kMaxDim];
+    box_centre_halfwidth(P.geom, e, mu, sig);
+    for (int c = 0; c < K; ++c)
+      for (int j = 0; j < J; ++j) {
+        int64_t f = ((int64_t)e * K + c) * J + j;
+        double s2 = 0, s2s = 0;
+        for (int a = 0; a < dim; ++a) {
+          double w = P.W[(size_t)f * dim + a];
+          double ws = w / sig[a];
+          ft[(size_t)a * nf + f] = w;
+          ft[(size_t)(dim + a) * nf + f] = ws;
+          s2 += ws * ws;
+          if (a < dim - 1) s2s += ws * ws;
+        }
+        ft[(size_t)(2 * dim) * nf + f] = P.b[f];
+        ft[(size_t)(2 * dim + 1) * nf + f] = s2;
+        ft[(size_t)(2 * dim + 2) * nf + f] = s2s;
+      }
+  }
+
+  // upload
+  P.d_px.resize(P.px.size());
+  RFM_HIP(hipMemcpy(P.d_px.p, P.px.data(), P.px.size() * sizeof(double), hipMemcpyHostToDevice));
+  P.d_pnormal.resize(P.pnormal.size());
+  RFM_HIP(hipMemcpy(P.d_pnormal.p, P.pnormal.data(), P.pnormal.size() * sizeof(double), hipMemcpyHostToDevice));
+  P.d_rowdata.resize(P.m);
+  RFM_HIP(hipMemcpy(P.d_rowdata.p, P.rowdata.data(), P.m * sizeof(double), hipMemcpyHostToDevice));
+  P.d_feat.resize(ft.size());
+  RFM_HIP(hipMemcpy(P.d_feat.p, ft.data(), ft.size() * sizeof(double), hipMemcpyHostToDevice));
+  for (int a = 0; a < kMaxDim; ++a) {
+    P.feat.W[a] = a < dim ? P.d_feat.p + (size_t)a * nf : nullptr;
+    P.feat.WS[a] = a < dim ? P.d_feat.p + (size_t)(dim + a) * nf : nullptr;
+  }
+  P.feat.b = P.d_feat.p + (size_t)(2 * dim) * nf;
+  P.feat.S2 = P.d_feat.p + (size_t)(2 * dim + 1) * nf;
+  P.feat.S2s = P.d_feat.p + (size_t)(2 * dim + 2) * nf;
+  P.d_rows.resize(P.m);
+  RFM_HIP(hipMemcpy(P.d_rows.p, rows.data(), P.m * sizeof(RowDesc), hipMemcpyHostToDevice));
+  P.d_tiles.resize(P.ntiles);
+  RFM_HIP(hipMemcpy(P.d_tiles.p, P.tiles_h.data(), P.ntiles * sizeof(TileDesc), hipMemcpyHostToDevice));
+  P.d_cb_ptr.resize(P.cb_ptr_h.size());
+  RFM_HIP(hipMemcpy(P.d_cb_ptr.p, P.cb_ptr_h.data(), P.cb_ptr_h.size() * 4, hipMemcpyHostToDevice));
+  P.d_cb_tile.resize(std::max<size_t>(1, P.cb_tile_h.size()));
+  P.d_cb_off.resize(std::max<size_t>(1, P.cb_off_h.size()));
+  if (!P.cb_tile_h.empty()) {
+    RFM_HIP(hipMemcpy(P.d_cb_tile.p, P.cb_tile_h.data(), P.cb_tile_h.size() * 4, hipMemcpyHostToDevice));
+    RFM_HIP(hipMemcpy(P.d_cb_off.p, P.cb_off_h.data(), P.cb_off_h.size() * 4, hipMemcpyHostToDevice));
+  }
+  P.d_rowtile.resize(P.m);
+  RFM_HIP(hipMemcpy(P.d_rowtile.p, rowtile.data(), P.m * 4, hipMemcpyHostToDevice));
+
+  // working storage sized by m and n
+  P.d_J.resize(P.nvals);
+  P.d_DF.resize(P.m);
+  P.d_D.resize(P.m);
+  P.d_part.resize(std::max<int64_t>(1, P.npart));
+  P.d_u.resize(P.n);
+  P.d_du.resize(P.n);
+  P.d_vec.resize(6 * std::max(P.m, P.n));
+  P.d_red.resize(65536);
+  P.d_scal.resize(64);
+  P.d_lsab.resize((size_t)P.m * (2 + 2 * K));
+  P.d_lsqr.resize(1);
+  P.d_sync.resize(1 << 16);
+  RFM_HIP(hipMemset(P.d_sync.p, 0, P.d_sync.n * sizeof(int32_t)));
+  RFM_HIP(hipDeviceSynchronize());
+  P.finalized = true;
+}
+
+static Problem& get(rfm_problem* p) {
+  RFM_CHECK(p != nullptr, RFM_EINVAL, "null problem");
+  Problem& P = *reinterpret_cast<Problem*>(p);
+  set_device(P);
+  return P;
+}
+
+static Problem& ready(rfm_problem* p) {
+  Problem& P = get(p);
+  finalize(P);
+  return P;
+}
+
+}  // namespace rfm
+
+using namespace rfm;
+
+extern "C" {
+
+const char* rfm_last_error(void) { return g_last_error.c_str(); }
+
+rfm_status rfm_create(rfm_problem** out, int32_t dim, int32_t ncomp, int32_t device, void* hip_stream) {
+  return guarded([&] {
+    RFM_CHECK(out != nullptr, RFM_EINVAL, "rfm_create: out is NULL");
+    *out = nullptr;
+    RFM_CHECK(dim >= 1 && dim <= kMaxDim, RFM_EINVAL, "rfm_create: dim must be 1..4");
+    RFM_CHECK(ncomp >= 1 && ncomp <= kMaxComp, RFM_EINVAL, "rfm_create: ncomp must be 1..4");
+    int ndev = 0;
+    RFM_HIP(hipGetDeviceCount(&ndev));
+    RFM_CHECK(device >= 0 && device < ndev, RFM_EINVAL, "rfm_create: no such device");
+    RFM_HIP(hipSetDevice(device));
+    auto* P = new Problem();
+    P->dim = dim;
+    P->ncomp = ncomp;
+    P->device = device;
+    P->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    P->geom.dim = dim;
+    P->geom.ncomp = ncomp;
+    *out = reinterpret_cast<rfm_problem*>(P);
+  });
+}
+
+void rfm_destroy(rfm_problem* p) {
+  if (!p) return;
+  Problem* P = reinterpret_cast<Problem*>(p);
+  (void)hipSetDevice(P->device);
+  (void)hipStreamSynchronize(P->stream);
+  delete P;
+}
+
+rfm_status rfm_set_partition(rfm_problem* p, const double* lo, const double* hi, const int32_t* nsub) {
+  return guarded([&] {
+    Problem& P = get(p);
+    RFM_CHECK(!P.finalized, RFM_EINVAL, "rfm_set_partition: problem already finalized");
+    RFM_CHECK(lo && hi && nsub, RFM_EINVAL, "rfm_set_partition: NULL argument");
+    int64_t nbox = 1;
+    for (int a = 0; a < P.dim; ++a) {
+      RFM_CHECK(std::isfinite(lo[a]) && std::isfinite(hi[a]) && hi[a] > lo[a], RFM_EINVAL,
+                "rfm_set_partition: need finite lo < hi");
+      RFM_CHECK(nsub[a] >= 1, RFM_EINVAL, "rfm_set_partition: nsub must be >= 1");
+      P.geom.lo[a] = lo[a];
+      P.geom.hi[a] = hi[a];
+      P.geom.nsub[a] = nsub[a];
+      nbox *= nsub[a];
+    }
+    RFM_CHECK(nbox < (1 << 24), RFM_EINVAL, "rfm_set_partition: too many boxes");
+    P.geom.nbox = (int)nbox;
+    P.have_partition = true;
+  });
+}
+
+rfm_status rfm_set_features(rfm_problem* p, int32_t J, const double* W, const double* b) {
+  return guarded([&] {
+    Problem& P = get(p);
+    RFM_CHECK(!P.finalized, RFM_EINVAL, "rfm_set_features: problem already finalized");
+    RFM_CHECK(P.have_partition, RFM_EINVAL, "rfm_set_features: set the partition first");
+    RFM_CHECK(J >= 1 && J <= 512, RFM_EINVAL, "rfm_set_features: J must be 1..512");
+    RFM_CHECK((int64_t)P.ncomp * J <= kMaxRowWidth, RFM_EINVAL, "rfm_set_features: ncomp*J exceeds 1024");
+    RFM_CHECK(W && b, RFM_EINVAL, "rfm_set_features: NULL argument");
+    const size_t nf = (size_t)P.geom.nbox * P.ncomp * J;
+    P.W = host_doubles(W, nf * P.dim);
+    P.b = host_doubles(b, nf);
+    RFM_CHECK(all_finite(P.W) && all_finite(P.b), RFM_ENUMERIC, "rfm_set_features: non-finite weights");
+    P.J = J;
+    P.geom.J = J;
+    P.n = (int64_t)nf;
+    P.have_features = true;
+  });
+}
+
+rfm_status rfm_add_points(rfm_problem* p, int32_t kind, int64_t npts, const double* x, int32_t owner,
+                          int32_t neighbor, const double* normal, int32_t comp, int32_t cont_order,
+                          const double* data) {
+  return guarded([&] {
+    Problem& P = get(p);
+    RFM_CHECK(!P.finalized, RFM_EINVAL, "rfm_add_points: problem already finalized");
+    RFM_CHECK(P.have_partition, RFM_EINVAL, "rfm_add_points: set the partition first");
+    RFM_CHECK(kind >= RFM_PDE && kind <= RFM_CONTINUITY, RFM_EINVAL, "rfm_add_points: bad kind");
+    RFM_CHECK(npts >= 0, RFM_EINVAL, "rfm_add_points: npts < 0");
+    RFM_CHECK(owner >= 0 && owner < P.geom.nbox, RFM_EINVAL, "rfm_add_points: owner out of range");
+    RFM_CHECK(comp >= -1 && comp < P.ncomp, RFM_EINVAL, "rfm_add_points: comp out of range");
+    if (kind == RFM_CONTINUITY) {
+      RFM_CHECK(neighbor >= 0 && neighbor < P.geom.nbox && neighbor != owner, RFM_EINVAL,
+                "rfm_add_points: continuity needs a different neighbour box");
+      RFM_CHECK(cont_order == 1 || cont_order == 2, RFM_EINVAL, "rfm_add_points: cont_order must be 1 or 2");
+      RFM_CHECK(data == nullptr, RFM_EINVAL, "rfm_add_points: continuity rows take no data");
+    } else {
+      RFM_CHECK(data != nullptr || npts == 0, RFM_EINVAL, "rfm_add_points: data required");
+    }
+    if (kind == RFM_NEUMANN || kind == RFM_CONTINUITY)
+      RFM_CHECK(normal != nullptr || npts == 0, RFM_EINVAL, "rfm_add_points: normal required");
+    if (npts == 0) return;
+    RFM_CHECK(x != nullptr, RFM_EINVAL, "rfm_add_points: x is NULL");
+    RFM_CHECK(P.npts + npts < (int64_t)INT32_MAX, RFM_EINVAL, "rfm_add_points: too many points");
+    const int dim = P.dim;
+    std::vector<double> xh = host_doubles(x, (size_t)npts * dim);
+    RFM_CHECK(all_finite(xh), RFM_ENUMERIC, "rfm_add_points: non-finite coordinates");
+    std::vector<double> nh((size_t)npts * dim, 0.0);
+    if (normal) {
+      nh = host_doubles(normal, (size_t)npts * dim);
+      RFM_CHECK(all_finite(nh), RFM_ENUMERIC, "rfm_add_points: non-finite normals");
+    }
+    const int nsel = comp < 0 ? P.ncomp : 1;
+    std::vector<double> dh;
+    if (data) {
+      dh = host_doubles(data, (size_t)npts * nsel);
+      RFM_CHECK(all_finite(dh), RFM_ENUMERIC, "rfm_add_points: non-finite data");
+    }
+    GroupH g;
+    g.kind = kind;
+    g.owner = owner;
+    g.neighbor = kind == RFM_CONTINUITY ? neighbor : -1;
+    g.comp = comp;
+    g.cont_order = kind == RFM_CONTINUITY ? cont_order : 1;
+    g.pt0 = P.npts;
+    g.npts = npts;
+    g.row0 = 0;
+    g.nrows = 0;
+    P.px.insert(P.px.end(), xh.begin(), xh.end());
+    P.pnormal.insert(P.pnormal.end(), nh.begin(), nh.end());
+    P.npts += npts;
+    // data per row in row order (selection, order, point)
+    int nord = g.cont_order;
+    for (int k = 0; k < nsel; ++k)
+      for (int s = 0; s < nord; ++s)
+        for (int64_t q = 0; q < npts; ++q) P.rowdata.push_back(data ? dh[(size_t)q * nsel + k] : 0.0);
+    P.groups.push_back(g);
+  });
+}
+
+rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nlin, const rfm_poly_term* nl,
+                            int32_t nnl) {
+  return guarded([&] {
+    Problem& P = get(p);
+    RFM_CHECK(!P.finalized, RFM_EINVAL, "rfm_set_operator: problem already finalized");
+    RFM_CHECK(nlin >= 0 && nlin <= kMaxLin && nnl >= 0 && nnl <= kMaxPoly, RFM_EINVAL,
+              "rfm_set_operator: at most 16 linear and 8 polynomial terms");
+    RFM_CHECK((nlin == 0 || lin) && (nnl == 0 || nl), RFM_EINVAL, "rfm_set_operator: NULL terms");
+    OpDesc op{};
+    op.nlin = nlin;
+    for (int i = 0; i < nlin; ++i) {
+      const auto& t = lin[i];
+      RFM_CHECK(t.eq >= 0 && t.eq < P.ncomp && t.comp >= 0 && t.comp < P.ncomp, RFM_EINVAL,
+                "rfm_set_operator: term index out of range");
+      bool ok = t.deriv == RFM_D_ID || (t.deriv >= RFM_D_X0 && t.deriv < RFM_D_X0 + P.dim) ||
+                t.deriv == RFM_D_LAPLACE || (t.deriv == RFM_D_LAPLACE_SPACE && P.dim >= 2);
+      RFM_CHECK(ok, RFM_EINVAL, "rfm_set_operator: bad derivative selector");
+      RFM_CHECK(std::isfinite(t.coeff), RFM_ENUMERIC, "rfm_set_operator: non-finite coefficient");
+      op.lin_eq[i] = t.eq;
+      op.lin_comp[i] = t.comp;
+      op.lin_deriv[i] = t.deriv;
+      op.lin_coeff[i] = t.coeff;
+    }
+    op.npoly = nnl;
+    for (int i = 0; i < nnl; ++i) {
+      const auto& t = nl[i];
+      RFM_CHECK(t.eq >= 0 && t.eq < P.ncomp, RFM_EINVAL, "rfm_set_operator: term index out of range");
+      RFM_CHECK(std::isfinite(t.coeff), RFM_ENUMERIC, "rfm_set_operator: non-finite coefficient");
+      op.poly_eq[i] = t.eq;
+      op.poly_coeff[i] = t.coeff;
+      for (int c = 0; c < kMaxComp; ++c) {
+        int pw = c < P.ncomp ? t.pow[c] : 0;
+        RFM_CHECK(pw >= 0 && pw <= 8, RFM_EINVAL, "rfm_set_operator: powers must be 0..8");
+        op.poly_pow[i][c] = pw;
+      }
+    }
+    P.op = op;
+    P.have_operator = true;
+  });
+}
+
+rfm_status rfm_finalize(rfm_problem* p) {
+  return guarded([&] { finalize(get(p)); });
+}
+
+int64_t rfm_num_unknowns(const rfm_problem* p) {
+  if (!p) return -1;
+  const Problem& P = *reinterpret_cast<const Problem*>(p);
+  return P.have_features ? P.n : -1;
+}
+
+int64_t rfm_num_rows(const rfm_problem* p) {
+  if (!p) return -1;
+  const Problem& P = *reinterpret_cast<const Problem*>(p);
+  return P.finalized ? P.m : -1;
+}
+
+int64_t rfm_sketch_rows(const rfm_problem* p) {
+  if (!p) return -1;
+  return reinterpret_cast<const Problem*>(p)->s;
+}
+
+// ---------------------------------------------------------------------------
+// stage calls
+// ---------------------------------------------------------------------------
+
+rfm_status rfm_stage_assemble(rfm_problem* p, const double* u, double row_scale_c) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(u != nullptr, RFM_EINVAL, "rfm_stage_assemble: u is NULL");
+    RFM_CHECK(row_scale_c > 0 && std::isfinite(row_scale_c), RFM_EINVAL, "rfm_stage_assemble: c must be > 0");
+    copy_in(P, P.d_u.p, u, P.n);
+    launch_assemble(P, P.d_u.p, row_scale_c);
+    P.have_J = true;
+    P.cur_c = row_scale_c;
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_get_scaled_residual(rfm_problem* p, double* DF) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_J, RFM_EINVAL, "no Jacobian assembled");
+    RFM_CHECK(DF, RFM_EINVAL, "NULL output");
+    copy_out(P, DF, P.d_DF.p, P.m);
+  });
+}
+
+rfm_status rfm_get_row_scale(rfm_problem* p, double* D) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_J, RFM_EINVAL, "no Jacobian assembled");
+    RFM_CHECK(D, RFM_EINVAL, "NULL output");
+    copy_out(P, D, P.d_D.p, P.m);
+  });
+}
+
+rfm_status rfm_get_jacobian_rows(rfm_problem* p, int64_t r0, int64_t nrows, double* out) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_J, RFM_EINVAL, "no Jacobian assembled");
+    RFM_CHECK(out && r0 >= 0 && nrows >= 0 && r0 + nrows <= P.m, RFM_EINVAL, "row range out of bounds");
+    RFM_CHECK((double)nrows * P.n < 4e9, RFM_EINVAL, "too many rows requested at once");
+    if (nrows == 0) return;
+    DBuf<double> tmp;
+    tmp.resize((size_t)nrows * P.n);
+    launch_jacobian_rows(P, r0, nrows, tmp.p);
+    copy_out(P, out, tmp.p, (size_t)nrows * P.n);
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_jmul(rfm_problem* p, const double* x, double* y) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_J, RFM_EINVAL, "no Jacobian assembled");
+    RFM_CHECK(x && y, RFM_EINVAL, "NULL argument");
+    double* dx = P.d_vec.p;
+    double* dy = P.d_vec.p + std::max(P.m, P.n);
+    copy_in(P, dx, x, P.n);
+    launch_jmul(P, P.d_J.p, dx, dy, nullptr, nullptr, nullptr);
+    copy_out(P, y, dy, P.m);
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_jtmul(rfm_problem* p, const double* y, double* x) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_J, RFM_EINVAL, "no Jacobian assembled");
+    RFM_CHECK(x && y, RFM_EINVAL, "NULL argument");
+    double* dy = P.d_vec.p;
+    double* dx = P.d_vec.p + std::max(P.m, P.n);
+    copy_in(P, dy, y, P.m);
+    launch_jtmul(P, P.d_J.p, dy, dx, nullptr);
+    copy_out(P, x, dx, P.n);
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_stage_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index, int32_t prec) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_J, RFM_EINVAL, "no Jacobian assembled");
+    RFM_CHECK(gamma > 1.0 && std::isfinite(gamma), RFM_EINVAL, "gamma must be > 1");
+    RFM_CHECK(prec == RFM_PREC_F64 || prec == RFM_PREC_BF16 || prec == RFM_PREC_FP8, RFM_EINVAL,
+              "sketch precision must be F64, BF16 or FP8");
+    int64_t s = (int64_t)std::ceil(gamma * (double)P.n);
+    RFM_CHECK(s >= P.n && s < (int64_t)INT32_MAX, RFM_EINVAL, "sketch size out of range");
+    P.s = s;
+    launch_sketch(P, seed, jac_index, prec);
+    P.have_B = true;
+    P.have_R = false;
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_get_sketch_cols(rfm_problem* p, int64_t c0, int64_t ncols, double* out) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_B, RFM_EINVAL, "no sketch (or it was factorised)");
+    RFM_CHECK(out && c0 >= 0 && ncols >= 0 && c0 + ncols <= P.n, RFM_EINVAL, "column range out of bounds");
+    copy_out(P, out, P.d_B.p + (size_t)c0 * P.s, (size_t)ncols * P.s);
+  });
+}
+
+rfm_status rfm_stage_qr(rfm_problem* p) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_B, RFM_EINVAL, "no sketch to factorise");
+    P.have_B = false;
+    qr_factor(P);
+    P.have_R = true;
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_get_r_cols(rfm_problem* p, int64_t c0, int64_t ncols, double* out) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_R, RFM_EINVAL, "no R factor");
+    RFM_CHECK(out && c0 >= 0 && ncols >= 0 && c0 + ncols <= P.n, RFM_EINVAL, "column range out of bounds");
+    if (ncols == 0) return;
+    DBuf<double> tmp;
+    tmp.resize((size_t)ncols * P.n);
+    launch_get_r_cols(P, c0, ncols, tmp.p);
+    copy_out(P, out, tmp.p, (size_t)ncols * P.n);
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_r_solve(rfm_problem* p, const double* y, double* x) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_R, RFM_EINVAL, "no R factor");
+    RFM_CHECK(x && y, RFM_EINVAL, "NULL argument");
+    double* dy = P.d_vec.p;
+    double* dx = P.d_vec.p + std::max(P.m, P.n);
+    copy_in(P, dy, y, P.n);
+    launch_trsv(P, dy, dx, false, nullptr, nullptr, 0, 0, nullptr);
+    copy_out(P, x, dx, P.n);
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_rt_solve(rfm_problem* p, const double* y, double* x) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_R, RFM_EINVAL, "no R factor");
+    RFM_CHECK(x && y, RFM_EINVAL, "NULL argument");
+    double* dy = P.d_vec.p;
+    double* dx = P.d_vec.p + std::max(P.m, P.n);
+    copy_in(P, dy, y, P.n);
+    launch_trsv(P, dy, dx, true, nullptr, nullptr, 0, 0, nullptr);
+    copy_out(P, x, dx, P.n);
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_stage_lsqr(rfm_problem* p, const double* rhs, double tol, int32_t max_iter, double* y,
+                          int32_t* iters, int32_t* istop) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_J && P.have_R, RFM_EINVAL, "need a Jacobian and an R factor");
+    RFM_CHECK(rhs && y, RFM_EINVAL, "NULL argument");
+    RFM_CHECK(tol > 0 && max_iter >= 1, RFM_EINVAL, "bad LSQR tolerance or iteration limit");
+    double* drhs = P.d_vec.p + 5 * std::max(P.m, P.n);
+    copy_in(P, drhs, rhs, P.m);
+    DBuf<double> dy;
+    dy.resize(P.n);
+    int it = 0, is = 0;
+    lsqr_run(P, drhs, tol, max_iter, dy.p, &it, &is);
+    copy_out(P, y, dy.p, P.n);
+    RFM_HIP(hipStreamSynchronize(P.stream));
+    if (iters) *iters = it;
+    if (istop) *istop = is;
+  });
+}
+
+static rfm_status guarded_rc(const std::function<rfm_status()>& f) {
+  rfm_status rc = RFM_OK;
+  rfm_status g = guarded([&] { rc = f(); });
+  return g != RFM_OK ? g : rc;
+}
+
+rfm_status rfm_solve(rfm_problem* p, const rfm_solve_opts* opts, double* u_inout, rfm_solve_stats* stats) {
+  return guarded_rc([&] { return api_solve(ready(p), opts, u_inout, stats); });
+}
+
+rfm_status rfm_residual(rfm_problem* p, const double* u, double* F, double* norm) {
+  return guarded_rc([&] {
+    RFM_CHECK(u != nullptr, RFM_EINVAL, "rfm_residual: u is NULL");
+    return api_residual(ready(p), u, F, norm);
+  });
+}
+
+rfm_status rfm_eval(rfm_problem* p, const double* u, int64_t npts, const double* x, const int32_t* owner,
+                    double* out) {
+  return guarded_rc([&] {
+    RFM_CHECK(u != nullptr, RFM_EINVAL, "rfm_eval: u is NULL");
+    return api_eval(ready(p), u, npts, x, owner, out);
+  });
+}
+
+rfm_status rfm_stage_linesearch(rfm_problem* p, const double* u, const double* du, int32_t gs_iters, double* alpha,
+                                double* phi) {
+  return guarded_rc([&] { return api_linesearch(ready(p), u, du, gs_iters, alpha, phi); });
+}
+
+}  // extern "C"

@@ -1,0 +1,591 @@
+// Row kernels: Jacobian/residual assembly with the row scale fused in, the
+// directional products of the line search, phi(alpha), field evaluation and the
+// block-sparse products J x and J^T y.
+//
+// One 64-wide wavefront owns one Jacobian row: lanes walk the row's features
+// (feature j on lane j mod 64), so every value of the row is produced and
+// written by consecutive lanes and the row's reductions (field values, the
+// maximum for the scale, the dot products) are wavefront reductions.
+#include "rfm_internal.h"
+
+namespace rfm {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kRowsPerBlock = 4;  // 256 threads, one row per wavefront
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+__device__ __forceinline__ double ipow(double x, int p) {
+  double r = 1.0;
+  for (int i = 0; i < p; ++i) r *= x;
+  return r;
+}
+
+struct RowsCtx {
+  GeomDesc g;
+  OpDesc op;
+  FeatDev f;
+  const RowDesc* rows;
+  const double* px;
+  const double* pn;
+  const double* rowdata;
+};
+
+// l_e(x) = (x - mu_e) / sigma_e, with the box bounds computed as lo + i h, + h
+__device__ __forceinline__ void norm_coords(const GeomDesc& g, int e, const double* x, double* l) {
+  int rem = e;
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) {
+    if (a < g.dim) {
+      int i = rem % g.nsub[a];
+      rem /= g.nsub[a];
+      double h = (g.hi[a] - g.lo[a]) / g.nsub[a];
+      double blo = g.lo[a] + i * h;
+      double bhi = blo + h;
+      double mu = 0.5 * (blo + bhi);
+      double sig = 0.5 * (bhi - blo);
+      l[a] = (x[a] - mu) / sig;
+    } else {
+      l[a] = 0.0;
+    }
+  }
+}
+
+// t = tanh(k . l + b) of feature f
+__device__ __forceinline__ double feat_t(const RowsCtx& C, int64_t f, const double* l) {
+  double z = 0.0;
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a)
+    if (a < C.g.dim) z += C.f.W[a][f] * l[a];
+  return tanh(z + C.f.b[f]);
+}
+
+// derivative selector applied to feature f with t = tanh(z)
+__device__ __forceinline__ double feat_deriv(const RowsCtx& C, int deriv, int64_t f, double t) {
+  double dt = 1.0 - t * t;
+  if (deriv == RFM_D_ID) return t;
+  if (deriv >= RFM_D_X0 && deriv <= RFM_D_X3) return dt * C.f.WS[deriv - RFM_D_X0][f];
+  if (deriv == RFM_D_LAPLACE) return -2.0 * t * dt * C.f.S2[f];
+  return -2.0 * t * dt * C.f.S2s[f];  // RFM_D_LAPLACE_SPACE
+}
+
+__device__ __forceinline__ double feat_normal(const RowsCtx& C, int64_t f, double t, const double* nrm) {
+  double dt = 1.0 - t * t;
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a)
+    if (a < C.g.dim) s += C.f.WS[a][f] * nrm[a];
+  return dt * s;
+}
+
+// Values of row r (positions c*J + j for PDE rows, j and J + j for continuity
+// rows) in vals[], lane-strided; the unscaled residual (data included) in F.
+// vals index: seg * KPER + k for feature j = lane + 64 k of segment/component seg.
+template <int KPER>
+__device__ void row_values(const RowsCtx& C, int64_t r, const double* __restrict__ u, int lane,
+                           double (&vals)[4 * KPER], double& F) {
+  const RowDesc rd = C.rows[r];
+  const int K = C.g.ncomp, J = C.g.J, dim = C.g.dim;
+  double x[kMaxDim], l[kMaxDim], nrm[kMaxDim];
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) {
+    x[a] = a < dim ? C.px[(int64_t)rd.pt * dim + a] : 0.0;
+    nrm[a] = a < dim ? C.pn[(int64_t)rd.pt * dim + a] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4 * KPER; ++i) vals[i] = 0.0;
+  if (rd.kind == RFM_PDE) {
+    const int q = rd.sel;
+    norm_coords(C.g, rd.owner, x, l);
+    double tv[4 * KPER];
+    double accv[kMaxComp] = {0, 0, 0, 0};
+    double accL = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= K) break;
+      const int64_t fb = ((int64_t)rd.owner * K + c) * J;
+#pragma unroll
+      for (int k = 0; k < KPER; ++k) {
+        const int j = lane + kWave * k;
+        tv[c * KPER + k] = 0.0;
+        if (j < J) {
+          const int64_t f = fb + j;
+          const double t = feat_t(C, f, l);
+          double Lv = 0.0;
+          for (int i = 0; i < C.op.nlin; ++i)
+            if (C.op.lin_eq[i] == q && C.op.lin_comp[i] == c) Lv += C.op.lin_coeff[i] * feat_deriv(C, C.op.lin_deriv[i], f, t);
+          const double uj = u[f];
+          accv[c] += t * uj;
+          accL += Lv * uj;
+          vals[c * KPER + k] = Lv;
+          tv[c * KPER + k] = t;
+        }
+      }
+    }
+    double val[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) val[c] = c < K ? wave_sum(accv[c]) : 0.0;
+    accL = wave_sum(accL);
+    double Fp = 0.0, dp[kMaxComp] = {0, 0, 0, 0};
+    for (int i = 0; i < C.op.npoly; ++i) {
+      if (C.op.poly_eq[i] != q) continue;
+      double prod = C.op.poly_coeff[i];
+      for (int c = 0; c < K; ++c) prod *= ipow(val[c], C.op.poly_pow[i][c]);
+      Fp += prod;
+      for (int c = 0; c < K; ++c) {
+        const int pc = C.op.poly_pow[i][c];
+        if (pc == 0) continue;
+        double d = C.op.poly_coeff[i] * pc * ipow(val[c], pc - 1);
+        for (int c2 = 0; c2 < K; ++c2)
+          if (c2 != c) d *= ipow(val[c2], C.op.poly_pow[i][c2]);
+        dp[c] += d;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c >= K) break;
+#pragma unroll
+      for (int k = 0; k < KPER; ++k) vals[c * KPER + k] += dp[c] * tv[c * KPER + k];
+    }
+    F = accL + Fp - C.rowdata[r];
+  } else if (rd.kind == RFM_CONTINUITY) {
+    const int c = rd.sel;
+    double acc = 0.0;
+#pragma unroll
+    for (int seg = 0; seg < 2; ++seg) {
+      const int e = seg == 0 ? rd.owner : rd.neighbor;
+      norm_coords(C.g, e, x, l);
+      const int64_t fb = ((int64_t)e * K + c) * J;
+#pragma unroll
+      for (int k = 0; k < KPER; ++k) {
+        const int j = lane + kWave * k;
+        if (j < J) {
+          const int64_t f = fb + j;
+          const double t = feat_t(C, f, l);
+          double v = rd.order == 0 ? t : feat_normal(C, f, t, nrm);
+          if (seg) v = -v;
+          vals[seg * KPER + k] = v;
+          acc += v * u[f];
+        }
+      }
+    }
+    F = wave_sum(acc);
+  } else {  // Dirichlet or Neumann
+    const int c = rd.sel;
+    norm_coords(C.g, rd.owner, x, l);
+    const int64_t fb = ((int64_t)rd.owner * K + c) * J;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < KPER; ++k) {
+      const int j = lane + kWave * k;
+      if (j < J) {
+        const int64_t f = fb + j;
+        const double t = feat_t(C, f, l);
+        const double v = rd.kind == RFM_DIRICHLET ? t : feat_normal(C, f, t, nrm);
+        vals[k] = v;
+        acc += v * u[f];
+      }
+    }
+    F = wave_sum(acc) - C.rowdata[r];
+  }
+}
+
+// store position of vals[idx] in the row, or -1
+template <int KPER>
+__device__ __forceinline__ int val_pos(int kind, int J, int idx, int lane) {
+  const int seg = idx / KPER, k = idx % KPER;
+  const int j = lane + kWave * k;
+  if (j >= J) return -1;
+  if (kind == RFM_PDE) return seg * J + j;
+  if (kind == RFM_CONTINUITY) return seg < 2 ? seg * J + j : -1;
+  return seg == 0 ? j : -1;
+}
+
+template <int KPER>
+__global__ void __launch_bounds__(256) k_assemble(RowsCtx C, const TileDesc* __restrict__ tiles,
+                                                  const int32_t* __restrict__ rowtile, int64_t m,
+                                                  const double* __restrict__ u, double cscale,
+                                                  double* __restrict__ Jv, double* __restrict__ DF,
+                                                  double* __restrict__ Dout) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
+  if (r >= m) return;
+  double vals[4 * KPER];
+  double F;
+  row_values<KPER>(C, r, u, lane, vals, F);
+  const int kind = C.rows[r].kind;
+  double mx = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4 * KPER; ++i) mx = fmax(mx, fabs(vals[i]));
+  mx = wave_max(mx);
+  const double D = mx > 0.0 ? cscale / mx : 1.0;
+  const TileDesc td = tiles[rowtile[r]];
+  const int w = td.wA + td.wB;
+  double* row = Jv + td.val_off + (int64_t)(r - td.row0) * w;
+#pragma unroll
+  for (int i = 0; i < 4 * KPER; ++i) {
+    const int pos = val_pos<KPER>(kind, C.g.J, i, lane);
+    if (pos >= 0 && pos < w) row[pos] = D * vals[i];
+  }
+  if (lane == 0) {
+    DF[r] = D * F;
+    Dout[r] = D;
+  }
+}
+
+// Linear part and field values along u and du for the line search:
+//   ab[r] = {a_r, b_r, vu_0..vu_{K-1}, vd_0..vd_{K-1}}
+//   F_r(alpha) = a_r + alpha b_r + sum_poly coeff prod_c (vu_c + alpha vd_c)^p_c
+template <int KPER>
+__global__ void __launch_bounds__(256) k_row_eval(RowsCtx C, int64_t m, const double* __restrict__ u,
+                                                  const double* __restrict__ du, double* __restrict__ ab) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
+  if (r >= m) return;
+  const RowDesc rd = C.rows[r];
+  const int K = C.g.ncomp, J = C.g.J, dim = C.g.dim;
+  const int stride = 2 + 2 * K;
+  double x[kMaxDim], l[kMaxDim], nrm[kMaxDim];
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) {
+    x[a] = a < dim ? C.px[(int64_t)rd.pt * dim + a] : 0.0;
+    nrm[a] = a < dim ? C.pn[(int64_t)rd.pt * dim + a] : 0.0;
+  }
+  double au = 0.0, ad = 0.0;
+  double vu[kMaxComp] = {0, 0, 0, 0}, vd[kMaxComp] = {0, 0, 0, 0};
+  if (rd.kind == RFM_PDE) {
+    const int q = rd.sel;
+    norm_coords(C.g, rd.owner, x, l);
+    for (int c = 0; c < K; ++c) {
+      const int64_t fb = ((int64_t)rd.owner * K + c) * J;
+      for (int j = lane; j < J; j += kWave) {
+        const int64_t f = fb + j;
+        const double t = feat_t(C, f, l);
+        double Lv = 0.0;
+        for (int i = 0; i < C.op.nlin; ++i)
+          if (C.op.lin_eq[i] == q && C.op.lin_comp[i] == c) Lv += C.op.lin_coeff[i] * feat_deriv(C, C.op.lin_deriv[i], f, t);
+        const double a = u[f];
+        const double d = du ? du[f] : 0.0;
+        vu[c] += t * a;
+        vd[c] += t * d;
+        au += Lv * a;
+        ad += Lv * d;
+      }
+    }
+  } else if (rd.kind == RFM_CONTINUITY) {
+    const int c = rd.sel;
+    for (int seg = 0; seg < 2; ++seg) {
+      const int e = seg == 0 ? rd.owner : rd.neighbor;
+      norm_coords(C.g, e, x, l);
+      const int64_t fb = ((int64_t)e * K + c) * J;
+      for (int j = lane; j < J; j += kWave) {
+        const int64_t f = fb + j;
+        const double t = feat_t(C, f, l);
+        double v = rd.order == 0 ? t : feat_normal(C, f, t, nrm);
+        if (seg) v = -v;
+        au += v * u[f];
+        ad += du ? v * du[f] : 0.0;
+      }
+    }
+  } else {
+    const int c = rd.sel;
+    norm_coords(C.g, rd.owner, x, l);
+    const int64_t fb = ((int64_t)rd.owner * K + c) * J;
+    for (int j = lane; j < J; j += kWave) {
+      const int64_t f = fb + j;
+      const double t = feat_t(C, f, l);
+      const double v = rd.kind == RFM_DIRICHLET ? t : feat_normal(C, f, t, nrm);
+      au += v * u[f];
+      ad += du ? v * du[f] : 0.0;
+    }
+  }
+  au = wave_sum(au);
+  ad = wave_sum(ad);
+  for (int c = 0; c < K; ++c) {
+    vu[c] = wave_sum(vu[c]);
+    vd[c] = wave_sum(vd[c]);
+  }
+  if (lane == 0) {
+    double* o = ab + r * stride;
+    o[0] = au - (rd.kind == RFM_CONTINUITY ? 0.0 : C.rowdata[r]);
+    o[1] = ad;
+    for (int c = 0; c < K; ++c) {
+      o[2 + c] = vu[c];
+      o[2 + K + c] = vd[c];
+    }
+  }
+}
+
+constexpr int kRedBlock = 256;
+
+// sum over rows of (D_r F_r(alpha))^2 -> one partial per block; optional F output
+__global__ void __launch_bounds__(kRedBlock) k_phi(RowsCtx C, int64_t m, const double* __restrict__ ab,
+                                                   double alpha, const double* __restrict__ D,
+                                                   double* __restrict__ partial, double* __restrict__ Fout) {
+  __shared__ double sh[kRedBlock];
+  const int K = C.g.ncomp;
+  const int stride = 2 + 2 * K;
+  double acc = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; r < m; r += (int64_t)gridDim.x * kRedBlock) {
+    const double* o = ab + r * stride;
+    double F = o[0] + alpha * o[1];
+    const RowDesc rd = C.rows[r];
+    if (rd.kind == RFM_PDE) {
+      for (int i = 0; i < C.op.npoly; ++i) {
+        if (C.op.poly_eq[i] != rd.sel) continue;
+        double prod = C.op.poly_coeff[i];
+        for (int c = 0; c < K; ++c) prod *= ipow(o[2 + c] + alpha * o[2 + K + c], C.op.poly_pow[i][c]);
+        F += prod;
+      }
+    }
+    if (Fout) Fout[r] = F;
+    const double s = D ? D[r] * F : F;
+    acc += s * s;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kRedBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// fixed-order sum of nparts partials into out[0]
+__global__ void __launch_bounds__(kRedBlock) k_reduce_sum(const double* __restrict__ partial, int nparts,
+                                                          double* __restrict__ out) {
+  __shared__ double sh[kRedBlock];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kRedBlock) acc += partial[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kRedBlock / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// u_n(x) at arbitrary points, one wavefront per point
+__global__ void __launch_bounds__(256) k_eval_points(RowsCtx C, int64_t npts, const double* __restrict__ x,
+                                                     const int32_t* __restrict__ owner,
+                                                     const double* __restrict__ u, double* __restrict__ out) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t p = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
+  if (p >= npts) return;
+  const int K = C.g.ncomp, J = C.g.J, dim = C.g.dim;
+  const int e = owner[p];
+  double xx[kMaxDim], l[kMaxDim];
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) xx[a] = a < dim ? x[p * dim + a] : 0.0;
+  norm_coords(C.g, e, xx, l);
+  for (int c = 0; c < K; ++c) {
+    const int64_t fb = ((int64_t)e * K + c) * J;
+    double acc = 0.0;
+    for (int j = lane; j < J; j += kWave) acc += feat_t(C, fb + j, l) * u[fb + j];
+    acc = wave_sum(acc);
+    if (lane == 0) out[p * K + c] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// block-sparse products on the stored (scaled) Jacobian
+// ---------------------------------------------------------------------------
+
+// y[r] = sum_p J[r,p] x[col(p)] - ucoef * uprev[r];  optional ||y||^2 partial per tile;
+// ucoef = alpha/beta is read from the LSQR state when st != null
+__global__ void __launch_bounds__(256) k_jmul(const TileDesc* __restrict__ tiles, const double* __restrict__ Jv,
+                                              const double* __restrict__ x, double* __restrict__ y,
+                                              const double* __restrict__ uprev, const LsqrState* __restrict__ st,
+                                              double* __restrict__ partial) {
+  if (st && st->done) return;
+  __shared__ double sh[kRowsPerBlock];
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const TileDesc td = tiles[blockIdx.x];
+  const int w = td.wA + td.wB;
+  const double uc = st ? st->alpha * st->inv_beta : 0.0;  // x arrives already scaled by 1/alpha
+  double nrm = 0.0;
+  for (int rr = wv; rr < td.nrows; rr += kRowsPerBlock) {
+    const double* row = Jv + td.val_off + (int64_t)rr * w;
+    double acc = 0.0;
+    for (int p = lane; p < w; p += kWave) {
+      const int col = p < td.wA ? td.colA + p : td.colB + (p - td.wA);
+      acc += row[p] * x[col];
+    }
+    acc = wave_sum(acc);
+    const int64_t r = td.row0 + rr;
+    if (uprev) acc -= uc * uprev[r];
+    if (lane == 0) y[r] = acc;
+    nrm += acc * acc;
+  }
+  if (partial) {
+    if (lane == 0) sh[wv] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  }
+}
+
+// part[tile slot + p] = sum_{rows} J[r,p] y[r] * yscale
+__global__ void __launch_bounds__(256) k_jtmul_tiles(const TileDesc* __restrict__ tiles,
+                                                     const double* __restrict__ Jv, const double* __restrict__ y,
+                                                     const LsqrState* __restrict__ st, double* __restrict__ part) {
+  if (st && st->done) return;
+  __shared__ double ys[kTileRows];
+  const TileDesc td = tiles[blockIdx.x];
+  const int w = td.wA + td.wB;
+  const double ysc = st ? st->inv_beta : 1.0;
+  if (threadIdx.x < td.nrows) ys[threadIdx.x] = y[td.row0 + threadIdx.x] * ysc;
+  __syncthreads();
+  for (int p = threadIdx.x; p < w; p += blockDim.x) {
+    double acc = 0.0;
+    const double* col = Jv + td.val_off + p;
+    for (int rr = 0; rr < td.nrows; ++rr) acc += col[(int64_t)rr * w] * ys[rr];
+    part[td.part_off + p] = acc;
+  }
+}
+
+// x[j] = sum over the tiles touching column block j / J, in tile order
+__global__ void __launch_bounds__(256) k_jtmul_reduce(const TileDesc* __restrict__ tiles,
+                                                      const int32_t* __restrict__ cb_ptr,
+                                                      const int32_t* __restrict__ cb_tile,
+                                                      const int32_t* __restrict__ cb_off, int J, int64_t n,
+                                                      const double* __restrict__ part, const LsqrState* __restrict__ st,
+                                                      double* __restrict__ x) {
+  if (st && st->done) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t blk = j / J;
+  const int jj = (int)(j - blk * J);
+  double acc = 0.0;
+  for (int k = cb_ptr[blk]; k < cb_ptr[blk + 1]; ++k) acc += part[tiles[cb_tile[k]].part_off + cb_off[k] + jj];
+  x[j] = acc;
+}
+
+// dense copy of rows [r0, r0 + nrows) of the stored Jacobian
+__global__ void k_jac_rows(const TileDesc* __restrict__ tiles, const int32_t* __restrict__ rowtile,
+                           const double* __restrict__ Jv, int64_t r0, int64_t nrows, int64_t n,
+                           double* __restrict__ out) {
+  const int64_t rr = blockIdx.x;
+  if (rr >= nrows) return;
+  const int64_t r = r0 + rr;
+  const TileDesc td = tiles[rowtile[r]];
+  const int w = td.wA + td.wB;
+  double* o = out + rr * n;
+  for (int64_t c = threadIdx.x; c < n; c += blockDim.x) o[c] = 0.0;
+  __syncthreads();
+  const double* row = Jv + td.val_off + (int64_t)(r - td.row0) * w;
+  for (int p = threadIdx.x; p < w; p += blockDim.x) {
+    const int col = p < td.wA ? td.colA + p : td.colB + (p - td.wA);
+    o[col] = row[p];
+  }
+}
+
+RowsCtx make_ctx(const Problem& P) {
+  RowsCtx C;
+  C.g = P.geom;
+  C.op = P.op;
+  C.f = P.feat;
+  C.rows = P.d_rows.p;
+  C.px = P.d_px.p;
+  C.pn = P.d_pnormal.p;
+  C.rowdata = P.d_rowdata.p;
+  return C;
+}
+
+int kper_of(const Problem& P) { return (P.J + kWave - 1) / kWave; }
+
+}  // namespace
+
+void launch_assemble(Problem& P, const double* u, double c) {
+  RowsCtx C = make_ctx(P);
+  dim3 grid((unsigned)((P.m + kRowsPerBlock - 1) / kRowsPerBlock));
+  switch (kper_of(P)) {
+#define RFM_CASE(KP)                                                                                    \
+  case KP:                                                                                              \
+    hipLaunchKernelGGL(k_assemble<KP>, grid, dim3(256), 0, P.stream, C, P.d_tiles.p, P.d_rowtile.p, P.m, u, c, \
+                       P.d_J.p, P.d_DF.p, P.d_D.p);                                                     \
+    break;
+    RFM_CASE(1) RFM_CASE(2) RFM_CASE(3) RFM_CASE(4) RFM_CASE(5) RFM_CASE(6) RFM_CASE(7) RFM_CASE(8)
+#undef RFM_CASE
+    default:
+      throw Error(RFM_EINVAL, "features per box above 512");
+  }
+  RFM_HIP(hipGetLastError());
+}
+
+void launch_row_eval(Problem& P, const double* u, const double* du, double* out_ab) {
+  RowsCtx C = make_ctx(P);
+  dim3 grid((unsigned)((P.m + kRowsPerBlock - 1) / kRowsPerBlock));
+  hipLaunchKernelGGL(k_row_eval<1>, grid, dim3(256), 0, P.stream, C, P.m, u, du, out_ab);
+  RFM_HIP(hipGetLastError());
+}
+
+int reduce_blocks_rows(const Problem& P) {
+  int64_t b = (P.m + kRedBlock - 1) / kRedBlock;
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 1024);
+}
+
+void launch_phi(Problem& P, const double* ab, double alpha, const double* D, double* out_sumsq) {
+  RowsCtx C = make_ctx(P);
+  const int nb = reduce_blocks_rows(P);
+  hipLaunchKernelGGL(k_phi, dim3(nb), dim3(kRedBlock), 0, P.stream, C, P.m, ab, alpha, D, P.d_red.p, nullptr);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(kRedBlock), 0, P.stream, P.d_red.p, nb, out_sumsq);
+  RFM_HIP(hipGetLastError());
+}
+
+void launch_residual_from_ab(Problem& P, const double* ab, double* F, double* out_sumsq) {
+  RowsCtx C = make_ctx(P);
+  const int nb = reduce_blocks_rows(P);
+  hipLaunchKernelGGL(k_phi, dim3(nb), dim3(kRedBlock), 0, P.stream, C, P.m, ab, 0.0, (const double*)nullptr,
+                     P.d_red.p, F);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(kRedBlock), 0, P.stream, P.d_red.p, nb, out_sumsq);
+  RFM_HIP(hipGetLastError());
+}
+
+void launch_reduce_sum(Problem& P, const double* partials, int nparts, double* out) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(kRedBlock), 0, P.stream, partials, nparts, out);
+  RFM_HIP(hipGetLastError());
+}
+
+void launch_eval_points(Problem& P, const double* u, int64_t npts, const double* x, const int32_t* owner,
+                        double* out) {
+  if (npts == 0) return;
+  RowsCtx C = make_ctx(P);
+  dim3 grid((unsigned)((npts + kRowsPerBlock - 1) / kRowsPerBlock));
+  hipLaunchKernelGGL(k_eval_points, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
+  RFM_HIP(hipGetLastError());
+}
+
+void launch_jmul(Problem& P, const double* J, const double* x, double* y, const double* u_prev,
+                 const LsqrState* st, double* red_partials) {
+  hipLaunchKernelGGL(k_jmul, dim3(P.ntiles), dim3(256), 0, P.stream, P.d_tiles.p, J, x, y, u_prev, st,
+                     red_partials);
+  RFM_HIP(hipGetLastError());
+}
+
+void launch_jtmul(Problem& P, const double* J, const double* y, double* x, const LsqrState* st) {
+  hipLaunchKernelGGL(k_jtmul_tiles, dim3(P.ntiles), dim3(256), 0, P.stream, P.d_tiles.p, J, y, st, P.d_part.p);
+  hipLaunchKernelGGL(k_jtmul_reduce, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, P.stream, P.d_tiles.p,
+                     P.d_cb_ptr.p, P.d_cb_tile.p, P.d_cb_off.p, P.J, P.n, P.d_part.p, st, x);
+  RFM_HIP(hipGetLastError());
+}
+
+void launch_jacobian_rows(Problem& P, int64_t r0, int64_t nrows, double* out) {
+  hipLaunchKernelGGL(k_jac_rows, dim3((unsigned)nrows), dim3(256), 0, P.stream, P.d_tiles.p, P.d_rowtile.p, P.d_J.p,
+                     r0, nrows, P.n, out);
+  RFM_HIP(hipGetLastError());
+}
+
+}  // namespace rfm

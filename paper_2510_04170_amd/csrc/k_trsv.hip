@@ -1,0 +1,179 @@
+// Triangular solves with the preconditioner R (Alg. 1 steps 3-5): x = R^{-1} y
+// and x = R^{-T} y, R stored as 64 x 64 column-major tiles of its upper triangle.
+//
+// One launch of nb = ceil(n / 64) workgroups.  A workgroup takes a ticket from
+// an atomic counter and solves row block i = nb-1-ticket (R x = y) or
+// i = ticket (R^T x = y).  It streams its off-diagonal tiles as soon as the
+// block of x they multiply is published, then solves the 64 x 64 diagonal
+// block by substitution in LDS and publishes its own block (data, release
+// fence, per-block flag = epoch).  A workgroup only waits for blocks held by
+// workgroups with smaller tickets, which are already running, so the launch
+// always drains; a spin limit turns a lost flag into an error instead of a hang.
+//
+// Optional fusion for LSQR: out = yscale-scaled solve minus coef * sub, and a
+// per-block partial of ||out||^2.
+#include "rfm_internal.h"
+
+namespace rfm {
+
+namespace {
+
+constexpr int kTB = 64;
+constexpr int kSpinLimit = 1 << 26;
+// sync words used here: [8] ticket counter, [9] error flag, [16 ...] block flags
+enum { kTicket = 8, kTrsvErr = 9, kFlags = 16 };
+
+__device__ __forceinline__ const double* tile_ptr(const double* Rt, int bi, int bj) {
+  return Rt + ((size_t)bj * (bj + 1) / 2 + bi) * kTB * kTB;
+}
+
+__device__ __forceinline__ void wait_flag(int32_t* sync, int blk, int32_t epoch) {
+  int spins = 0;
+  while (__hip_atomic_load(&sync[kFlags + blk], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    __builtin_amdgcn_s_sleep(1);
+    if ((++spins & 1023) == 0 && __hip_atomic_load(&sync[kTrsvErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      break;  // a wait already timed out: drain
+    if (spins > kSpinLimit) {
+      __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+}
+
+// mode 0: R x = y   (back substitution over row blocks)
+// mode 1: R^T x = y (forward substitution over column blocks)
+template <int MODE>
+__global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int n, int nbk,
+                                              const double* __restrict__ y, double* __restrict__ z,
+                                              double* __restrict__ out, const double* __restrict__ sub,
+                                              const LsqrState* __restrict__ st, int yscale_sel, int sub_sel,
+                                              double* __restrict__ partial, int32_t* __restrict__ sync,
+                                              int32_t epoch) {
+  if (st && st->done) return;
+  __shared__ int tk_sh;
+  __shared__ double Dt[kTB][kTB + 1];
+  __shared__ double rhs[kTB];
+  __shared__ double red[4][kTB];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  if (tid == 0) {
+    const int t = __hip_atomic_fetch_add(&sync[kTicket], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == nbk - 1) __hip_atomic_store(&sync[kTicket], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tk_sh = t;
+  }
+  __syncthreads();
+  const int ticket = tk_sh;
+  const int i = MODE == 0 ? nbk - 1 - ticket : ticket;
+  double ysc = 1.0, coef = 0.0;
+  if (st) {
+    ysc = yscale_sel == 1 ? st->inv_alpha : 1.0;
+    coef = sub_sel == 1 ? st->beta * st->inv_alpha : 0.0;
+  }
+
+  // off-diagonal contributions
+  double acc = 0.0;            // MODE 0: row lane of the block, columns quarter wv
+  double accT[16];             // MODE 1: columns wv*16 .. +15, rows lane
+#pragma unroll
+  for (int q = 0; q < 16; ++q) accT[q] = 0.0;
+  if (MODE == 0) {
+    for (int j = nbk - 1; j > i; --j) {
+      if (tid == 0) wait_flag(sync, j, epoch);
+      __syncthreads();
+      const double* T = tile_ptr(Rt, i, j);
+      const double* xj = z + (size_t)j * kTB;
+#pragma unroll 4
+      for (int c = wv * 16; c < wv * 16 + 16; ++c) acc += T[c * kTB + lane] * xj[c];
+    }
+  } else {
+    for (int j = 0; j < i; ++j) {
+      if (tid == 0) wait_flag(sync, j, epoch);
+      __syncthreads();
+      const double* T = tile_ptr(Rt, j, i);
+      const double zl = z[(size_t)j * kTB + lane];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) accT[q] += T[(wv * 16 + q) * kTB + lane] * zl;
+    }
+  }
+  // combine: red[wv][row]
+  if (MODE == 0) {
+    red[wv][lane] = acc;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      double v = accT[q];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == q) red[0][wv * 16 + q] = v;
+    }
+  }
+  // diagonal tile to LDS
+  {
+    const double* T = tile_ptr(Rt, i, i);
+    for (int e = tid; e < kTB * kTB; e += 256) Dt[e % kTB][e / kTB] = T[e];
+  }
+  __syncthreads();
+  if (tid < kTB) {
+    const int row = i * kTB + tid;
+    const double yv = row < n ? y[row] * ysc : 0.0;
+    const double s = MODE == 0 ? (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]) : red[0][tid];
+    rhs[tid] = yv - s;
+  }
+  __syncthreads();
+  // substitution inside the diagonal tile, one wavefront
+  if (wv == 0) {
+    double r = rhs[lane];
+    if (MODE == 0) {
+      for (int k = kTB - 1; k >= 0; --k) {
+        const double xk = __shfl(r, k, 64) / Dt[k][k];
+        if (lane == k) r = xk;
+        else if (lane < k) r -= Dt[lane][k] * xk;
+      }
+    } else {
+      for (int k = 0; k < kTB; ++k) {
+        const double xk = __shfl(r, k, 64) / Dt[k][k];
+        if (lane == k) r = xk;
+        else if (lane > k) r -= Dt[k][lane] * xk;
+      }
+    }
+    const int row = i * kTB + lane;
+    z[row] = r;  // padded length: nbk * 64
+    double o = r;
+    if (sub && row < n) o = r - coef * sub[row];
+    if (row < n) out[row] = o;
+    if (partial) {
+      double q = row < n ? o * o : 0.0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
+      if (lane == 0) partial[i] = q;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    __hip_atomic_store(&sync[kFlags + i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+}  // namespace
+
+int trsv_block() { return kTB; }
+
+// x = R^{-1} (y * yscale) or R^{-T} (y * yscale); with st != null the scale and the
+// subtraction coefficient come from the LSQR state.  sub_vec may alias x.
+void launch_trsv(Problem& P, const double* y, double* x, bool transpose, const double* sub_vec,
+                 const LsqrState* st, int yscale_sel, int sub_sel, double* red_partials) {
+  const int nbk = (int)((P.n + kTB - 1) / kTB);
+  RFM_CHECK(kFlags + nbk <= (int)P.d_sync.n, RFM_EINVAL, "triangular solve: too many blocks");
+  double* z = P.d_vec.p + 4 * std::max(P.m, P.n);  // padded solution (nbk * 64 <= n + 63)
+  RFM_CHECK(4 * std::max(P.m, P.n) + (int64_t)nbk * kTB <= (int64_t)P.d_vec.n, RFM_EINVAL, "scratch too small");
+  int32_t epoch = (int32_t)(++P.trsv_epoch & 0x7fffffff);
+  if (epoch == 0) epoch = (int32_t)(++P.trsv_epoch & 0x7fffffff);
+  if (transpose)
+    hipLaunchKernelGGL(k_trsv<1>, dim3(nbk), dim3(256), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, x, sub_vec, st,
+                       yscale_sel, sub_sel, red_partials, P.d_sync.p, epoch);
+  else
+    hipLaunchKernelGGL(k_trsv<0>, dim3(nbk), dim3(256), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, x, sub_vec, st,
+                       yscale_sel, sub_sel, red_partials, P.d_sync.p, epoch);
+  RFM_HIP(hipGetLastError());
+}
+
+}  // namespace rfm

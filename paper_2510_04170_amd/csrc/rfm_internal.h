@@ -1,0 +1,248 @@
+// Internal declarations of librfmnewton: device layouts, the problem object and
+// the host-side launchers of every kernel.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rfm.h"
+
+namespace rfm {
+
+// ---------------------------------------------------------------------------
+// errors: internal code throws rfm::Error, the C-ABI layer turns it into a status
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  rfm_status code;
+  Error(rfm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define RFM_HIP(call)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      throw ::rfm::Error(e_ == hipErrorOutOfMemory ? RFM_ENOMEM : RFM_EDEVICE,                 \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+#define RFM_CHECK(cond, code, msg)                 \
+  do {                                                \
+    if (!(cond)) throw ::rfm::Error((code), (msg));   \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffer (owned by the problem object)
+// ---------------------------------------------------------------------------
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void resize(size_t count) {  // contents are not kept
+    if (count <= n && p) return;
+    release();
+    if (count == 0) return;
+    RFM_HIP(hipMalloc(&p, count * sizeof(T)));
+    n = count;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// limits and layouts shared by host and device
+// ---------------------------------------------------------------------------
+constexpr int kMaxDim = 4;
+constexpr int kMaxComp = 4;
+constexpr int kMaxLin = 16;
+constexpr int kMaxPoly = 8;
+constexpr int kMaxRowWidth = 1024;  // widest Jacobian row (16 values per lane of a wave)
+constexpr int kTileRows = 64;       // rows per Jacobian tile
+
+struct OpDesc {
+  int nlin;
+  int lin_eq[kMaxLin], lin_comp[kMaxLin], lin_deriv[kMaxLin];
+  double lin_coeff[kMaxLin];
+  int npoly;
+  int poly_eq[kMaxPoly];
+  int poly_pow[kMaxPoly][kMaxComp];
+  double poly_coeff[kMaxPoly];
+};
+
+struct GeomDesc {
+  int dim, ncomp, J, nbox;
+  int nsub[kMaxDim];
+  double lo[kMaxDim], hi[kMaxDim];
+};
+
+// one Jacobian row: which point, which box(es), which equation/component, which order
+struct RowDesc {
+  int32_t pt;
+  int32_t owner;
+  int32_t neighbor;
+  uint8_t kind, sel, order, pad;
+};
+
+// consecutive rows with one column support: segment A (and B for continuity rows);
+// values are stored row-major, nrows x (wA + wB), starting at val_off
+struct TileDesc {
+  int32_t row0, nrows;
+  int32_t colA, wA;
+  int32_t colB, wB;
+  int64_t val_off;
+  int64_t part_off;  // start of this tile's slot in the J^T y partial buffer
+};
+
+// feature table, structure of arrays indexed by (e * ncomp + c) * J + j
+struct FeatDev {
+  const double* W[kMaxDim];   // raw weights
+  const double* WS[kMaxDim];  // weight / box half-width
+  const double* b;
+  const double* S2;           // sum_a WS_a^2
+  const double* S2s;          // same over the space axes only
+};
+
+// device scalars of one LSQR run (Paige-Saunders recurrences kept on the GPU)
+struct LsqrState {
+  double alpha, beta;         // current normalisation of v and u
+  double rhobar, phibar;
+  double rho, phi, theta;     // step coefficients of the latest iteration
+  double bnorm, anorm2, xnorm2;
+  double rnorm, arnorm;
+  double tol;
+  int32_t itn, maxit;
+  int32_t istop;              // 0 running / iteration limit, 1 rule 1, 2 rule 2, 3 b = 0
+  int32_t done;               // 1 once a stop rule fired
+  double inv_alpha, inv_beta; // 1/alpha and 1/beta (0 when the norm is 0)
+  double cx, cw;              // x += cx w;  w = v - cw w
+};
+
+// ---------------------------------------------------------------------------
+// the problem object
+// ---------------------------------------------------------------------------
+struct GroupH {
+  int kind, owner, neighbor, comp, cont_order;
+  int64_t pt0, npts;   // into the point arrays
+  int64_t row0, nrows;
+};
+
+struct Problem {
+  int dim = 0, ncomp = 0, device = 0;
+  hipStream_t stream = nullptr;
+  bool have_partition = false, have_features = false, have_operator = false, finalized = false;
+  GeomDesc geom{};
+  OpDesc op{};
+  std::vector<double> W, b;           // host copies as given
+  std::vector<double> px, pnormal;    // points [npts][dim], normals [npts][dim]
+  std::vector<double> rowdata;        // data per row (0 for continuity rows)
+  std::vector<GroupH> groups;
+  int64_t npts = 0, m = 0, n = 0;
+  int J = 0;
+
+  // layout
+  std::vector<TileDesc> tiles_h;
+  int64_t nvals = 0, npart = 0;
+  int ntiles = 0;
+  std::vector<int32_t> cb_ptr_h, cb_tile_h, cb_off_h;  // column block -> contributing tiles
+
+  // device: geometry, features, rows, tiles
+  DBuf<double> d_px, d_pnormal, d_rowdata;
+  DBuf<double> d_feat;  // packed SoA feature table
+  FeatDev feat{};
+  DBuf<RowDesc> d_rows;
+  DBuf<TileDesc> d_tiles;
+  DBuf<int32_t> d_cb_ptr, d_cb_tile, d_cb_off;
+  DBuf<int32_t> d_rowtile;  // tile index of each row
+
+  // device: current Jacobian (scaled), residual, scale
+  DBuf<double> d_J, d_DF, d_D, d_part;
+  bool have_J = false;
+  double cur_c = 100.0;
+
+  // device: sketch and preconditioner
+  int64_t s = 0;
+  DBuf<double> d_B;       // s x n column-major (becomes Q's reflectors and R)
+  DBuf<double> d_tau;     // Householder scalars
+  DBuf<double> d_R;       // R in tiled upper storage for the triangular solves
+  DBuf<double> d_ws;      // QR workspace
+  DBuf<int32_t> d_sync;   // grid-barrier / ticket / flag words
+  int64_t ws_elems = 0;
+  bool have_B = false, have_R = false;
+  uint32_t trsv_epoch = 0;
+  uint32_t barrier_epoch = 0;
+
+  // device: work vectors
+  DBuf<double> d_u, d_du, d_vec;  // coefficient vectors and scratch
+  DBuf<double> d_red;             // reduction partials
+  DBuf<double> d_scal;            // reduction results
+  DBuf<double> d_lsab;            // line search: a_r, b_r, vu[K], vd[K] per row
+  DBuf<LsqrState> d_lsqr;
+  DBuf<double> d_ws_lsqr;         // LSQR vectors and partials
+  DBuf<double> d_F0, d_F1;        // residual vectors of the drivers
+
+  ~Problem();
+};
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+
+// k_rows.hip
+void launch_assemble(Problem& P, const double* u, double c);
+void launch_row_eval(Problem& P, const double* u, const double* du, double* out_ab);
+void launch_phi(Problem& P, const double* ab, double alpha, const double* D, double* out_sumsq);
+void launch_eval_points(Problem& P, const double* u, int64_t npts, const double* x, const int32_t* owner,
+                        double* out);
+void launch_jmul(Problem& P, const double* J, const double* x, double* y, const double* u_prev,
+                 const LsqrState* st, double* red_partials);
+void launch_jtmul(Problem& P, const double* J, const double* y, double* x, const LsqrState* st);
+void launch_jacobian_rows(Problem& P, int64_t r0, int64_t nrows, double* out);
+void launch_reduce_sum(Problem& P, const double* partials, int nparts, double* out);
+void launch_residual_from_ab(Problem& P, const double* ab, double* F, double* out_sumsq);
+int reduce_blocks_rows(const Problem& P);
+
+// k_sketch.hip
+void launch_sketch(Problem& P, uint64_t seed, uint64_t jac_index, int prec);
+
+// k_qr.hip
+void qr_factor(Problem& P);   // in place on d_B, leaves R in d_R (tiled), throws RFM_ESINGULAR
+void launch_get_r_cols(Problem& P, int64_t c0, int64_t ncols, double* out);
+
+// k_trsv.hip
+// yscale_sel: 0 -> 1, 1 -> 1/alpha (LSQR state); sub_sel: 0 -> none, 1 -> out = x - (beta/alpha) sub
+void launch_trsv(Problem& P, const double* y, double* x, bool transpose, const double* sub_vec,
+                 const LsqrState* st, int yscale_sel, int sub_sel, double* red_partials);
+int trsv_block();
+
+// k_lsqr.hip
+void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, int* iters, int* istop);
+
+// vector helpers (k_lsqr.hip)
+void launch_axpy(Problem& P, int64_t n, double a, const double* x, double* y);
+void launch_scale_copy(Problem& P, int64_t n, double a, const double* x, double* y);
+void launch_neg_mul(Problem& P, int64_t n, const double* D, const double* F, double* out);  // out = -D*F
+void launch_diff_norm2(Problem& P, int64_t n, const double* a, const double* b, const double* D, double* out);
+
+// C-ABI bodies (solver.cpp)
+rfm_status api_solve(Problem& P, const rfm_solve_opts* opts, double* u_inout, rfm_solve_stats* stats);
+rfm_status api_residual(Problem& P, const double* u, double* F, double* norm);
+rfm_status api_eval(Problem& P, const double* u, int64_t npts, const double* x, const int32_t* owner, double* out);
+rfm_status api_linesearch(Problem& P, const double* u, const double* du, int gs_iters, double* alpha, double* phi);
+
+// utilities
+bool is_device_ptr(const void* p);
+void copy_in(Problem& P, double* dst, const double* src, size_t count);    // src host or device
+void copy_out(Problem& P, double* dst, const double* src, size_t count);   // dst host or device
+
+}  // namespace rfm

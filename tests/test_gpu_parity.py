@@ -1,0 +1,290 @@
+"""HIP path vs the CPU oracle, stage by stage and end to end, through the C ABI.
+
+Tolerances (FP64 everywhere):
+  * assembly (F, J, D), J x, J^T y, field values: relative L2 <= 1e-13 -- both
+    sides evaluate the same closed forms; only the summation order differs;
+  * sketch B = S D J: relative L2 <= 1e-12 (identical Philox streams, Gaussians
+    within a few ulp of each other);
+  * R: compared through R^T R = B^T B (<= 1e-12 relative), not entrywise, since
+    R of an ill-conditioned B is only determined to about kappa(B) * eps;
+  * LSQR / triangular solves: backward errors and the residual of the Newton
+    step (the quantity the method needs), <= 1e-9;
+  * full solves: field relative L2 against the oracle's solve <= 1e-8 and
+    against the manufactured solution <= 1e-6.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import rfm_workloads as W
+from oracle import rfm as O
+from oracle import philox as PH
+
+pytestmark = pytest.mark.gpu
+
+R = None
+
+
+def setup_module(module):
+    global R
+    import paper_2510_04170_amd as Rm
+    Rm.lib()
+    R = Rm
+
+
+def _with_neumann(prob, box=1, npts=7, seed=5):
+    rng = np.random.default_rng(seed)
+    blo, bhi = W.box_bounds(box, prob.lo, prob.hi, prob.nsub)
+    x = rng.uniform(blo, bhi, size=(npts, prob.dim))
+    nrm = rng.normal(size=(npts, prob.dim))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    jet = W.jet_of(prob)(x)
+    data = np.einsum("pcd,pd->pc", jet[1], nrm)
+    prob.groups.append(W.PointGroup(W.KIND_NEUMANN, x, box, normal=nrm, comp=-1, data=data))
+    return prob
+
+
+CASES = {
+    # full 2-D workload: m = 1920, n = 800
+    "poisson2d_full": lambda: W.config1(),
+    # Gray-Scott pair, 2 x 2 x 2 boxes, J = 40 (ragged against 64-wide tiles)
+    "grayscott_small": lambda: W.config2(nsub=(2, 2, 2), J=40, q=4, test_per_dim=3),
+    # Helmholtz, J = 37 (odd), q = 5
+    "helmholtz_small": lambda: W.config3_nohole(nsub=(2, 2, 1), J=37, q=5, test_per_dim=3),
+    # space-time Allen-Cahn, J = 70 (> 64: two feature slots per lane), with Neumann rows
+    "allencahn_small": lambda: _with_neumann(W.config4_nohole(nsub=(2, 1, 2), J=70, q=4, test_per_dim=3)),
+}
+
+
+def _relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _announce(msg):
+    sys.stdout.write(f"\n[gpu-test] {msg}\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    _announce(f"case {request.param}")
+    prob = CASES[request.param]()
+    lp = R.from_description(prob)
+    assert (lp.m, lp.n) == (O.row_table(prob)[1], prob.n)
+    rng = np.random.default_rng(11)
+    u = 0.1 * rng.normal(size=prob.n)
+    F, J = O.assemble(prob, u)
+    D = O.row_scale(J)
+    yield dict(name=request.param, prob=prob, lp=lp, u=u, F=F, J=J, D=D, DJ=D[:, None] * J)
+    lp.close()
+
+
+def test_assembly_and_row_scale(case):
+    lp, D, DJ, F = case["lp"], case["D"], case["DJ"], case["F"]
+    lp.stage_assemble(case["u"], 100.0)
+    Dg = lp.get_row_scale()
+    assert _relerr(Dg, D) < 1e-13
+    assert np.max(np.abs(Dg / D - 1)) < 1e-12
+    assert _relerr(lp.get_scaled_residual(), D * F) < 1e-13
+    Jg = lp.get_jacobian_rows(0, lp.m)
+    assert _relerr(Jg, DJ) < 1e-13
+    # the scaled rows peak at c = 100 exactly where the row is non-zero
+    assert np.allclose(np.abs(Jg).max(1), 100.0, rtol=1e-14)
+
+
+def test_block_sparse_products(case):
+    lp, DJ = case["lp"], case["DJ"]
+    lp.stage_assemble(case["u"], 100.0)
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=lp.n)
+    y = rng.normal(size=lp.m)
+    assert _relerr(lp.jmul(x), DJ @ x) < 1e-13
+    assert _relerr(lp.jtmul(y), DJ.T @ y) < 1e-13
+
+
+def test_residual_and_field_eval(case):
+    lp, prob, u = case["lp"], case["prob"], case["u"]
+    F, nrm = lp.residual(u)
+    assert _relerr(F, case["F"]) < 1e-13
+    assert abs(nrm - np.linalg.norm(case["F"])) < 1e-12 * np.linalg.norm(case["F"])
+    val = lp.eval(u, prob.test_x, prob.test_owner)
+    assert _relerr(val, O.eval_field(prob, u, prob.test_x, prob.test_owner)) < 1e-13
+
+
+def test_sketch_matches_oracle(case):
+    lp, DJ = case["lp"], case["DJ"]
+    lp.stage_assemble(case["u"], 100.0)
+    lp.stage_sketch(2.0, 1, 3, R.RFM_PREC_F64)
+    s = lp.s
+    assert s == O.sketch_rows(lp.n, 2.0)
+    Bg = lp.get_sketch_cols(0, lp.n)
+    Bo = O.sketch(DJ, s, 1, 3)
+    assert _relerr(Bg, Bo) < 1e-12
+
+
+def test_qr_invariants_and_conditioning(case):
+    lp, DJ = case["lp"], case["DJ"]
+    lp.stage_assemble(case["u"], 100.0)
+    lp.stage_sketch(2.0, 1, 0, R.RFM_PREC_F64)
+    B = lp.get_sketch_cols(0, lp.n)
+    lp.stage_qr()
+    Rg = lp.get_r_cols(0, lp.n)
+    assert np.array_equal(np.tril(Rg, -1), np.zeros_like(Rg))
+    assert np.all(np.diag(Rg) > 0)
+    G = B.T @ B
+    assert np.abs(Rg.T @ Rg - G).max() < 1e-12 * np.abs(G).max()
+    # same factor as LAPACK up to the conditioning of B
+    Ro = O.qr_r(B)
+    kB = np.linalg.cond(B)
+    assert _relerr(Rg, Ro) < max(1e-12, 1e-15 * kB)
+    # the preconditioned Jacobian is well conditioned (Sec. 4.1 bound)
+    sv = np.linalg.svd(DJ @ np.linalg.inv(Rg), compute_uv=False)
+    assert sv[0] / sv[-1] < 12.0
+
+
+def test_triangular_solves(case):
+    lp = case["lp"]
+    lp.stage_assemble(case["u"], 100.0)
+    lp.stage_sketch(2.0, 1, 0, R.RFM_PREC_F64)
+    lp.stage_qr()
+    Rg = lp.get_r_cols(0, lp.n)
+    y = np.random.default_rng(5).normal(size=lp.n)
+    x = lp.r_solve(y)
+    xt = lp.rt_solve(y)
+    nR = np.abs(Rg).sum(1).max()
+    # componentwise-style backward errors
+    assert np.linalg.norm(Rg @ x - y) <= 1e-13 * nR * np.linalg.norm(x) + 1e-13 * np.linalg.norm(y)
+    assert np.linalg.norm(Rg.T @ xt - y) <= 1e-13 * nR * np.linalg.norm(xt) + 1e-13 * np.linalg.norm(y)
+    xo = O.r_solve(Rg, y)
+    assert _relerr(x, xo) < max(1e-12, 1e-15 * np.linalg.cond(Rg))
+
+
+def test_lsqr_step_matches_oracle(case):
+    lp, DJ = case["lp"], case["DJ"]
+    lp.stage_assemble(case["u"], 100.0)
+    DF = lp.get_scaled_residual()
+    lp.stage_sketch(2.0, 1, 0, R.RFM_PREC_F64)
+    lp.stage_qr()
+    Rg = lp.get_r_cols(0, lp.n)
+    y, it, istop = lp.stage_lsqr(-DF, 1e-10, 500)
+    ro = O.lsqr(lambda v: DJ @ O.r_solve(Rg, v), lambda w: O.rt_solve(Rg, DJ.T @ w), -DF, lp.n, 1e-10, 500)
+    assert istop in (1, 2)
+    assert abs(it - ro.iters) <= 3
+    # Both sides apply R^{-1} by backward-stable triangular solves, which agree
+    # only to about eps * kappa(R) in the directions where R is small; the
+    # meaningful comparison is the quality of the Newton step as a
+    # least-squares solution, against the dense step, next to the oracle's own.
+    du_g = lp.r_solve(y)
+    du_o = O.r_solve(Rg, ro.x)
+    du_ls = np.linalg.lstsq(DJ, -DF, rcond=None)[0]
+    nF = np.linalg.norm(DF)
+    err_g = np.linalg.norm(DJ @ (du_g - du_ls)) / nF
+    err_o = np.linalg.norm(DJ @ (du_o - du_ls)) / nF
+    print(f"step error vs lstsq: gpu {err_g:.3e} oracle {err_o:.3e} kappa(R) {np.linalg.cond(Rg):.3e}")
+    assert err_g <= max(10 * err_o, 1e-9)
+    # the linearised residual left by the step is as small as the oracle's
+    rg = np.linalg.norm(DF + DJ @ du_g)
+    ro_ = np.linalg.norm(DF + DJ @ du_o)
+    assert rg <= 10 * ro_ + 1e-9 * nF
+
+
+def test_linesearch_matches_oracle(case):
+    lp, prob, u = case["lp"], case["prob"], case["u"]
+    lp.stage_assemble(u, 100.0)
+    D = lp.get_row_scale()
+    rng = np.random.default_rng(9)
+    du = 0.5 * rng.normal(size=lp.n)
+    a_g, phi_g = lp.stage_linesearch(u, du, 25)
+    phi0 = np.linalg.norm(D * O.residual(prob, u))
+    a_o, phi_o, _ = O.golden_section(lambda a: np.linalg.norm(D * O.residual(prob, u + a * du)), phi0, 25)
+    assert abs(a_g - a_o) < 1e-6
+    assert abs(phi_g - phi_o) < 1e-10 * phi0
+
+
+# ---------------------------------------------------------------------------
+# end to end
+# ---------------------------------------------------------------------------
+
+def _solve_both(prob, method, **kw):
+    lp = R.from_description(prob)
+    o = R.default_opts(sketch_factor=2.0, lsqr_tol=1e-10, method=method, **kw)
+    ug, stg, rc = lp.solve(None, o)
+    oo = O.Opts(method="amipn" if method == R.RFM_AMIPN else "ipn", gamma=2.0, lsqr_tol=1e-10,
+                m_max=kw.get("m_max", 3))
+    uo, sto = O.solve(prob, None, oo)
+    return lp, ug, stg, rc, uo, sto
+
+
+@pytest.mark.parametrize("method", ["ipn", "amipn"])
+def test_full_solve_poisson2d(method):
+    _announce(f"full solve poisson2d {method}")
+    prob = W.config1()
+    m = R.RFM_IPN if method == "ipn" else R.RFM_AMIPN
+    lp, ug, stg, rc, uo, sto = _solve_both(prob, m, m_max=5)
+    assert rc == R.RFM_OK, stg
+    fg = O.eval_field(prob, ug, prob.test_x, prob.test_owner)
+    fo = O.eval_field(prob, uo, prob.test_x, prob.test_owner)
+    ex = prob.exact(prob.test_x)
+    assert _relerr(fg, ex) < 1e-6
+    assert _relerr(fg, fo) < 1e-8
+    # field evaluation through the library agrees
+    # converged coefficients are large and cancel: allow a few more ulps than for random u
+    assert _relerr(lp.eval(ug, prob.test_x, prob.test_owner), fg) < 1e-11
+    assert stg["jac_evals"] <= stg["outer_iters"] + 1
+    lp.close()
+
+
+def test_full_solve_grayscott_small():
+    _announce("full solve grayscott small")
+    prob = W.config2(nsub=(2, 2, 2), J=60, q=5, test_per_dim=4)
+    lp, ug, stg, rc, uo, sto = _solve_both(prob, R.RFM_IPN)
+    assert rc == R.RFM_OK, stg
+    fg = O.eval_field(prob, ug, prob.test_x, prob.test_owner)
+    fo = O.eval_field(prob, uo, prob.test_x, prob.test_owner)
+    assert _relerr(fg, fo) < 1e-8
+    assert abs(stg["final_resnorm"] - sto.resnorms[-1]) < 1e-8 * max(1.0, sto.resnorms[0])
+    lp.close()
+
+
+# ---------------------------------------------------------------------------
+# degenerate inputs and error statuses
+# ---------------------------------------------------------------------------
+
+def test_zero_feature_column_is_singular():
+    prob = W.config1(nsub=(2, 2), J=20, q=6)
+    prob.W[0, 0, 3, :] = 0.0
+    prob.b[0, 0, 3] = 0.0          # tanh(0) = 0: an all-zero column of J
+    lp = R.from_description(prob)
+    lp.stage_assemble(np.zeros(prob.n), 100.0)
+    lp.stage_sketch(2.0, 1, 0, R.RFM_PREC_F64)
+    with pytest.raises(R.RfmError) as ei:
+        lp.stage_qr()
+    assert ei.value.status == R.RFM_ESINGULAR
+    lp.close()
+
+
+def test_bad_arguments_rejected():
+    prob = W.config1(nsub=(2, 2), J=8, q=4)
+    lp = R.from_description(prob)
+    with pytest.raises(R.RfmError) as ei:
+        lp.add_points(R.RFM_PDE, np.zeros((2, 2)), 0, data=np.zeros((2, 1)))   # after finalize
+    assert ei.value.status == R.RFM_EINVAL
+    with pytest.raises(R.RfmError):
+        lp.get_jacobian_rows(0, 1)                                               # nothing assembled
+    with pytest.raises(R.RfmError):
+        lp.eval(np.zeros(prob.n), np.zeros((1, 2)), np.array([7]))              # owner out of range
+    lp.close()
+    p2 = R.RfmProblem(2, 1)
+    p2.set_partition([0, 0], [1, 1], [1, 1])
+    p2.set_features(4, np.zeros((1, 1, 4, 2)), np.zeros((1, 1, 4)))
+    with pytest.raises(R.RfmError) as ei:
+        p2.add_points(R.RFM_DIRICHLET, np.zeros((1, 2)), 0, data=np.array([[np.nan]]))
+    assert ei.value.status == R.RFM_ENUMERIC
+    with pytest.raises(R.RfmError) as ei:
+        p2.add_points(R.RFM_CONTINUITY, np.zeros((1, 2)), 0, neighbor=0, normal=np.ones((1, 2)))
+    assert ei.value.status == R.RFM_EINVAL
+    p2.add_points(R.RFM_PDE, np.zeros((0, 2)), 0, data=np.zeros((0, 1)))          # empty group is fine
+    p2.close()
