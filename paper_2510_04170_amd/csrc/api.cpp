@@ -622,6 +622,7 @@ rfm_status rfm_r_solve(rfm_problem* p, const double* y, double* x) {
     double* dx = P.d_vec.p + std::max(P.m, P.n);
     copy_in(P, dy, y, P.n);
     launch_trsv(P, dy, dx, false, nullptr, nullptr, 0, 0, nullptr);
+    check_trsv_error(P);
     copy_out(P, x, dx, P.n);
     RFM_HIP(hipStreamSynchronize(P.stream));
   });
@@ -636,6 +637,7 @@ rfm_status rfm_rt_solve(rfm_problem* p, const double* y, double* x) {
     double* dx = P.d_vec.p + std::max(P.m, P.n);
     copy_in(P, dy, y, P.n);
     launch_trsv(P, dy, dx, true, nullptr, nullptr, 0, 0, nullptr);
+    check_trsv_error(P);
     copy_out(P, x, dx, P.n);
     RFM_HIP(hipStreamSynchronize(P.stream));
   });

@@ -294,9 +294,7 @@ void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, i
   LsqrState S;
   RFM_HIP(hipMemcpyAsync(&S, st, sizeof(S), hipMemcpyDeviceToHost, P.stream));
   RFM_HIP(hipStreamSynchronize(P.stream));
-  int32_t err[2];
-  RFM_HIP(hipMemcpy(err, P.d_sync.p + 8, sizeof(err), hipMemcpyDeviceToHost));
-  RFM_CHECK(err[1] == 0, RFM_EDEVICE, "triangular solve: dependency wait timed out");
+  check_trsv_error(P);
   *iters = S.itn;
   *istop = S.istop;
 }

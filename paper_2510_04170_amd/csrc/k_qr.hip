@@ -37,15 +37,28 @@ constexpr int kSpinLimit = 1 << 26;
 // sync words (d_sync): [0] grid barrier counter, [1] error flag, [2] singular flag
 enum { kSyncBarrier = 0, kSyncError = 1, kSyncSingular = 2 };
 
+// Cross-workgroup exchange without cache maintenance: partial sums and the
+// diagonal row are written and read with device-scope relaxed atomics (sc1,
+// coherent across the XCDs' L2s); every wave waits for its stores to be
+// acknowledged before the workgroup arrives at the barrier.
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void grid_barrier(int32_t* sync, int nblocks, int& phase) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
   ++phase;
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(&sync[kSyncBarrier], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&sync[kSyncBarrier], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int target = phase * nblocks;
     int spins = 0;
-    while (__hip_atomic_load(&sync[kSyncBarrier], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&sync[kSyncBarrier], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
       if ((++spins & 1023) == 0 &&
           __hip_atomic_load(&sync[kSyncError], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
@@ -113,22 +126,32 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t l
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int pr = r0 + rg + 4 * i;
-      if (pr == j && pr < rend && c >= j && c < nb) DRb[c] = a[i];  // only the owning chunk publishes
+      if (pr == j && pr < rend && c >= j && c < nb) st_dev(&DRb[c], a[i]);  // only the owning chunk publishes
     }
     __syncthreads();
-    if (rg == 0 && c >= j && c < nb) Pb[(size_t)g * kPanel + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    if (rg == 0 && c >= j && c < nb) st_dev(&Pb[(size_t)g * kPanel + c], (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]));
     grid_barrier(sync, G, phase);
     // reduce the partials of every workgroup in a fixed order
     double tot = 0.0;
     if (c >= j && c < nb) {
-      for (int gg = rg; gg < G; gg += 4) tot += __builtin_nontemporal_load(&Pb[(size_t)gg * kPanel + c]);
+      // keep 16 device-coherent loads in flight, then add them in a fixed order
+      for (int g0 = rg; g0 < G; g0 += 64) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int gg = g0 + 4 * u;
+          v[u] = gg < G ? ld_dev(&Pb[(size_t)gg * kPanel + c]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) tot += v[u];
+      }
     }
     red[rg][c] = tot;
     __syncthreads();
     double gc = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
     if (threadIdx.x == 0) {
       const double sigma = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
-      const double alpha = __builtin_nontemporal_load(&DRb[j]);
+      const double alpha = ld_dev(&DRb[j]);
       double beta, t, sc;
       if (sigma == 0.0) {
         beta = alpha;
@@ -147,7 +170,7 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t l
     __syncthreads();
     const double beta = scal_sh[0], t = scal_sh[1], sc = scal_sh[2];
     if (c > j && c < nb) {
-      const double ajc = __builtin_nontemporal_load(&DRb[c]);
+      const double ajc = ld_dev(&DRb[c]);
       const double wc = ajc + gc * sc;
       const double tw = t * wc;
 #pragma unroll
@@ -230,32 +253,38 @@ __global__ void __launch_bounds__(256) k_gemm_tn(const double* __restrict__ V, i
 
 // T of the compact-WY form from G = V^T V (summed over splits) and tau:
 // T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j]   (columnwise, forward)
-__global__ void __launch_bounds__(64) k_build_t(const double* __restrict__ part, int nsplit, int nb,
-                                                const double* __restrict__ tau, double* __restrict__ T) {
+__global__ void __launch_bounds__(256) k_build_t(const double* __restrict__ part, int nsplit, int nb,
+                                                 const double* __restrict__ tau, double* __restrict__ T) {
   __shared__ double Ts[kPanel][kPanel + 1];
-  __shared__ double Gj[kPanel];
-  const int i = threadIdx.x;
-  for (int r = 0; r < kPanel; ++r) Ts[r][i] = 0.0;
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    // column j of G: G[i][j] = sum_split part[split][j][i]
-    double gij = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) gij += part[((size_t)sp * nb + j) * kPanel + i];
-    Gj[i] = gij;
-    __syncthreads();
-    const double tj = tau[j];
-    double v = 0.0;
-    if (i < j) {
-      for (int k = i; k < j; ++k) v += Ts[i][k] * Gj[k];
-      v = -tj * v;
-    } else if (i == j) {
-      v = tj;
-    }
-    __syncthreads();
-    if (i <= j) Ts[i][j] = v;
-    __syncthreads();
+  __shared__ double Gs[kPanel][kPanel + 1];  // Gs[j][i] = G[i][j]
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kPanel * kPanel; e += 256) {
+    const int j = e / kPanel, i = e % kPanel;
+    double g = 0.0;
+    if (j < nb)
+      for (int sp = 0; sp < nsplit; ++sp) g += part[((size_t)sp * nb + j) * kPanel + i];
+    Gs[j][i] = g;
+    Ts[i][j] = 0.0;
   }
-  for (int r = 0; r < kPanel; ++r) T[r * kPanel + i] = Ts[r][i];
+  __syncthreads();
+  if (tid < kPanel) {
+    const int i = tid;
+    for (int j = 0; j < nb; ++j) {
+      const double tj = tau[j];
+      double v = 0.0;
+      if (i < j) {
+        for (int k = i; k < j; ++k) v += Ts[i][k] * Gs[j][k];
+        v = -tj * v;
+      } else if (i == j) {
+        v = tj;
+      }
+      // every lane reads column j < current only; the write goes to column j
+      if (i <= j) Ts[i][j] = v;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kPanel * kPanel; e += 256) T[e] = Ts[e / kPanel][e % kPanel];
 }
 
 // W2[col][p] = -sum_{q <= p} T[q][p] W[col][q], W = sum over splits
@@ -324,6 +353,218 @@ __global__ void __launch_bounds__(256) k_gemm_nn(double* __restrict__ C, int64_t
       if (r < M) C[(int64_t)col * ldc + r] = acc[ct][t];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// 128 x 128 tiles for the trailing update of 128-column outer panels.
+// Four wavefronts in a 2 x 2 arrangement each own a 64 x 64 block (4 x 4 MFMA
+// tiles, 64 accumulator doubles per lane); operands are staged through LDS 16
+// values of k at a time, with the next chunk's global loads issued before the
+// current chunk's MFMAs.
+// ---------------------------------------------------------------------------
+constexpr int kBig = 128;
+constexpr int kKC = 16;
+
+// C[M x N] += A[M x K] B, A column-major (lda), B[k][n] = Bt[n * ldb + k]; K a multiple of 16
+__global__ void __launch_bounds__(256) k_gemm_nn128(double* __restrict__ C, int64_t ldc,
+                                                    const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ Bt, int64_t ldb, int M, int N, int K) {
+  __shared__ double As[kKC][kBig + 1];
+  __shared__ double Bs[kKC][kBig + 1];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int wr = wv / 2, wc = wv % 2;
+  const int r0 = blockIdx.x * kBig, n0 = blockIdx.y * kBig;
+  v4d acc[4][4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int col = n0 + wc * 64 + ct * 16 + lane % 16;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = r0 + wr * 64 + rt * 16 + (lane / 16) + 4 * t;
+        acc[rt][ct][t] = (r < M && col < N) ? C[(int64_t)col * ldc + r] : 0.0;
+      }
+  }
+  // loader roles: A: m = tid % 128, k = tid / 128 + 2 i;  B: k = tid % 16, n = tid / 16 + 16 i
+  const int am = tid % kBig, ak = tid / kBig;
+  const int bk = tid % kKC, bn = tid / kKC;
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + ak + 2 * i;
+      ra[i] = (r0 + am < M) ? A[(int64_t)k * lda + r0 + am] : 0.0;
+      const int n = n0 + bn + 16 * i;
+      rb[i] = (n < N) ? Bt[(int64_t)n * ldb + k0 + bk] : 0.0;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += kKC) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      As[ak + 2 * i][am] = ra[i];
+      Bs[bk][bn + 16 * i] = rb[i];
+    }
+    __syncthreads();
+    if (k0 + kKC < K) load(k0 + kKC);
+#pragma unroll
+    for (int ks = 0; ks < kKC / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      double a[4], b[4];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) a[rt] = As[kr][wr * 64 + rt * 16 + lane % 16];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) b[ct] = Bs[kr][wc * 64 + ct * 16 + lane % 16];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int col = n0 + wc * 64 + ct * 16 + lane % 16;
+    if (col >= N) continue;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = r0 + wr * 64 + rt * 16 + (lane / 16) + 4 * t;
+        if (r < M) C[(int64_t)col * ldc + r] = acc[rt][ct][t];
+      }
+  }
+}
+
+// part[split][n][p] = sum_{k in split} A[k][p] B[k][n]; A: K x 128 (lda), B: K x N (ldb), both
+// column-major; rows of a split: [split * krange, ...), krange a multiple of 16
+__global__ void __launch_bounds__(256) k_gemm_tn128(const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ B, int64_t ldb, int K, int N,
+                                                    int krange, double* __restrict__ part) {
+  __shared__ double As[kKC][kBig + 1];
+  __shared__ double Bs[kKC][kBig + 1];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int wr = wv / 2, wc = wv % 2;
+  const int n0 = blockIdx.x * kBig;
+  const int split = blockIdx.y;
+  const int kb = split * krange, ke = min(K, kb + krange);
+  v4d acc[4][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = v4d{0, 0, 0, 0};
+  const int lk = tid % kKC, lc = tid / kKC;  // k = lk, column lc + 16 i
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+    const int k = k0 + lk;
+    const bool kv = k < ke;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int c = lc + 16 * i;
+      ra[i] = kv ? A[(int64_t)c * lda + k] : 0.0;
+      rb[i] = (kv && n0 + c < N) ? B[(int64_t)(n0 + c) * ldb + k] : 0.0;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += kKC) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      As[lk][lc + 16 * i] = ra[i];
+      Bs[lk][lc + 16 * i] = rb[i];
+    }
+    __syncthreads();
+    if (k0 + kKC < ke) load(k0 + kKC);
+#pragma unroll
+    for (int ks = 0; ks < kKC / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      double a[4], b[4];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) a[rt] = As[kr][wr * 64 + rt * 16 + lane % 16];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) b[ct] = Bs[kr][wc * 64 + ct * 16 + lane % 16];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* o = part + (size_t)split * N * kBig;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int col = n0 + wc * 64 + ct * 16 + lane % 16;
+    if (col >= N) continue;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) o[(int64_t)col * kBig + wr * 64 + rt * 16 + (lane / 16) + 4 * t] = acc[rt][ct][t];
+  }
+}
+
+// W2[n][p] = -sum_{q <= p} T[q][p] W[n][q], W = sum over splits of part (T: 128 x 128 row-major)
+__global__ void __launch_bounds__(256) k_reduce_w128(const double* __restrict__ part, int nsplit, int N,
+                                                     const double* __restrict__ T, double* __restrict__ W2) {
+  __shared__ double Wsh[2][kBig];
+  const int p = threadIdx.x % kBig, sub = threadIdx.x / kBig;
+  const int n = blockIdx.x * 2 + sub;
+  double w = 0.0;
+  if (n < N)
+    for (int sp = 0; sp < nsplit; ++sp) w += part[((size_t)sp * N + n) * kBig + p];
+  Wsh[sub][p] = w;
+  __syncthreads();
+  if (n < N) {
+    double v = 0.0;
+    for (int qq = 0; qq <= p; ++qq) v += T[qq * kBig + p] * Wsh[sub][qq];
+    W2[(int64_t)n * kBig + p] = -v;
+  }
+}
+
+// T (128 x 128, row-major) of two consecutive 64-column reflector blocks:
+// [[Ta, -Ta Gab Tb], [0, Tb]], Gab = Va^T Vb from split partials part[split][b][a]
+__global__ void __launch_bounds__(256) k_combine_t(const double* __restrict__ Ta, const double* __restrict__ Tb,
+                                                   const double* __restrict__ part, int nsplit, int nbb,
+                                                   double* __restrict__ T) {
+  __shared__ double Xs[kPanel][kPanel + 1];
+  __shared__ double Gs[kPanel][kPanel + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kPanel * kPanel; e += 256) {
+    const int a = e / kPanel, b = e % kPanel;
+    double g = 0.0;
+    if (b < nbb)
+      for (int sp = 0; sp < nsplit; ++sp) g += part[((size_t)sp * nbb + b) * kPanel + a];
+    Gs[a][b] = g;
+  }
+  __syncthreads();
+  // X = Gab Tb
+  for (int e = tid; e < kPanel * kPanel; e += 256) {
+    const int a = e / kPanel, b = e % kPanel;
+    double v = 0.0;
+    if (nbb > 0)
+      for (int k = 0; k <= b; ++k) v += Gs[a][k] * Tb[k * kPanel + b];
+    Xs[a][b] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < kBig * kBig; e += 256) {
+    const int qq = e / kBig, p = e % kBig;
+    double v = 0.0;
+    if (qq < kPanel && p < kPanel) {
+      v = Ta[qq * kPanel + p];
+    } else if (qq >= kPanel && p >= kPanel) {
+      v = Tb[(qq - kPanel) * kPanel + (p - kPanel)];
+    } else if (qq < kPanel && p >= kPanel) {
+      const int b = p - kPanel;
+      for (int k = qq; k < kPanel; ++k) v += Ta[qq * kPanel + k] * Xs[k][b];
+      v = -v;
+    }
+    T[e] = v;
+  }
+}
+
+// zero the top 64 rows of columns 64..127 of V (M x 128, leading dimension ldv)
+__global__ void k_zero_top(double* __restrict__ V, int64_t ldv) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < kPanel * kPanel) V[(int64_t)(kPanel + e / kPanel) * ldv + e % kPanel] = 0.0;
 }
 
 // R (upper n x n of B) into tiled storage: tile (bi, bj), bi <= bj, at
@@ -408,20 +649,32 @@ void launch_panel(Problem& P, double* A, int64_t ld, int M, int nb, double* tau,
 
 }  // namespace
 
+// split-row count for the TN products: enough workgroups to fill the chip,
+// at least 256 rows per split, krange a multiple of 32
+static void tn_split(int M, int ntile, int ncu, int cap, int* nsplit, int* krange) {
+  int ns = std::max(1, std::min(cap, (4 * ncu + ntile - 1) / ntile));
+  ns = std::max(1, std::min(ns, M / 256));
+  int kr = ((M + ns - 1) / ns + 31) / 32 * 32;
+  *krange = kr;
+  *nsplit = (M + kr - 1) / kr;
+}
+
 void qr_factor(Problem& P) {
   const int64_t s = P.s, n = P.n;
   RFM_CHECK(s >= n, RFM_EINVAL, "QR: sketch has fewer rows than columns");
   const int ncu = num_cus(P.device);
-  // workspace: Vb (s x 64), T (64 x 64), P partials (2 x ncu x 64), DR (2 x 64),
-  // TN partials (nsplit x max(N, 64) x 64), W2 (N x 64)
-  const int max_split = 64;
-  const size_t vb = (size_t)s * kPanel;
-  const size_t tn = (size_t)max_split * std::max<int64_t>(n, kPanel) * kPanel;
-  const size_t need = vb + kPanel * kPanel + 2 * (size_t)ncu * kPanel + 2 * kPanel + tn + (size_t)n * kPanel + 256;
+  const int max_split = 32;
+  // workspace
+  const size_t vb = (size_t)s * kBig;
+  const size_t tn = (size_t)max_split * std::max<int64_t>(n, kBig) * kBig;
+  const size_t need = vb + 2 * kPanel * kPanel + kBig * kBig + 2 * (size_t)ncu * kPanel + 2 * kPanel + tn +
+                      (size_t)n * kBig + 256;
   P.d_ws.resize(need);
   double* Vb = P.d_ws.p;
-  double* T = Vb + vb;
-  double* Pp = T + kPanel * kPanel;
+  double* Ta = Vb + vb;
+  double* Tb = Ta + kPanel * kPanel;
+  double* T = Tb + kPanel * kPanel;
+  double* Pp = T + kBig * kBig;
   double* DR = Pp + 2 * (size_t)ncu * kPanel;
   double* part = DR + 2 * kPanel;
   double* W2 = part + tn;
@@ -430,34 +683,60 @@ void qr_factor(Problem& P) {
   RFM_HIP(hipMemcpyAsync(P.d_sync.p, zero3, sizeof(zero3), hipMemcpyHostToDevice, P.stream));
 
   double* B = P.d_B.p;
-  for (int64_t col0 = 0; col0 < n; col0 += kPanel) {
-    const int nb = (int)std::min<int64_t>(kPanel, n - col0);
+  auto gram_t = [&](const double* V, int64_t ldv, int K, int nb, const double* tau, double* Tout) {
+    int nsplit, krange;
+    tn_split(K, 1, ncu / 4, 64, &nsplit, &krange);
+    hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit), dim3(256), 0, P.stream, V, ldv, V, ldv, K, nb, krange, part);
+    hipLaunchKernelGGL(k_build_t, dim3(1), dim3(256), 0, P.stream, part, nsplit, nb, tau, Tout);
+  };
+  for (int64_t col0 = 0; col0 < n; col0 += kBig) {
+    const int nbo = (int)std::min<int64_t>(kBig, n - col0);
+    const int na = std::min(kPanel, nbo), nbb = nbo - na;
     const int M = (int)(s - col0);
-    double* A = B + col0 * s + col0;
-    launch_panel(P, A, s, M, nb, P.d_tau.p + col0, Pp, DR, Vb, M);
-    // Gram V^T V with the same split-row product
-    {
-      int nsplit = std::min(max_split, std::max(1, M / 2048));
-      int krange = ((M + nsplit - 1) / nsplit + 31) / 32 * 32;
-      nsplit = (M + krange - 1) / krange;
-      hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, Vb, (int64_t)M, M, nb,
-                         krange, part);
-      hipLaunchKernelGGL(k_build_t, dim3(1), dim3(64), 0, P.stream, part, nsplit, nb, P.d_tau.p + col0, T);
-    }
-    const int64_t N = n - col0 - nb;
-    if (N > 0) {
-      double* C = B + (col0 + nb) * s + col0;
-      const int ntile = (int)((N + 63) / 64);
-      int nsplit = std::max(1, std::min(max_split, (4 * ncu + ntile - 1) / ntile));
-      nsplit = std::min<int>(nsplit, std::max(1, M / 256));
-      int krange = ((M + nsplit - 1) / nsplit + 31) / 32 * 32;
-      nsplit = (M + krange - 1) / krange;
-      hipLaunchKernelGGL(k_gemm_tn, dim3(ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, C, s, M, (int)N,
-                         krange, part);
-      hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, P.stream, part, nsplit, (int)N, T,
+    // sub-panel a
+    launch_panel(P, B + col0 * s + col0, s, M, na, P.d_tau.p + col0, Pp, DR, Vb, M);
+    gram_t(Vb, M, M, na, P.d_tau.p + col0, Ta);
+    int nsplit_ab = 1;
+    if (nbb > 0) {
+      // apply sub-panel a to sub-panel b, then factor b
+      double* Cb = B + (col0 + kPanel) * s + col0;
+      int nsplit, krange;
+      tn_split(M, 1, ncu, 64, &nsplit, &krange);
+      hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, Cb, s, M, nbb, krange,
+                         part);
+      hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((nbb + 3) / 4)), dim3(256), 0, P.stream, part, nsplit, nbb, Ta,
                          W2);
-      hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((M + 63) / 64), (unsigned)ntile), dim3(256), 0, P.stream, C, s,
-                         Vb, (int64_t)M, W2, M, (int)N, nb);
+      hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((M + 63) / 64), 1), dim3(256), 0, P.stream, Cb, s, Vb,
+                         (int64_t)M, W2, M, nbb, kPanel);
+      double* Vbb = Vb + (int64_t)kPanel * M + kPanel;
+      launch_panel(P, B + (col0 + kPanel) * s + col0 + kPanel, s, M - kPanel, nbb, P.d_tau.p + col0 + kPanel, Pp,
+                   DR, Vbb, M);
+      hipLaunchKernelGGL(k_zero_top, dim3(kPanel * kPanel / 256), dim3(256), 0, P.stream, Vb, (int64_t)M);
+      gram_t(Vbb, M, M - kPanel, nbb, P.d_tau.p + col0 + kPanel, Tb);
+      // Gab = Va^T Vb over rows 64..M-1
+      tn_split(M - kPanel, 1, ncu, 64, &nsplit_ab, &krange);
+      hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit_ab), dim3(256), 0, P.stream, Vb + kPanel, (int64_t)M, Vbb,
+                         (int64_t)M, M - kPanel, nbb, krange, part);
+    } else {
+      // columns 64..127 of V are unused: keep them zero for the 128-wide products
+      hipLaunchKernelGGL(k_zero_top, dim3(kPanel * kPanel / 256), dim3(256), 0, P.stream, Vb, (int64_t)M);
+      RFM_HIP(hipMemsetAsync(Vb + (int64_t)kPanel * M, 0, (size_t)kPanel * M * sizeof(double), P.stream));
+    }
+    hipLaunchKernelGGL(k_combine_t, dim3(1), dim3(256), 0, P.stream, Ta, Tb, part, nsplit_ab, nbb, T);
+    const int64_t N = n - col0 - nbo;
+    if (N > 0) {
+      double* C = B + (col0 + nbo) * s + col0;
+      const int ntile = (int)((N + kBig - 1) / kBig);
+      int nsplit, krange;
+      tn_split(M, ntile, ncu, max_split, &nsplit, &krange);
+      krange = (krange + kKC - 1) / kKC * kKC;
+      nsplit = (M + krange - 1) / krange;
+      hipLaunchKernelGGL(k_gemm_tn128, dim3(ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, C, s, M, (int)N,
+                         krange, part);
+      hipLaunchKernelGGL(k_reduce_w128, dim3((unsigned)((N + 1) / 2)), dim3(256), 0, P.stream, part, nsplit, (int)N,
+                         T, W2);
+      hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)ntile), dim3(256), 0,
+                         P.stream, C, s, Vb, (int64_t)M, W2, (int64_t)kBig, M, (int)N, kBig);
     }
     RFM_HIP(hipGetLastError());
   }

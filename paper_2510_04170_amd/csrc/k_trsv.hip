@@ -22,22 +22,32 @@ constexpr int kTB = 64;
 constexpr int kSpinLimit = 1 << 26;
 // sync words used here: [8] ticket counter, [9] error flag, [16 ...] block flags
 enum { kTicket = 8, kTrsvErr = 9, kFlags = 16 };
+constexpr int kBatch = 8;  // flags polled per round trip
 
 __device__ __forceinline__ const double* tile_ptr(const double* Rt, int bi, int bj) {
   return Rt + ((size_t)bj * (bj + 1) / 2 + bi) * kTB * kTB;
 }
 
-__device__ __forceinline__ void wait_flag(int32_t* sync, int blk, int32_t epoch) {
-  int spins = 0;
-  while (__hip_atomic_load(&sync[kFlags + blk], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-    __builtin_amdgcn_s_sleep(1);
-    if ((++spins & 1023) == 0 && __hip_atomic_load(&sync[kTrsvErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-      break;  // a wait already timed out: drain
-    if (spins > kSpinLimit) {
-      __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      break;
-    }
-  }
+// Cross-workgroup handoff without cache maintenance: the published block of x
+// and its flag are written and read with device-scope relaxed atomics (sc1,
+// coherent across the XCDs' L2s); the writer waits for its data stores to be
+// acknowledged before it stores the flag.
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stores_done() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+__device__ __forceinline__ double bcast(double v, int k) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, k);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), k);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
 // mode 0: R x = y   (back substitution over row blocks)
@@ -53,6 +63,9 @@ __global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int
   __shared__ int tk_sh;
   __shared__ double Dt[kTB][kTB + 1];
   __shared__ double rhs[kTB];
+  __shared__ double rdiag[kTB];
+  __shared__ double xs[kBatch][kTB];
+  __shared__ int nready_sh;
   __shared__ double red[4][kTB];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   if (tid == 0) {
@@ -69,28 +82,106 @@ __global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int
     coef = sub_sel == 1 ? st->beta * st->inv_alpha : 0.0;
   }
 
+  // diagonal tile to LDS first: it does not depend on any other block
+  {
+    const double* T = tile_ptr(Rt, i, i);
+    for (int e = tid; e < kTB * kTB; e += 256) Dt[e % kTB][e / kTB] = T[e];
+  }
+  __syncthreads();
+  if (tid < kTB) rdiag[tid] = 1.0 / Dt[tid][tid];
+
   // off-diagonal contributions
   double acc = 0.0;            // MODE 0: row lane of the block, columns quarter wv
   double accT[16];             // MODE 1: columns wv*16 .. +15, rows lane
 #pragma unroll
   for (int q = 0; q < 16; ++q) accT[q] = 0.0;
+  // Blocks of x become ready in chain order.  Per step, wavefront 0 polls the
+  // flags of up to kBatch upcoming blocks in one round trip, loads every ready
+  // block once into LDS, and all four wavefronts then stream those tiles.
   if (MODE == 0) {
-    for (int j = nbk - 1; j > i; --j) {
-      if (tid == 0) wait_flag(sync, j, epoch);
+    int j = nbk - 1;
+    while (j > i) {
+      if (wv == 0) {
+        const int cnt = min(kBatch, j - i);
+        int ready = 0;
+        int spins = 0;
+        while (true) {
+          int ok = 0;  // lanes past cnt count as not ready, so ~bal has a set bit at or below cnt
+          if (lane < cnt) ok = __hip_atomic_load(&sync[kFlags + j - lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+          const unsigned long long bal = __ballot(ok);
+          ready = __builtin_ctzll(~bal);  // leading run of ready blocks j, j-1, ...
+          if (ready > cnt) ready = cnt;
+          if (ready > 0) break;
+          __builtin_amdgcn_s_sleep(1);
+          if ((++spins & 1023) == 0 && __hip_atomic_load(&sync[kTrsvErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ready = cnt;
+            break;
+          }
+          if (spins > kSpinLimit) {
+            __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ready = cnt;
+            break;
+          }
+        }
+        double xv[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) xv[b] = b < ready ? ld_dev(&z[(size_t)(j - b) * kTB + lane]) : 0.0;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) xs[b][lane] = xv[b];
+        if (lane == 0) nready_sh = ready;
+      }
       __syncthreads();
-      const double* T = tile_ptr(Rt, i, j);
-      const double* xj = z + (size_t)j * kTB;
-#pragma unroll 4
-      for (int c = wv * 16; c < wv * 16 + 16; ++c) acc += T[c * kTB + lane] * xj[c];
+      const int ready = nready_sh;
+      for (int b = 0; b < ready; ++b) {
+        const double* T = tile_ptr(Rt, i, j - b);
+#pragma unroll
+        for (int c = wv * 16; c < wv * 16 + 16; ++c) acc += T[c * kTB + lane] * xs[b][c];
+      }
+      __syncthreads();
+      j -= ready;
     }
   } else {
-    for (int j = 0; j < i; ++j) {
-      if (tid == 0) wait_flag(sync, j, epoch);
-      __syncthreads();
-      const double* T = tile_ptr(Rt, j, i);
-      const double zl = z[(size_t)j * kTB + lane];
+    int j = 0;
+    while (j < i) {
+      if (wv == 0) {
+        const int cnt = min(kBatch, i - j);
+        int ready = 0;
+        int spins = 0;
+        while (true) {
+          int ok = 0;  // lanes past cnt count as not ready, so ~bal has a set bit at or below cnt
+          if (lane < cnt) ok = __hip_atomic_load(&sync[kFlags + j + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+          const unsigned long long bal = __ballot(ok);
+          ready = __builtin_ctzll(~bal);
+          if (ready > cnt) ready = cnt;
+          if (ready > 0) break;
+          __builtin_amdgcn_s_sleep(1);
+          if ((++spins & 1023) == 0 && __hip_atomic_load(&sync[kTrsvErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ready = cnt;
+            break;
+          }
+          if (spins > kSpinLimit) {
+            __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ready = cnt;
+            break;
+          }
+        }
+        double xv[kBatch];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) accT[q] += T[(wv * 16 + q) * kTB + lane] * zl;
+        for (int b = 0; b < kBatch; ++b) xv[b] = b < ready ? ld_dev(&z[(size_t)(j + b) * kTB + lane]) : 0.0;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) xs[b][lane] = xv[b];
+        if (lane == 0) nready_sh = ready;
+      }
+      __syncthreads();
+      const int ready = nready_sh;
+      for (int b = 0; b < ready; ++b) {
+        const double* T = tile_ptr(Rt, j + b, i);
+        const double zl = xs[b][lane];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) accT[q] += T[(wv * 16 + q) * kTB + lane] * zl;
+      }
+      __syncthreads();
+      j += ready;
     }
   }
   // combine: red[wv][row]
@@ -105,11 +196,6 @@ __global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int
       if (lane == q) red[0][wv * 16 + q] = v;
     }
   }
-  // diagonal tile to LDS
-  {
-    const double* T = tile_ptr(Rt, i, i);
-    for (int e = tid; e < kTB * kTB; e += 256) Dt[e % kTB][e / kTB] = T[e];
-  }
   __syncthreads();
   if (tid < kTB) {
     const int row = i * kTB + tid;
@@ -122,20 +208,22 @@ __global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int
   if (wv == 0) {
     double r = rhs[lane];
     if (MODE == 0) {
+#pragma unroll
       for (int k = kTB - 1; k >= 0; --k) {
-        const double xk = __shfl(r, k, 64) / Dt[k][k];
+        const double xk = bcast(r, k) * rdiag[k];
         if (lane == k) r = xk;
         else if (lane < k) r -= Dt[lane][k] * xk;
       }
     } else {
+#pragma unroll
       for (int k = 0; k < kTB; ++k) {
-        const double xk = __shfl(r, k, 64) / Dt[k][k];
+        const double xk = bcast(r, k) * rdiag[k];
         if (lane == k) r = xk;
         else if (lane > k) r -= Dt[k][lane] * xk;
       }
     }
     const int row = i * kTB + lane;
-    z[row] = r;  // padded length: nbk * 64
+    st_dev(&z[row], r);  // padded length: nbk * 64
     double o = r;
     if (sub && row < n) o = r - coef * sub[row];
     if (row < n) out[row] = o;
@@ -146,16 +234,27 @@ __global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int
       if (lane == 0) partial[i] = q;
     }
   }
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    __hip_atomic_store(&sync[kFlags + i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (wv == 0) {
+    stores_done();
+    if (lane == 0) __hip_atomic_store(&sync[kFlags + i], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 }  // namespace
 
 int trsv_block() { return kTB; }
+
+// report (and clear) a dependency wait that hit its spin limit in an earlier solve
+void check_trsv_error(Problem& P) {
+  int32_t err = 0;
+  RFM_HIP(hipMemcpyAsync(&err, P.d_sync.p + kTrsvErr, sizeof(err), hipMemcpyDeviceToHost, P.stream));
+  RFM_HIP(hipStreamSynchronize(P.stream));
+  if (err) {
+    const int32_t zero = 0;
+    RFM_HIP(hipMemcpy(P.d_sync.p + kTrsvErr, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    throw Error(RFM_EDEVICE, "triangular solve: dependency wait timed out");
+  }
+}
 
 // x = R^{-1} (y * yscale) or R^{-T} (y * yscale); with st != null the scale and the
 // subtraction coefficient come from the LSQR state.  sub_vec may alias x.

@@ -224,6 +224,7 @@ void launch_get_r_cols(Problem& P, int64_t c0, int64_t ncols, double* out);
 void launch_trsv(Problem& P, const double* y, double* x, bool transpose, const double* sub_vec,
                  const LsqrState* st, int yscale_sel, int sub_sel, double* red_partials);
 int trsv_block();
+void check_trsv_error(Problem& P);
 
 // k_lsqr.hip
 void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, int* iters, int* istop);

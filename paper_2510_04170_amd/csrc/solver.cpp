@@ -80,7 +80,7 @@ struct Driver {
     int it = 0, is = 0;
     lsqr_run(P, rhs, o.lsqr_tol, o.lsqr_max_iter, y, &it, &is);
     launch_trsv(P, y, d, false, nullptr, nullptr, 0, 0, nullptr);
-    sync();
+    check_trsv_error(P);
     st.t_lsqr += now() - t0;
     st.lsqr_iters_total += it;
     if (st.nsteps < RFM_MAX_STEPS) st.lsqr_iters[st.nsteps] = it;
