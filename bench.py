@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the randomized preconditioned Newton solver on one MI355X.
+
+A step is one complete Newton solve from the zero guess: assembly with the row
+scale, Gaussian sketch, QR, preconditioned LSQR, back-transform, line search and
+update, repeated until the stop test fires.  The workload is the steady 3-D
+Gray-Scott system on the unit cube, 4 x 4 x 4 boxes, 300 tanh features per box and
+component (n = 38,400 unknowns), 10^3 collocation points per box and 10 x 10 face
+grids (m = 204,800 rows), sketch s = 2n, LSQR tolerance 1e-10, FP64 throughout.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+prints one JSON line.  The problem description is uploaded before the timed
+region; the coefficient vector lives in device memory.  Kernel times for the
+roofline figures are HIP events recorded by the library around its kernels on
+the stream they run on, over the timed steps.
+
+    python bench.py --summarize-rocpd DB
+
+prints a per-kernel summary (launches, total and average duration) of a
+rocprofv3 kernel-trace database.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import re
+import sqlite3
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+
+METRIC = "Newton solves/s at relL2<=1e-6; sketch-GEMM TFLOP/s; LSQR SpMV HBM GB/s"
+
+
+def summarize_rocpd(db_path: str) -> str:
+    db = sqlite3.connect(db_path)
+    cur = db.cursor()
+    cols = [r[1] for r in cur.execute("pragma table_info(kernels)")]
+    iname = cols.index("name") if "name" in cols else cols.index("kernel_name")
+    ist, ien = cols.index("start"), cols.index("end")
+    agg = {}
+    for r in cur.execute("select * from kernels"):
+        n = r[iname].replace("(anonymous namespace)::", "")
+        n = re.sub(r"\(.*", "", n)
+        d = (r[ien] - r[ist]) * 1e-9
+        a = agg.setdefault(n, [0, 0.0])
+        a[0] += 1
+        a[1] += d
+    tot = sum(v[1] for v in agg.values())
+    lines = [f"# kernel summary of {os.path.basename(db_path)}: {sum(v[0] for v in agg.values())} dispatches, "
+             f"{tot:.4f} s of kernel time",
+             f"{'total_s':>10} {'pct':>6} {'calls':>7} {'avg_us':>12}  kernel"]
+    for n, (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{t:10.4f} {100 * t / tot:6.1f} {c:7d} {1e6 * t / c:12.1f}  {n}")
+    return "\n".join(lines)
+
+
+def cpu_baseline(quick: bool) -> dict:
+    """The CPU oracle on a bounded sample of the same workload family."""
+    import numpy as np
+    import rfm_workloads as W
+    from oracle import rfm as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    nsub, J, q = ((2, 1, 1), 30, 4) if quick else ((2, 2, 2), 60, 5)
+    prob = W.config2(nsub=nsub, J=J, q=q, test_per_dim=2)
+    t0 = time.perf_counter()
+    u, st = O.ipn(prob, opts=O.Opts(gamma=2.0, lsqr_tol=1e-10))
+    dt = time.perf_counter() - t0
+    n_full = 4 * 4 * 4 * 2 * 300
+    scale = (n_full / prob.n) ** 3
+    return {"value": 1.0 / (dt * scale), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle IPN (FP64 numpy, dense J, Philox sketch, LAPACK QR, own LSQR) on the same "
+                       f"Gray-Scott system with {nsub} boxes, J={J}, q={q} (n={prob.n}, m={O.row_table(prob)[1]}): "
+                       f"{dt:.2f} s for {st.outer_iters} Newton steps; extrapolated to n={n_full} by (n/n_s)^3, "
+                       f"the growth of the QR that dominates the solve"),
+            "measured_s": dt, "n_sample": prob.n}
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--method", choices=["ipn", "amipn"], default="ipn")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-rocpd", metavar="DB")
+    a = ap.parse_args()
+    if a.summarize_rocpd:
+        print(summarize_rocpd(a.summarize_rocpd))
+        return
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              f"(a multi-GPU layout is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import rfm_workloads as W
+    import paper_2510_04170_amd as R
+
+    rank = int(os.environ.get("RANK", "0"))
+    prob = W.config2()
+    lp = R.from_description(prob)
+    n, m = lp.n, lp.m
+    method = R.RFM_AMIPN if a.method == "amipn" else R.RFM_IPN
+    opts = R.default_opts(method=method, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5)
+    dev = torch.device("cuda", 0)
+    u = torch.zeros(n, dtype=torch.float64, device=dev)
+    print(f"[bench] workload ready: m={m} n={n}; warmup {a.warmup}", file=sys.stderr, flush=True)
+    for _ in range(a.warmup):
+        u.zero_()
+        lp.solve(u, opts)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    lp.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for k in range(a.steps):
+        u.zero_()
+        _, stats, rc = lp.solve(u, opts)
+        print(f"[bench] step {k + 1}/{a.steps}: status {rc}, IT {stats['outer_iters']}, NJ {stats['jac_evals']}, "
+              f"{stats['t_total']:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = lp.profile_read()
+    lp.profile_enable(False)
+
+    elapsed = t1 - t0
+    val = lp.eval(u, prob.test_x, prob.test_owner)
+    ex = prob.exact(prob.test_x)
+    rel = (np.linalg.norm(val - ex, axis=0) / np.linalg.norm(ex, axis=0)).tolist()
+
+    def rate(name, what):
+        k = kern.get(name)
+        if not k or k["seconds"] <= 0:
+            return None
+        return (k["flops"] / k["seconds"] / 1e12) if what == "flops" else (k["bytes"] / k["seconds"] / 1e9)
+
+    kernels = {}
+    for name, k in kern.items():
+        kernels[name] = {"launches": k["launches"], "seconds": round(k["seconds"], 6),
+                         "avg_us": round(1e6 * k["seconds"] / max(1, k["launches"]), 2)}
+        if k["flops"] > 0:
+            kernels[name]["tflops"] = round(k["flops"] / k["seconds"] / 1e12, 3)
+        if k["bytes"] > 0:
+            kernels[name]["gbs"] = round(k["bytes"] / k["seconds"] / 1e9, 1)
+    cand = {nm: k for nm, k in kern.items() if not nm.endswith("_total")}
+    dom = max(cand, key=lambda nm: cand[nm]["seconds"])
+    dk = cand[dom]
+    mfma_bound = dk["flops"] > 0 and dk["flops"] / max(dk["bytes"], 1.0) > PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if mfma_bound:
+        achieved = dk["flops"] / dk["seconds"] / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "per_launch_flops": dk["flops"] / dk["launches"],
+                "avg_launch_us": round(1e6 * dk["seconds"] / dk["launches"], 2)}
+    else:
+        achieved = dk["bytes"] / dk["seconds"] / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "per_launch_bytes": dk["bytes"] / dk["launches"],
+                "avg_launch_us": round(1e6 * dk["seconds"] / dk["launches"], 2)}
+
+    out = {
+        "metric": METRIC,
+        "value": a.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "gray_scott_3d_4x4x4_J300_q10", "n": n, "m": m, "s": 2 * n, "method": a.method,
+                   "sketch": "gaussian_philox4x64_f64", "lsqr_tol": 1e-10, "outer_tol": 1e-10,
+                   "row_scale_c": 100.0, "initial_guess": "zero"},
+        "relL2": rel,
+        "relL2_target_met": bool(max(rel) <= 1e-6),
+        "newton": {"outer_iters": stats["outer_iters"], "jac_evals": stats["jac_evals"],
+                   "lsqr_iters": stats["lsqr_iters"], "final_resnorm": stats["final_resnorm"]},
+        "sketch_tflops": rate("sketch_f64", "flops"),
+        "lsqr_spmv_gbs": {"jmul": rate("jmul", "bytes"), "jtmul": rate("jtmul", "bytes")},
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if rank == 0 and not a.no_cpu_baseline:
+        print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(a.quick_cpu_baseline)
+    if rank == 0:
+        print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

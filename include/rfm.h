@@ -226,6 +226,29 @@ rfm_status rfm_stage_lsqr(rfm_problem* p, const double* rhs, double tol, int32_t
 rfm_status rfm_stage_linesearch(rfm_problem* p, const double* u, const double* du, int32_t gs_iters,
                                 double* alpha, double* phi);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing.  While enabled, the main kernels are bracketed by HIP events
+ * on the problem's stream; each record accumulates launches, seconds, and the
+ * algorithmic floating-point operations and HBM bytes of those launches
+ * (flops: 2 s nnz(J) for the sketch, 2 M N K for the QR products; bytes: the
+ * stored Jacobian plus the vectors for J x and J^T y, the packed triangle of R
+ * for a triangular solve).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double seconds;
+  double flops;
+  double bytes;
+} rfm_kernel_stat;
+
+/* on != 0 starts recording (clearing previous records); on == 0 stops. */
+rfm_status rfm_profile_enable(rfm_problem* p, int32_t on);
+
+/* Copies up to max records to out (synchronising the stream first) and returns
+ * the number of records, or a negative status. */
+int32_t rfm_profile_read(rfm_problem* p, rfm_kernel_stat* out, int32_t max);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,11 @@ class rfm_solve_stats(C.Structure):
                     t_linesearch=self.t_linesearch, t_total=self.t_total, status=self.status_detail)
 
 
+class rfm_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("seconds", C.c_double), ("flops", C.c_double),
+                ("bytes", C.c_double)]
+
+
 class RfmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"rfm status {status}: {msg}")
@@ -98,6 +103,8 @@ _SIGS = {
     "rfm_rt_solve": (C.c_int, [_P, _D, _D]),
     "rfm_stage_lsqr": (C.c_int, [_P, _D, C.c_double, C.c_int32, _D, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "rfm_stage_linesearch": (C.c_int, [_P, _D, _D, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "rfm_profile_enable": (C.c_int, [_P, C.c_int32]),
+    "rfm_profile_read": (C.c_int32, [_P, C.POINTER(rfm_kernel_stat), C.c_int32]),
 }
 
 
@@ -303,6 +310,16 @@ class RfmProblem:
         _check(lib().rfm_stage_lsqr(self.h, rhs.ctypes.data, tol, max_iter, y.ctypes.data, C.byref(it),
                                     C.byref(istop)))
         return y, it.value, istop.value
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().rfm_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel name: dict(launches, seconds, flops, bytes)} recorded since profile_enable."""
+        buf = (rfm_kernel_stat * 64)()
+        k = _check(lib().rfm_profile_read(self.h, buf, 64))
+        return {buf[i].name.decode(): dict(launches=buf[i].launches, seconds=buf[i].seconds, flops=buf[i].flops,
+                                           bytes=buf[i].bytes) for i in range(min(k, 64))}
 
     def stage_linesearch(self, u, du, gs_iters: int = 25):
         u, du = _f64(u), _f64(du)

@@ -68,6 +68,62 @@ static std::vector<double> host_doubles(const double* src, size_t count) {
 
 Problem::~Problem() {}
 
+int Profiler::slot_of(const char* name) {
+  for (size_t i = 0; i < names.size(); ++i)
+    if (names[i] == name) return (int)i;
+  names.emplace_back(name);
+  stats.emplace_back();
+  return (int)names.size() - 1;
+}
+
+void Profiler::begin(hipStream_t s, hipEvent_t* a) {
+  if (pool.empty()) {
+    hipEvent_t e;
+    RFM_HIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  *a = pool.back();
+  pool.pop_back();
+  RFM_HIP(hipEventRecord(*a, s));
+}
+
+void Profiler::end(hipStream_t s, hipEvent_t a, const char* name, double flops, double bytes) {
+  hipEvent_t b;
+  if (pool.empty()) {
+    RFM_HIP(hipEventCreate(&b));
+  } else {
+    b = pool.back();
+    pool.pop_back();
+  }
+  RFM_HIP(hipEventRecord(b, s));
+  pending.push_back(PendingEv{a, b, slot_of(name), flops, bytes});
+  if (pending.size() >= 4096) resolve();
+}
+
+void Profiler::resolve() {
+  for (auto& pe : pending) {
+    RFM_HIP(hipEventSynchronize(pe.b));
+    float ms = 0.f;
+    RFM_HIP(hipEventElapsedTime(&ms, pe.a, pe.b));
+    KStat& k = stats[pe.slot];
+    k.launches += 1;
+    k.seconds += 1e-3 * ms;
+    k.flops += pe.flops;
+    k.bytes += pe.bytes;
+    pool.push_back(pe.a);
+    pool.push_back(pe.b);
+  }
+  pending.clear();
+}
+
+Profiler::~Profiler() {
+  for (auto& pe : pending) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
 static void set_device(Problem& P) { RFM_HIP(hipSetDevice(P.device)); }
 
 static bool all_finite(const std::vector<double>& v) {
@@ -691,6 +747,38 @@ rfm_status rfm_eval(rfm_problem* p, const double* u, int64_t npts, const double*
 rfm_status rfm_stage_linesearch(rfm_problem* p, const double* u, const double* du, int32_t gs_iters, double* alpha,
                                 double* phi) {
   return guarded_rc([&] { return api_linesearch(ready(p), u, du, gs_iters, alpha, phi); });
+}
+
+rfm_status rfm_profile_enable(rfm_problem* p, int32_t on) {
+  return guarded([&] {
+    Problem& P = get(p);
+    P.prof.resolve();
+    if (on) {
+      P.prof.names.clear();
+      P.prof.stats.clear();
+    }
+    P.prof.on = on != 0;
+  });
+}
+
+int32_t rfm_profile_read(rfm_problem* p, rfm_kernel_stat* out, int32_t max) {
+  int32_t count = 0;
+  rfm_status rc = guarded([&] {
+    Problem& P = get(p);
+    RFM_CHECK(max >= 0 && (max == 0 || out), RFM_EINVAL, "rfm_profile_read: bad output");
+    RFM_HIP(hipStreamSynchronize(P.stream));
+    P.prof.resolve();
+    count = (int32_t)P.prof.names.size();
+    for (int32_t i = 0; i < count && i < max; ++i) {
+      std::memset(&out[i], 0, sizeof(out[i]));
+      std::strncpy(out[i].name, P.prof.names[i].c_str(), sizeof(out[i].name) - 1);
+      out[i].launches = P.prof.stats[i].launches;
+      out[i].seconds = P.prof.stats[i].seconds;
+      out[i].flops = P.prof.stats[i].flops;
+      out[i].bytes = P.prof.stats[i].bytes;
+    }
+  });
+  return rc == RFM_OK ? count : rc;
 }
 
 }  // extern "C"

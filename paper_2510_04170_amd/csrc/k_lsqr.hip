@@ -274,6 +274,7 @@ void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, i
   hipLaunchKernelGGL(k_lsqr_init_xw, dim3(gn), dim3(kB), 0, P.stream, st, vt, y, w, n);
   RFM_HIP(hipGetLastError());
 
+  ProfScope ps_all(P.prof, P.stream, "lsqr_total", 0.0, 0.0);
   const int poll = 8;
   int32_t done = 0;
   for (int it = 0; it < maxit && !done; ++it) {

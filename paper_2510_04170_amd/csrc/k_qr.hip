@@ -637,6 +637,7 @@ void launch_panel(Problem& P, double* A, int64_t ld, int M, int nb, double* tau,
   int chunk = (M + G - 1) / G;
   const int need = (chunk + 3) / 4;
   hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, P.stream, P.d_sync.p);
+  ProfScope ps(P.prof, P.stream, "qr_panel", 4.0 * M * (double)nb * nb, 16.0 * M * (double)nb);
   dim3 grid(G);
   if (need <= 16) launch_panel_t<16>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
   else if (need <= 32) launch_panel_t<32>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
@@ -731,12 +732,20 @@ void qr_factor(Problem& P) {
       tn_split(M, ntile, ncu, max_split, &nsplit, &krange);
       krange = (krange + kKC - 1) / kKC * kKC;
       nsplit = (M + krange - 1) / krange;
-      hipLaunchKernelGGL(k_gemm_tn128, dim3(ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, C, s, M, (int)N,
-                         krange, part);
+      {
+        ProfScope ps(P.prof, P.stream, "qr_gemm_tn", 2.0 * M * (double)N * kBig,
+                     8.0 * ((double)M * N + (double)M * kBig + (double)nsplit * N * kBig));
+        hipLaunchKernelGGL(k_gemm_tn128, dim3(ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, C, s, M,
+                           (int)N, krange, part);
+      }
       hipLaunchKernelGGL(k_reduce_w128, dim3((unsigned)((N + 1) / 2)), dim3(256), 0, P.stream, part, nsplit, (int)N,
                          T, W2);
-      hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)ntile), dim3(256), 0,
-                         P.stream, C, s, Vb, (int64_t)M, W2, (int64_t)kBig, M, (int)N, kBig);
+      {
+        ProfScope ps(P.prof, P.stream, "qr_gemm_nn", 2.0 * M * (double)N * kBig,
+                     8.0 * (2.0 * M * N + (double)M * kBig + (double)N * kBig));
+        hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)ntile), dim3(256), 0,
+                           P.stream, C, s, Vb, (int64_t)M, W2, (int64_t)kBig, M, (int)N, kBig);
+      }
     }
     RFM_HIP(hipGetLastError());
   }

@@ -509,6 +509,7 @@ int kper_of(const Problem& P) { return (P.J + kWave - 1) / kWave; }
 }  // namespace
 
 void launch_assemble(Problem& P, const double* u, double c) {
+  ProfScope ps(P.prof, P.stream, "assemble", 0.0, 8.0 * ((double)P.nvals + 2.0 * P.m + P.n));
   RowsCtx C = make_ctx(P);
   dim3 grid((unsigned)((P.m + kRowsPerBlock - 1) / kRowsPerBlock));
   switch (kper_of(P)) {
@@ -526,6 +527,7 @@ void launch_assemble(Problem& P, const double* u, double c) {
 }
 
 void launch_row_eval(Problem& P, const double* u, const double* du, double* out_ab) {
+  ProfScope ps(P.prof, P.stream, "linesearch_products", 0.0, 8.0 * ((double)P.m * (2 + 2 * P.ncomp) + 2.0 * P.n));
   RowsCtx C = make_ctx(P);
   dim3 grid((unsigned)((P.m + kRowsPerBlock - 1) / kRowsPerBlock));
   hipLaunchKernelGGL(k_row_eval<1>, grid, dim3(256), 0, P.stream, C, P.m, u, du, out_ab);
@@ -538,6 +540,7 @@ int reduce_blocks_rows(const Problem& P) {
 }
 
 void launch_phi(Problem& P, const double* ab, double alpha, const double* D, double* out_sumsq) {
+  ProfScope ps(P.prof, P.stream, "linesearch_phi", 0.0, 8.0 * (double)P.m * (3 + 2 * P.ncomp));
   RowsCtx C = make_ctx(P);
   const int nb = reduce_blocks_rows(P);
   hipLaunchKernelGGL(k_phi, dim3(nb), dim3(kRedBlock), 0, P.stream, C, P.m, ab, alpha, D, P.d_red.p, nullptr);
@@ -570,12 +573,14 @@ void launch_eval_points(Problem& P, const double* u, int64_t npts, const double*
 
 void launch_jmul(Problem& P, const double* J, const double* x, double* y, const double* u_prev,
                  const LsqrState* st, double* red_partials) {
+  ProfScope ps(P.prof, P.stream, "jmul", 2.0 * P.nvals, 8.0 * ((double)P.nvals + P.n + (u_prev ? 2.0 : 1.0) * P.m));
   hipLaunchKernelGGL(k_jmul, dim3(P.ntiles), dim3(256), 0, P.stream, P.d_tiles.p, J, x, y, u_prev, st,
                      red_partials);
   RFM_HIP(hipGetLastError());
 }
 
 void launch_jtmul(Problem& P, const double* J, const double* y, double* x, const LsqrState* st) {
+  ProfScope ps(P.prof, P.stream, "jtmul", 2.0 * P.nvals, 8.0 * ((double)P.nvals + P.m + P.n));
   hipLaunchKernelGGL(k_jtmul_tiles, dim3(P.ntiles), dim3(256), 0, P.stream, P.d_tiles.p, J, y, st, P.d_part.p);
   hipLaunchKernelGGL(k_jtmul_reduce, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, P.stream, P.d_tiles.p,
                      P.d_cb_ptr.p, P.d_cb_tile.p, P.d_cb_off.p, P.J, P.n, P.d_part.p, st, x);

@@ -153,6 +153,7 @@ void launch_sketch(Problem& P, uint64_t seed, uint64_t jac_index, int prec) {
   const int ntc = (P.J + 15) / 16;
   const int nctw = (ntc + 3) / 4;
   const double sq = sqrt((double)P.s);
+  ProfScope ps(P.prof, P.stream, "sketch_f64", 2.0 * (double)P.s * P.nvals, 8.0 * ((double)P.nvals + (double)P.s * P.n));
   switch (nctw) {
 #define RFM_CASE(N)                                                                                          \
   case N:                                                                                                    \

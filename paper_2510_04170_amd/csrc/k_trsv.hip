@@ -264,6 +264,8 @@ void launch_trsv(Problem& P, const double* y, double* x, bool transpose, const d
   RFM_CHECK(kFlags + nbk <= (int)P.d_sync.n, RFM_EINVAL, "triangular solve: too many blocks");
   double* z = P.d_vec.p + 4 * std::max(P.m, P.n);  // padded solution (nbk * 64 <= n + 63)
   RFM_CHECK(4 * std::max(P.m, P.n) + (int64_t)nbk * kTB <= (int64_t)P.d_vec.n, RFM_EINVAL, "scratch too small");
+  const double nn = (double)P.n;
+  ProfScope ps(P.prof, P.stream, "trsv", nn * nn, 8.0 * (nn * (nn + 1) / 2 + 3 * nn));
   int32_t epoch = (int32_t)(++P.trsv_epoch & 0x7fffffff);
   if (epoch == 0) epoch = (int32_t)(++P.trsv_epoch & 0x7fffffff);
   if (transpose)

@@ -137,6 +137,44 @@ struct GroupH {
   int64_t row0, nrows;
 };
 
+// event-timed kernel records (rfm_profile_*)
+struct KStat {
+  int64_t launches = 0;
+  double seconds = 0, flops = 0, bytes = 0;
+};
+struct PendingEv {
+  hipEvent_t a, b;
+  int slot;
+  double flops, bytes;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<std::string> names;
+  std::vector<KStat> stats;
+  std::vector<PendingEv> pending;
+  std::vector<hipEvent_t> pool;
+  int slot_of(const char* name);
+  void begin(hipStream_t s, hipEvent_t* a);
+  void end(hipStream_t s, hipEvent_t a, const char* name, double flops, double bytes);
+  void resolve();
+  ~Profiler();
+};
+
+// RAII bracket around one kernel launch (no-op when profiling is off)
+struct ProfScope {
+  Profiler& pr;
+  hipStream_t s;
+  const char* name;
+  double flops, bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(Profiler& p, hipStream_t st, const char* n, double f, double b) : pr(p), s(st), name(n), flops(f), bytes(b) {
+    if (pr.on) pr.begin(s, &a);
+  }
+  ~ProfScope() {
+    if (pr.on && a) pr.end(s, a, name, flops, bytes);
+  }
+};
+
 struct Problem {
   int dim = 0, ncomp = 0, device = 0;
   hipStream_t stream = nullptr;
@@ -190,6 +228,7 @@ struct Problem {
   DBuf<LsqrState> d_lsqr;
   DBuf<double> d_ws_lsqr;         // LSQR vectors and partials
   DBuf<double> d_F0, d_F1;        // residual vectors of the drivers
+  Profiler prof;
 
   ~Problem();
 };
