@@ -10,12 +10,12 @@ is bumped by two Weyl constants between rounds.  Written here in plain numpy
 uint64 arithmetic (the 128-bit product is assembled from 32-bit halves).
 
 Sketch entries (a reading of the sketch S_k of Sec. 4.1, made Gaussian):
-S[i, r] for sketch row i and Jacobian row r uses the counter (i // 4, r, 0, 0)
-and the key (seed, jac_index).  The four 64-bit outputs x0..x3 form two
-Box-Muller pairs (x0, x1) and (x2, x3); with u1 = ((x >> 11) + 1) 2^-53 in
-(0, 1] and u2 = (x >> 11) 2^-53 in [0, 1), the pair gives
-sqrt(-2 ln u1) cos(2 pi u2) for the even lane and ... sin(...) for the odd
-lane.  Entries are scaled by 1/sqrt(s) so that E[S^T S] = I.
+S[i, r] for sketch row i and Jacobian row r uses the counter (i // 8, r, 0, 0)
+and the key (seed, jac_index).  Each of the four 64-bit outputs x_w is one
+Box-Muller pair: with u1 = ((x_w >> 32) + 1) 2^-32 in (0, 1] and
+u2 = (x_w mod 2^32) 2^-32 in [0, 1), rows 8q + 2w and 8q + 2w + 1 get
+sqrt(-2 ln u1) cos(2 pi u2) and sqrt(-2 ln u1) sin(2 pi u2).  Entries are
+scaled by 1/sqrt(s) so that E[S^T S] = I.
 """
 from __future__ import annotations
 
@@ -63,28 +63,22 @@ def philox4x64(ctr: np.ndarray, key, rounds: int = 10) -> np.ndarray:
     return np.stack([x0, x1, x2, x3], axis=1)
 
 
-def _unit_open_closed(x: np.ndarray) -> np.ndarray:
-    return ((x >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
-
-
-def _unit_closed_open(x: np.ndarray) -> np.ndarray:
-    return (x >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
-
-
-def gaussian_quads(seed: int, jac_index: int, q: np.ndarray, r: np.ndarray) -> np.ndarray:
-    """N(0,1) entries G[4q + l, r] for l = 0..3, returned as [N, 4]."""
+def gaussian_octets(seed: int, jac_index: int, q: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """N(0,1) entries G[8q + l, r] for l = 0..7, returned as [N, 8]."""
     q = np.asarray(q, np.int64).ravel()
     r = np.asarray(r, np.int64).ravel()
     ctr = np.zeros((q.size, 4), np.uint64)
     ctr[:, 0] = q.astype(np.uint64)
     ctr[:, 1] = r.astype(np.uint64)
     x = philox4x64(ctr, (seed, jac_index))
-    out = np.empty((q.size, 4))
-    for pair in range(2):
-        rad = np.sqrt(-2.0 * np.log(_unit_open_closed(x[:, 2 * pair])))
-        ang = 2.0 * np.pi * _unit_closed_open(x[:, 2 * pair + 1])
-        out[:, 2 * pair] = rad * np.cos(ang)
-        out[:, 2 * pair + 1] = rad * np.sin(ang)
+    out = np.empty((q.size, 8))
+    for w in range(4):
+        u1 = ((x[:, w] >> np.uint64(32)).astype(np.float64) + 1.0) * 2.0 ** -32
+        u2 = (x[:, w] & np.uint64(0xFFFFFFFF)).astype(np.float64) * 2.0 ** -32
+        rad = np.sqrt(-2.0 * np.log(u1))
+        ang = 2.0 * np.pi * u2
+        out[:, 2 * w] = rad * np.cos(ang)
+        out[:, 2 * w + 1] = rad * np.sin(ang)
     return out
 
 
@@ -95,14 +89,14 @@ def gaussian_entries(seed: int, jac_index: int, i: np.ndarray, r: np.ndarray) ->
     shape = np.broadcast(i, r).shape
     i = np.broadcast_to(i, shape).ravel()
     r = np.broadcast_to(r, shape).ravel()
-    quads = gaussian_quads(seed, jac_index, i // 4, r)
-    return quads[np.arange(i.size), i % 4].reshape(shape)
+    octs = gaussian_octets(seed, jac_index, i // 8, r)
+    return octs[np.arange(i.size), i % 8].reshape(shape)
 
 
 def sketch_matrix(seed: int, jac_index: int, s: int, m: int) -> np.ndarray:
     """Dense S in R^{s x m} with N(0, 1/s) entries (small problems only)."""
-    nq = (s + 3) // 4
+    nq = (s + 7) // 8
     qq, rr = np.meshgrid(np.arange(nq), np.arange(m), indexing="ij")
-    quads = gaussian_quads(seed, jac_index, qq, rr).reshape(nq, m, 4)
-    G = quads.transpose(0, 2, 1).reshape(4 * nq, m)[:s]
+    octs = gaussian_octets(seed, jac_index, qq, rr).reshape(nq, m, 8)
+    G = octs.transpose(0, 2, 1).reshape(8 * nq, m)[:s]
     return G / np.sqrt(s)

@@ -34,8 +34,8 @@ constexpr int kPanel = 64;      // panel width ib
 constexpr int kTB = 64;         // tile size of the triangular-solve storage
 constexpr int kSpinLimit = 1 << 26;
 
-// sync words (d_sync): [0] grid barrier counter, [1] error flag, [2] singular flag
-enum { kSyncBarrier = 0, kSyncError = 1, kSyncSingular = 2 };
+// sync words (d_sync): [1] error flag, [2] singular flag, [1024, 1280) grid-barrier arrival words
+enum { kSyncBarrier = 0, kSyncError = 1, kSyncSingular = 2, kSyncArrive = 1024 };
 
 // Cross-workgroup exchange without cache maintenance: partial sums and the
 // diagonal row are written and read with device-scope relaxed atomics (sc1,
@@ -48,17 +48,20 @@ __device__ __forceinline__ void st_dev(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Grid barrier without atomics: workgroup g publishes its phase in its own word
+// (after its data stores are acknowledged); thread t < G polls word t.  Arrival
+// words start at 0 for every launch (k_reset_sync).
 __device__ __forceinline__ void grid_barrier(int32_t* sync, int nblocks, int& phase) {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
   ++phase;
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(&sync[kSyncBarrier], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int target = phase * nblocks;
+  int32_t* arrive = sync + kSyncArrive;
+  if (threadIdx.x == 0) __hip_atomic_store(&arrive[blockIdx.x], phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((int)threadIdx.x < nblocks) {
     int spins = 0;
-    while (__hip_atomic_load(&sync[kSyncBarrier], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&arrive[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < phase) {
       __builtin_amdgcn_s_sleep(1);
       if ((++spins & 1023) == 0 &&
           __hip_atomic_load(&sync[kSyncError], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
@@ -73,12 +76,12 @@ __device__ __forceinline__ void grid_barrier(int32_t* sync, int nblocks, int& ph
 }
 
 __global__ void k_reset_sync(int32_t* sync) {
-  if (threadIdx.x == 0) sync[kSyncBarrier] = 0;
+  sync[kSyncArrive + threadIdx.x] = 0;  // one word per workgroup, 256 threads
 }
 
 // Panel factorisation.  A: panel top-left (rows col0.., leading dimension ld),
 // M rows, nb <= 64 columns; chunk rows per workgroup; RPT >= ceil(chunk / 4).
-// P: partial-sum buffer [2][G][64], DR: diagonal-row buffer [2][64].
+// P: partial-sum buffer [2][G][64] (G <= 256), DR: diagonal rows [2][64] then column totals [2][64].
 // Writes V below the diagonal and R on/above it in place, tau[nb], and the unit
 // lower-trapezoidal V into Vb (M x 64, leading dimension ldv).
 template <int RPT>
@@ -89,6 +92,7 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t l
   __shared__ double colj[4][RPT];
   __shared__ double red[4][kPanel];
   __shared__ double scal_sh[4];
+  __shared__ double wsum[4];
   const int G = gridDim.x, g = blockIdx.x;
   const int c = threadIdx.x % kPanel, rg = threadIdx.x / kPanel;
   const int r0 = g * chunk;
@@ -106,6 +110,7 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t l
     const int buf = j & 1;
     double* Pb = P + (size_t)buf * G * kPanel;
     double* DRb = DR + (size_t)buf * kPanel;
+    double* TOTb = DR + (size_t)(2 + buf) * kPanel;
     // column j of this chunk to LDS
     if (c == j) {
 #pragma unroll
@@ -131,26 +136,26 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t l
     __syncthreads();
     if (rg == 0 && c >= j && c < nb) st_dev(&Pb[(size_t)g * kPanel + c], (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]));
     grid_barrier(sync, G, phase);
-    // reduce the partials of every workgroup in a fixed order
-    double tot = 0.0;
-    if (c >= j && c < nb) {
-      // keep 16 device-coherent loads in flight, then add them in a fixed order
-      for (int g0 = rg; g0 < G; g0 += 64) {
-        double v[16];
+    // stage 1: workgroup g reduces columns j + g, j + g + G, ... over all workgroups'
+    // partials in a fixed order and publishes the totals
+    for (int cc = g; cc < nb - j; cc += G) {
+      const int col = j + cc;
+      double v = threadIdx.x < G ? ld_dev(&Pb[(size_t)threadIdx.x * kPanel + col]) : 0.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int gg = g0 + 4 * u;
-          v[u] = gg < G ? ld_dev(&Pb[(size_t)gg * kPanel + c]) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) tot += v[u];
-      }
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) st_dev(&TOTb[col], (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
+      __syncthreads();
     }
-    red[rg][c] = tot;
+    grid_barrier(sync, G, phase);
+    // stage 2: every workgroup reads the column totals it needs
+    double gc = 0.0;
+    if (c >= j && c < nb) gc = ld_dev(&TOTb[c]);
+    if (threadIdx.x == j) red[0][j] = gc;
     __syncthreads();
-    double gc = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
     if (threadIdx.x == 0) {
-      const double sigma = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+      const double sigma = red[0][j];
       const double alpha = ld_dev(&DRb[j]);
       double beta, t, sc;
       if (sigma == 0.0) {
@@ -365,32 +370,48 @@ __global__ void __launch_bounds__(256) k_gemm_nn(double* __restrict__ C, int64_t
 constexpr int kBig = 128;
 constexpr int kKC = 16;
 
-// C[M x N] += A[M x K] B, A column-major (lda), B[k][n] = Bt[n * ldb + k]; K a multiple of 16
-__global__ void __launch_bounds__(256) k_gemm_nn128(double* __restrict__ C, int64_t ldc,
-                                                    const double* __restrict__ A, int64_t lda,
-                                                    const double* __restrict__ Bt, int64_t ldb, int M, int N, int K) {
-  __shared__ double As[kKC][kBig + 1];
-  __shared__ double Bs[kKC][kBig + 1];
-  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
-  const int wr = wv / 2, wc = wv % 2;
-  const int r0 = blockIdx.x * kBig, n0 = blockIdx.y * kBig;
-  v4d acc[4][4];
+// One 16-deep k-chunk of MFMAs on LDS tiles As[k][m], Bs[k][n] for a 2 x 2 wavefront grid.
+__device__ __forceinline__ void mfma_chunk(const double (*As)[kBig + 1], const double (*Bs)[kBig + 1], int lane,
+                                           int wr, int wc, v4d (&acc)[4][4]) {
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int col = n0 + wc * 64 + ct * 16 + lane % 16;
+  for (int ks = 0; ks < kKC / 4; ++ks) {
+    const int kr = ks * 4 + lane / 16;
+    double a[4], b[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) a[rt] = As[kr][wr * 64 + rt * 16 + lane % 16];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) b[ct] = Bs[kr][wc * 64 + ct * 16 + lane % 16];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int r = r0 + wr * 64 + rt * 16 + (lane / 16) + 4 * t;
-        acc[rt][ct][t] = (r < M && col < N) ? C[(int64_t)col * ldc + r] : 0.0;
-      }
+      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
   }
+}
+
+// C[M x N] += A[M x K] B, A column-major (lda), B[k][n] = Bt[n * ldb + k]; K a multiple of 16.
+// LDS is double-buffered: chunk c+1 is loaded to registers while chunk c runs on the
+// MFMA units and stored to the other buffer afterwards, one barrier per chunk.
+__global__ void __launch_bounds__(256, 2) k_gemm_nn128(double* __restrict__ C, int64_t ldc,
+                                                       const double* __restrict__ A, int64_t lda,
+                                                       const double* __restrict__ Bt, int64_t ldb, int M, int N,
+                                                       int K) {
+  __shared__ double As[2][kKC][kBig + 1];
+  __shared__ double Bs[2][kKC][kBig + 1];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int wr = wv / 2, wc = wv % 2;
+  const int r0 = blockIdx.x * kBig, n0 = blockIdx.y * kBig;
+  // accumulate from zero and add C in the epilogue, so that no C values are live
+  // during the K loop (keeps the kernel at two wavefronts per SIMD)
+  v4d acc[4][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = v4d{0, 0, 0, 0};
   // loader roles: A: m = tid % 128, k = tid / 128 + 2 i;  B: k = tid % 16, n = tid / 16 + 16 i
   const int am = tid % kBig, ak = tid / kBig;
   const int bk = tid % kKC, bn = tid / kKC;
-  double ra[8], rb[8];
-  auto load = [&](int k0) {
+  double ra0[8], rb0[8];
+  auto load = [&](double (&ra)[8], double (&rb)[8], int k0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + ak + 2 * i;
@@ -399,55 +420,64 @@ __global__ void __launch_bounds__(256) k_gemm_nn128(double* __restrict__ C, int6
       rb[i] = (n < N) ? Bt[(int64_t)n * ldb + k0 + bk] : 0.0;
     }
   };
-  load(0);
-  for (int k0 = 0; k0 < K; k0 += kKC) {
+  auto stash = [&](const double (&ra)[8], const double (&rb)[8], int buf) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      As[ak + 2 * i][am] = ra[i];
-      Bs[bk][bn + 16 * i] = rb[i];
+      As[buf][ak + 2 * i][am] = ra[i];
+      Bs[buf][bk][bn + 16 * i] = rb[i];
     }
+  };
+  load(ra0, rb0, 0);
+  stash(ra0, rb0, 0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += kKC) {
+    const bool more = k0 + kKC < K;
+    if (more) load(ra0, rb0, k0 + kKC);
+    mfma_chunk(As[buf], Bs[buf], lane, wr, wc, acc);
+    if (more) stash(ra0, rb0, buf ^ 1);
     __syncthreads();
-    if (k0 + kKC < K) load(k0 + kKC);
-#pragma unroll
-    for (int ks = 0; ks < kKC / 4; ++ks) {
-      const int kr = ks * 4 + lane / 16;
-      double a[4], b[4];
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) a[rt] = As[kr][wr * 64 + rt * 16 + lane % 16];
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) b[ct] = Bs[kr][wc * 64 + ct * 16 + lane % 16];
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
-    }
-    __syncthreads();
+    buf ^= 1;
   }
+  // epilogue: per column tile, 16 loads of C in flight, then add and store
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) {
     const int col = n0 + wc * 64 + ct * 16 + lane % 16;
     if (col >= N) continue;
+    double* ccol = C + (int64_t)col * ldc;
+    double cv[4][4];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int r = r0 + wr * 64 + rt * 16 + (lane / 16) + 4 * t;
-        if (r < M) C[(int64_t)col * ldc + r] = acc[rt][ct][t];
+        cv[rt][t] = r < M ? ccol[r] : 0.0;
+      }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = r0 + wr * 64 + rt * 16 + (lane / 16) + 4 * t;
+        if (r < M) ccol[r] = cv[rt][t] + acc[rt][ct][t];
       }
   }
 }
 
 // part[split][n][p] = sum_{k in split} A[k][p] B[k][n]; A: K x 128 (lda), B: K x N (ldb), both
 // column-major; rows of a split: [split * krange, ...), krange a multiple of 16
-__global__ void __launch_bounds__(256) k_gemm_tn128(const double* __restrict__ A, int64_t lda,
-                                                    const double* __restrict__ B, int64_t ldb, int K, int N,
-                                                    int krange, double* __restrict__ part) {
-  __shared__ double As[kKC][kBig + 1];
-  __shared__ double Bs[kKC][kBig + 1];
+__global__ void __launch_bounds__(256, 2) k_gemm_tn128(const double* __restrict__ A, int64_t lda,
+                                                       const double* __restrict__ B, int64_t ldb, int K, int N,
+                                                       int krange, double* __restrict__ part, int pstride) {
+  __shared__ double As[2][kKC][kBig + 1];
+  __shared__ double Bs[2][kKC][kBig + 1];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
-  const int n0 = blockIdx.x * kBig;
-  const int split = blockIdx.y;
+  // grid: (P halves of a 256-wide V, column tiles, row splits); the two halves of one
+  // column tile are neighbours in launch order, so the second read of C hits cache
+  const int half = blockIdx.x;
+  const int n0 = blockIdx.y * kBig;
+  const int split = blockIdx.z;
+  A += (int64_t)half * kBig * lda;
   const int kb = split * krange, ke = min(K, kb + krange);
   v4d acc[4][4];
 #pragma unroll
@@ -455,8 +485,8 @@ __global__ void __launch_bounds__(256) k_gemm_tn128(const double* __restrict__ A
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = v4d{0, 0, 0, 0};
   const int lk = tid % kKC, lc = tid / kKC;  // k = lk, column lc + 16 i
-  double ra[8], rb[8];
-  auto load = [&](int k0) {
+  double ra0[8], rb0[8];
+  auto load = [&](double (&ra)[8], double (&rb)[8], int k0) {
     const int k = k0 + lk;
     const bool kv = k < ke;
 #pragma unroll
@@ -466,31 +496,28 @@ __global__ void __launch_bounds__(256) k_gemm_tn128(const double* __restrict__ A
       rb[i] = (kv && n0 + c < N) ? B[(int64_t)(n0 + c) * ldb + k] : 0.0;
     }
   };
-  if (kb < ke) load(kb);
-  for (int k0 = kb; k0 < ke; k0 += kKC) {
+  auto stash = [&](const double (&ra)[8], const double (&rb)[8], int buf) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      As[lk][lc + 16 * i] = ra[i];
-      Bs[lk][lc + 16 * i] = rb[i];
+      As[buf][lk][lc + 16 * i] = ra[i];
+      Bs[buf][lk][lc + 16 * i] = rb[i];
     }
-    __syncthreads();
-    if (k0 + kKC < ke) load(k0 + kKC);
-#pragma unroll
-    for (int ks = 0; ks < kKC / 4; ++ks) {
-      const int kr = ks * 4 + lane / 16;
-      double a[4], b[4];
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) a[rt] = As[kr][wr * 64 + rt * 16 + lane % 16];
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) b[ct] = Bs[kr][wc * 64 + ct * 16 + lane % 16];
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
-    }
-    __syncthreads();
+  };
+  if (kb < ke) {
+    load(ra0, rb0, kb);
+    stash(ra0, rb0, 0);
   }
-  double* o = part + (size_t)split * N * kBig;
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += kKC) {
+    const bool more = k0 + kKC < ke;
+    if (more) load(ra0, rb0, k0 + kKC);
+    mfma_chunk(As[buf], Bs[buf], lane, wr, wc, acc);
+    if (more) stash(ra0, rb0, buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* o = part + (size_t)split * N * pstride + (size_t)half * kBig;
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) {
     const int col = n0 + wc * 64 + ct * 16 + lane % 16;
@@ -498,7 +525,7 @@ __global__ void __launch_bounds__(256) k_gemm_tn128(const double* __restrict__ A
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) o[(int64_t)col * kBig + wr * 64 + rt * 16 + (lane / 16) + 4 * t] = acc[rt][ct][t];
+      for (int t = 0; t < 4; ++t) o[(int64_t)col * pstride + wr * 64 + rt * 16 + (lane / 16) + 4 * t] = acc[rt][ct][t];
   }
 }
 
@@ -567,6 +594,82 @@ __global__ void k_zero_top(double* __restrict__ V, int64_t ldv) {
   if (e < kPanel * kPanel) V[(int64_t)(kPanel + e / kPanel) * ldv + e % kPanel] = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// 256-column outer panels: T of four 64-column reflector blocks, and the
+// -T^T W reduction for 256 reflectors
+// ---------------------------------------------------------------------------
+constexpr int kOuter = 256;
+
+// zero rows [0, nrows) of columns [c0, c0 + ncols) of V (leading dimension ldv)
+__global__ void k_zero_block(double* __restrict__ V, int64_t ldv, int c0, int ncols, int nrows) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (int64_t)ncols * nrows) V[(int64_t)(c0 + e / nrows) * ldv + e % nrows] = 0.0;
+}
+
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+// G[a][b] (row-major 128 x 128) = sum over splits of part[split][b][a] (pstride 128)
+__global__ void k_gsum128(const double* __restrict__ part, int nsplit, double* __restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kBig * kBig) return;
+  const int a = e / kBig, b = e % kBig;
+  double g = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) g += part[((size_t)sp * kBig + b) * kBig + a];
+  G[e] = g;
+}
+
+// C = alpha * A B for row-major 128 x 128 matrices, one thread per entry
+__global__ void k_sq_gemm128(const double* __restrict__ A, const double* __restrict__ B, double alpha,
+                             double* __restrict__ C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kBig * kBig) return;
+  const int i = e / kBig, j = e % kBig;
+  double v = 0.0;
+  for (int k = 0; k < kBig; ++k) v += A[i * kBig + k] * B[k * kBig + j];
+  C[e] = alpha * v;
+}
+
+// T (256 x 256, row-major) = [[T1, Y], [0, T2]] from 128 x 128 blocks
+__global__ void k_assemble_t256(const double* __restrict__ T1, const double* __restrict__ T2,
+                                const double* __restrict__ Y, double* __restrict__ T) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kOuter * kOuter) return;
+  const int qq = e / kOuter, p = e % kOuter;
+  double v = 0.0;
+  if (qq < kBig && p < kBig) v = T1[qq * kBig + p];
+  else if (qq >= kBig && p >= kBig) v = T2[(qq - kBig) * kBig + (p - kBig)];
+  else if (qq < kBig && p >= kBig) v = Y[qq * kBig + (p - kBig)];
+  T[e] = v;
+}
+
+// W2[n][p] = -sum_{q <= p} T[q][p] W[n][q], W = sum over splits (pstride 256), 8 columns per block
+__global__ void __launch_bounds__(256) k_reduce_w256(const double* __restrict__ part, int nsplit, int N,
+                                                     const double* __restrict__ T, double* __restrict__ W2) {
+  __shared__ double Wsh[8][kOuter];
+  const int p = threadIdx.x;
+  const int n0 = blockIdx.x * 8;
+  for (int c = 0; c < 8; ++c) {
+    const int n = n0 + c;
+    double w = 0.0;
+    if (n < N)
+      for (int sp = 0; sp < nsplit; ++sp) w += part[((size_t)sp * N + n) * kOuter + p];
+    Wsh[c][p] = w;
+  }
+  __syncthreads();
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int qq = 0; qq <= p; ++qq) {
+    const double t = T[qq * kOuter + p];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] += t * Wsh[c][qq];
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if (n0 + c < N) W2[(int64_t)(n0 + c) * kOuter + p] = -v[c];
+}
+
 // R (upper n x n of B) into tiled storage: tile (bi, bj), bi <= bj, at
 // ((bj (bj + 1)) / 2 + bi) * 64 * 64, column-major inside the tile, zero padded;
 // row i is negated when B[i][i] < 0 so that diag(R) > 0.
@@ -633,10 +736,10 @@ void launch_panel_t(Problem& P, dim3 grid, double* A, int64_t ld, int M, int nb,
 void launch_panel(Problem& P, double* A, int64_t ld, int M, int nb, double* tau, double* Pp, double* DR, double* Vb,
                   int64_t ldv) {
   const int ncu = num_cus(P.device);
-  int G = std::max(1, std::min(ncu, (M + 63) / 64));
+  int G = std::max(1, std::min(std::min(ncu, 256), (M + 63) / 64));
   int chunk = (M + G - 1) / G;
   const int need = (chunk + 3) / 4;
-  hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, P.stream, P.d_sync.p);
+  hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(256), 0, P.stream, P.d_sync.p);
   ProfScope ps(P.prof, P.stream, "qr_panel", 4.0 * M * (double)nb * nb, 16.0 * M * (double)nb);
   dim3 grid(G);
   if (need <= 16) launch_panel_t<16>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
@@ -664,87 +767,131 @@ void qr_factor(Problem& P) {
   const int64_t s = P.s, n = P.n;
   RFM_CHECK(s >= n, RFM_EINVAL, "QR: sketch has fewer rows than columns");
   const int ncu = num_cus(P.device);
-  const int max_split = 32;
+  const int max_split = 16;
   // workspace
-  const size_t vb = (size_t)s * kBig;
-  const size_t tn = (size_t)max_split * std::max<int64_t>(n, kBig) * kBig;
-  const size_t need = vb + 2 * kPanel * kPanel + kBig * kBig + 2 * (size_t)ncu * kPanel + 2 * kPanel + tn +
-                      (size_t)n * kBig + 256;
+  const size_t vb = (size_t)s * kOuter;
+  const size_t tn = (size_t)max_split * std::max<int64_t>(n, kOuter) * kOuter;
+  const size_t small = 4 * kPanel * kPanel + 5 * kBig * kBig + kOuter * kOuter;
+  const size_t need = vb + small + 2 * (size_t)ncu * kPanel + 4 * kPanel + tn + (size_t)n * kOuter + 256;
   P.d_ws.resize(need);
   double* Vb = P.d_ws.p;
-  double* Ta = Vb + vb;
-  double* Tb = Ta + kPanel * kPanel;
-  double* T = Tb + kPanel * kPanel;
-  double* Pp = T + kBig * kBig;
+  double* T64 = Vb + vb;                    // 4 blocks of 64 x 64
+  double* T128 = T64 + 4 * kPanel * kPanel; // 2 blocks of 128 x 128
+  double* G128 = T128 + 2 * kBig * kBig;
+  double* X128 = G128 + kBig * kBig;
+  double* Y128 = X128 + kBig * kBig;
+  double* T256 = Y128 + kBig * kBig;
+  double* Pp = T256 + kOuter * kOuter;
   double* DR = Pp + 2 * (size_t)ncu * kPanel;
-  double* part = DR + 2 * kPanel;
+  double* part = DR + 4 * kPanel;
   double* W2 = part + tn;
   P.d_tau.resize(n);
   int32_t zero3[3] = {0, 0, 0};
   RFM_HIP(hipMemcpyAsync(P.d_sync.p, zero3, sizeof(zero3), hipMemcpyHostToDevice, P.stream));
+  auto zero_block = [&](double* V, int64_t ldv, int c0, int ncols, int nrows) {
+    const int64_t cnt = (int64_t)ncols * nrows;
+    if (cnt > 0)
+      hipLaunchKernelGGL(k_zero_block, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, P.stream, V, ldv, c0, ncols,
+                         nrows);
+  };
+  auto fill = [&](double* p, int64_t cnt) {
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, P.stream, p, cnt, 0.0);
+  };
 
   double* B = P.d_B.p;
   auto gram_t = [&](const double* V, int64_t ldv, int K, int nb, const double* tau, double* Tout) {
     int nsplit, krange;
-    tn_split(K, 1, ncu / 4, 64, &nsplit, &krange);
+    tn_split(K, 1, std::max(1, ncu / 16), 64, &nsplit, &krange);
     hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit), dim3(256), 0, P.stream, V, ldv, V, ldv, K, nb, krange, part);
     hipLaunchKernelGGL(k_build_t, dim3(1), dim3(256), 0, P.stream, part, nsplit, nb, tau, Tout);
   };
-  for (int64_t col0 = 0; col0 < n; col0 += kBig) {
-    const int nbo = (int)std::min<int64_t>(kBig, n - col0);
-    const int na = std::min(kPanel, nbo), nbb = nbo - na;
+  for (int64_t col0 = 0; col0 < n; col0 += kOuter) {
+    const int nbo = (int)std::min<int64_t>(kOuter, n - col0);
+    const int nsp = (nbo + kPanel - 1) / kPanel;
     const int M = (int)(s - col0);
-    // sub-panel a
-    launch_panel(P, B + col0 * s + col0, s, M, na, P.d_tau.p + col0, Pp, DR, Vb, M);
-    gram_t(Vb, M, M, na, P.d_tau.p + col0, Ta);
-    int nsplit_ab = 1;
-    if (nbb > 0) {
-      // apply sub-panel a to sub-panel b, then factor b
-      double* Cb = B + (col0 + kPanel) * s + col0;
-      int nsplit, krange;
-      tn_split(M, 1, ncu, 64, &nsplit, &krange);
-      hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, Cb, s, M, nbb, krange,
-                         part);
-      hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((nbb + 3) / 4)), dim3(256), 0, P.stream, part, nsplit, nbb, Ta,
-                         W2);
-      hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((M + 63) / 64), 1), dim3(256), 0, P.stream, Cb, s, Vb,
-                         (int64_t)M, W2, M, nbb, kPanel);
-      double* Vbb = Vb + (int64_t)kPanel * M + kPanel;
-      launch_panel(P, B + (col0 + kPanel) * s + col0 + kPanel, s, M - kPanel, nbb, P.d_tau.p + col0 + kPanel, Pp,
-                   DR, Vbb, M);
-      hipLaunchKernelGGL(k_zero_top, dim3(kPanel * kPanel / 256), dim3(256), 0, P.stream, Vb, (int64_t)M);
-      gram_t(Vbb, M, M - kPanel, nbb, P.d_tau.p + col0 + kPanel, Tb);
-      // Gab = Va^T Vb over rows 64..M-1
-      tn_split(M - kPanel, 1, ncu, 64, &nsplit_ab, &krange);
-      hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit_ab), dim3(256), 0, P.stream, Vb + kPanel, (int64_t)M, Vbb,
-                         (int64_t)M, M - kPanel, nbb, krange, part);
-    } else {
-      // columns 64..127 of V are unused: keep them zero for the 128-wide products
-      hipLaunchKernelGGL(k_zero_top, dim3(kPanel * kPanel / 256), dim3(256), 0, P.stream, Vb, (int64_t)M);
-      RFM_HIP(hipMemsetAsync(Vb + (int64_t)kPanel * M, 0, (size_t)kPanel * M * sizeof(double), P.stream));
+    // V columns of sub-panels beyond the last one stay zero
+    if (nsp < 4) zero_block(Vb, M, nsp * kPanel, (4 - nsp) * kPanel, M);
+    if (nsp < 4) fill(T64 + (size_t)nsp * kPanel * kPanel, (int64_t)(4 - nsp) * kPanel * kPanel);
+    int nbs[4] = {0, 0, 0, 0};
+    for (int sp = 0; sp < nsp; ++sp) {
+      const int64_t c_sp = col0 + (int64_t)sp * kPanel;
+      const int Msp = M - sp * kPanel;
+      const int nbsp = std::min(kPanel, nbo - sp * kPanel);
+      nbs[sp] = nbsp;
+      double* Vsp = Vb + (int64_t)sp * kPanel * M + sp * kPanel;
+      if (sp > 0) zero_block(Vb, M, sp * kPanel, kPanel, sp * kPanel);
+      launch_panel(P, B + c_sp * s + c_sp, s, Msp, nbsp, P.d_tau.p + c_sp, Pp, DR, Vsp, M);
+      gram_t(Vsp, M, Msp, nbsp, P.d_tau.p + c_sp, T64 + (size_t)sp * kPanel * kPanel);
+      const int Nr = nbo - (sp + 1) * kPanel;
+      if (Nr > 0) {
+        // apply this sub-panel's reflectors to the rest of the outer panel
+        double* Cr = B + (c_sp + kPanel) * s + c_sp;
+        int nsplit, krange;
+        tn_split(Msp, (Nr + 63) / 64, ncu, 64, &nsplit, &krange);
+        hipLaunchKernelGGL(k_gemm_tn, dim3((unsigned)((Nr + 63) / 64), nsplit), dim3(256), 0, P.stream, Vsp,
+                           (int64_t)M, Cr, s, Msp, Nr, krange, part);
+        hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((Nr + 3) / 4)), dim3(256), 0, P.stream, part, nsplit, Nr,
+                           T64 + (size_t)sp * kPanel * kPanel, W2);
+        hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((Msp + 63) / 64), (unsigned)((Nr + 63) / 64)), dim3(256), 0,
+                           P.stream, Cr, s, Vsp, (int64_t)M, W2, Msp, Nr, kPanel);
+      }
     }
-    hipLaunchKernelGGL(k_combine_t, dim3(1), dim3(256), 0, P.stream, Ta, Tb, part, nsplit_ab, nbb, T);
+    // T of the 256 reflectors: pairs of 64-blocks into 128-blocks, then the two 128-blocks
+    for (int pr = 0; pr < 2; ++pr) {
+      const int a = 2 * pr, b = 2 * pr + 1;
+      int nsplit_ab = 1, krange;
+      const int Kab = M - b * kPanel;
+      if (nbs[b] > 0) {
+        tn_split(Kab, 1, ncu, 64, &nsplit_ab, &krange);
+        hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit_ab), dim3(256), 0, P.stream,
+                           Vb + (int64_t)a * kPanel * M + b * kPanel, (int64_t)M,
+                           Vb + (int64_t)b * kPanel * M + b * kPanel, (int64_t)M, Kab, nbs[b], krange, part);
+      }
+      hipLaunchKernelGGL(k_combine_t, dim3(1), dim3(256), 0, P.stream, T64 + (size_t)a * kPanel * kPanel,
+                         T64 + (size_t)b * kPanel * kPanel, part, nsplit_ab, nbs[b], T128 + (size_t)pr * kBig * kBig);
+    }
+    {
+      // G = V01^T V23 over rows 128..M-1 (V23 is zero above row 128)
+      const int K2 = M - kBig;
+      if (nsp > 2 && K2 > 0) {
+        int nsplit, krange;
+        tn_split(K2, 1, ncu, max_split, &nsplit, &krange);
+        krange = (krange + kKC - 1) / kKC * kKC;
+        nsplit = (K2 + krange - 1) / krange;
+        hipLaunchKernelGGL(k_gemm_tn128, dim3(1, 1, nsplit), dim3(256), 0, P.stream, Vb + kBig, (int64_t)M,
+                           Vb + (int64_t)kBig * M + kBig, (int64_t)M, K2, kBig, krange, part, kBig);
+        hipLaunchKernelGGL(k_gsum128, dim3(kBig * kBig / 256), dim3(256), 0, P.stream, part, nsplit, G128);
+      } else {
+        fill(G128, (int64_t)kBig * kBig);  // no reflectors past column 128 in this block
+      }
+      hipLaunchKernelGGL(k_sq_gemm128, dim3(kBig * kBig / 256), dim3(256), 0, P.stream, G128, T128 + kBig * kBig,
+                         1.0, X128);
+      hipLaunchKernelGGL(k_sq_gemm128, dim3(kBig * kBig / 256), dim3(256), 0, P.stream, T128, X128, -1.0, Y128);
+      hipLaunchKernelGGL(k_assemble_t256, dim3(kOuter * kOuter / 256), dim3(256), 0, P.stream, T128,
+                         T128 + kBig * kBig, Y128, T256);
+    }
+    RFM_HIP(hipGetLastError());
     const int64_t N = n - col0 - nbo;
     if (N > 0) {
       double* C = B + (col0 + nbo) * s + col0;
       const int ntile = (int)((N + kBig - 1) / kBig);
       int nsplit, krange;
-      tn_split(M, ntile, ncu, max_split, &nsplit, &krange);
+      tn_split(M, 2 * ntile, ncu, max_split, &nsplit, &krange);
       krange = (krange + kKC - 1) / kKC * kKC;
       nsplit = (M + krange - 1) / krange;
       {
-        ProfScope ps(P.prof, P.stream, "qr_gemm_tn", 2.0 * M * (double)N * kBig,
-                     8.0 * ((double)M * N + (double)M * kBig + (double)nsplit * N * kBig));
-        hipLaunchKernelGGL(k_gemm_tn128, dim3(ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, C, s, M,
-                           (int)N, krange, part);
+        ProfScope ps(P.prof, P.stream, "qr_gemm_tn", 2.0 * M * (double)N * kOuter,
+                     8.0 * (2.0 * M * N + (double)M * kOuter + (double)nsplit * N * kOuter));
+        hipLaunchKernelGGL(k_gemm_tn128, dim3(2, ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, C, s, M,
+                           (int)N, krange, part, kOuter);
       }
-      hipLaunchKernelGGL(k_reduce_w128, dim3((unsigned)((N + 1) / 2)), dim3(256), 0, P.stream, part, nsplit, (int)N,
-                         T, W2);
+      hipLaunchKernelGGL(k_reduce_w256, dim3((unsigned)((N + 7) / 8)), dim3(256), 0, P.stream, part, nsplit, (int)N,
+                         T256, W2);
       {
-        ProfScope ps(P.prof, P.stream, "qr_gemm_nn", 2.0 * M * (double)N * kBig,
-                     8.0 * (2.0 * M * N + (double)M * kBig + (double)N * kBig));
+        ProfScope ps(P.prof, P.stream, "qr_gemm_nn", 2.0 * M * (double)N * kOuter,
+                     8.0 * (2.0 * M * N + (double)M * kOuter + (double)N * kOuter));
         hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)ntile), dim3(256), 0,
-                           P.stream, C, s, Vb, (int64_t)M, W2, (int64_t)kBig, M, (int)N, kBig);
+                           P.stream, C, s, Vb, (int64_t)M, W2, (int64_t)kOuter, M, (int)N, kOuter);
       }
     }
     RFM_HIP(hipGetLastError());

@@ -1,15 +1,16 @@
 // Gaussian sketch B = S (D J) (the sketch of Sec. 4.1 taken Gaussian).
 //
 // S is never stored.  Entry S[i][r] is N(0,1)/sqrt(s) from Philox4x64-10
-// (Salmon et al., SC'11) with counter (i/4, r, 0, 0) and key (seed, jac_index);
-// the four 64-bit outputs give two Box-Muller pairs, i.e. the entries of rows
-// 4q .. 4q+3.  Because every Jacobian row touches at most two column blocks,
-// each Gaussian is generated once per column block it meets.
+// (Salmon et al., SC'11) with counter (i/8, r, 0, 0) and key (seed, jac_index);
+// each of the four 64-bit outputs is one Box-Muller pair (32-bit uniforms),
+// giving the entries of rows 8q .. 8q+7.  Because every Jacobian row touches at
+// most two column blocks, each Gaussian is generated once per column block it
+// meets.
 //
 // Work unit: one workgroup computes a 64-row x J-column slab of B for one
 // column block (box e, component c) and runs over every stored Jacobian tile
-// that touches the block.  Per 16-row chunk of those tiles, the 256 threads
-// generate the 64 x 16 slice of S into LDS (one Philox call each), and each
+// that touches the block.  Per 32-row chunk of those tiles, the 256 threads
+// generate the 64 x 32 slice of S into LDS (one Philox call each), and each
 // wavefront accumulates its column tiles with v_mfma_f64_16x16x4 from the
 // Jacobian rows read straight from HBM.
 #include "rfm_internal.h"
@@ -44,20 +45,20 @@ __device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64
   }
 }
 
-// Box-Muller on one 64-bit pair: u1 in (0,1], u2 in [0,1)
-__device__ __forceinline__ void box_muller(uint64_t xa, uint64_t xb, double& z0, double& z1) {
-  const double u1 = ((double)(xa >> 11) + 1.0) * 0x1.0p-53;
-  const double u2 = (double)(xb >> 11) * 0x1.0p-53;
+// Box-Muller on one 64-bit word: u1 = (hi + 1) 2^-32 in (0,1], u2 = lo 2^-32 in [0,1);
+// cos/sin(2 pi u2) as cospi/sinpi(2 u2), whose argument needs no range reduction
+__device__ __forceinline__ void box_muller(uint64_t x, double& z0, double& z1) {
+  const double u1 = ((double)(x >> 32) + 1.0) * 0x1.0p-32;
+  const double u2 = (double)(x & 0xFFFFFFFFull) * 0x1.0p-32;
   const double rad = sqrt(-2.0 * log(u1));
-  const double two_pi = 2.0 * 3.14159265358979323846;
   double sn, cs;
-  sincos(two_pi * u2, &sn, &cs);
+  sincospi(2.0 * u2, &sn, &cs);
   z0 = rad * cs;
   z1 = rad * sn;
 }
 
 constexpr int kSRows = 64;   // sketch rows per workgroup
-constexpr int kChunk = 16;   // Jacobian rows per LDS stage
+constexpr int kChunk = 32;   // Jacobian rows per LDS stage
 
 // NCTW: 16-column MFMA tiles per wavefront (wavefront w owns tiles w, w+4, ...)
 template <int NCTW>
@@ -66,7 +67,7 @@ __global__ void __launch_bounds__(256) k_sketch_f64(const TileDesc* __restrict__
                                                     const int32_t* __restrict__ cb_tile,
                                                     const int32_t* __restrict__ cb_off,
                                                     const double* __restrict__ Jv, int J, int64_t s,
-                                                    double sqrt_s, uint64_t seed, uint64_t jac,
+                                                    double inv_sqrt_s, uint64_t seed, uint64_t jac,
                                                     double* __restrict__ B) {
   __shared__ double sS[kChunk][kSRows + 1];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
@@ -80,28 +81,30 @@ __global__ void __launch_bounds__(256) k_sketch_f64(const TileDesc* __restrict__
 #pragma unroll
     for (int k = 0; k < NCTW; ++k) acc[rt][k] = v4d{0, 0, 0, 0};
 
-  // generation role of this thread: sketch rows 4*qi .. 4*qi+3 of the slab, Jacobian row rr of the chunk
-  const int qi = tid % 16, rr = tid / 16;
+  // generation role of this thread: sketch rows 8*qi .. 8*qi+7 of the slab, Jacobian row rr of the chunk
+  const int qi = tid % 8, rr = tid / 8;
 
   for (int kk = cb_ptr[blk]; kk < cb_ptr[blk + 1]; ++kk) {
     const TileDesc td = tiles[cb_tile[kk]];
     const int off = cb_off[kk];
     const int w = td.wA + td.wB;
     for (int base = 0; base < td.nrows; base += kChunk) {
-      // S[i0 .. i0+63][row0+base .. +15] into LDS
+      // S[i0 .. i0+63][row0+base .. +31] into LDS
       {
         const int rloc = base + rr;
-        double z[4] = {0, 0, 0, 0};
+        double z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (rloc < td.nrows) {
-          uint64_t c0 = (uint64_t)(i0 / 4 + qi), c1 = (uint64_t)(td.row0 + rloc), c2 = 0, c3 = 0;
+          uint64_t c0 = (uint64_t)(i0 / 8 + qi), c1 = (uint64_t)(td.row0 + rloc), c2 = 0, c3 = 0;
           philox4x64_10(c0, c1, c2, c3, seed, jac);
-          box_muller(c0, c1, z[0], z[1]);
-          box_muller(c2, c3, z[2], z[3]);
+          box_muller(c0, z[0], z[1]);
+          box_muller(c1, z[2], z[3]);
+          box_muller(c2, z[4], z[5]);
+          box_muller(c3, z[6], z[7]);
 #pragma unroll
-          for (int t = 0; t < 4; ++t) z[t] = z[t] / sqrt_s;
+          for (int t = 0; t < 8; ++t) z[t] *= inv_sqrt_s;
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) sS[rr][4 * qi + t] = z[t];
+        for (int t = 0; t < 8; ++t) sS[rr][8 * qi + t] = z[t];
       }
       __syncthreads();
 #pragma unroll
@@ -152,7 +155,7 @@ void launch_sketch(Problem& P, uint64_t seed, uint64_t jac_index, int prec) {
   dim3 grid((unsigned)((P.s + kSRows - 1) / kSRows), (unsigned)nblk);
   const int ntc = (P.J + 15) / 16;
   const int nctw = (ntc + 3) / 4;
-  const double sq = sqrt((double)P.s);
+  const double sq = 1.0 / sqrt((double)P.s);
   ProfScope ps(P.prof, P.stream, "sketch_f64", 2.0 * (double)P.s * P.nvals, 8.0 * ((double)P.nvals + (double)P.s * P.n));
   switch (nctw) {
 #define RFM_CASE(N)                                                                                          \

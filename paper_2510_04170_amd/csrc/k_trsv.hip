@@ -95,6 +95,16 @@ __global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int
   double accT[16];             // MODE 1: columns wv*16 .. +15, rows lane
 #pragma unroll
   for (int q = 0; q < 16; ++q) accT[q] = 0.0;
+  // the tile multiplying the block this one waits for last sits on the critical
+  // path: load this thread's 16 values of it before any waiting
+  double tl[16];
+  {
+    const int jl = MODE == 0 ? i + 1 : i - 1;
+    const bool has = MODE == 0 ? jl < nbk : jl >= 0;
+    const double* T = has ? (MODE == 0 ? tile_ptr(Rt, i, jl) : tile_ptr(Rt, jl, i)) : nullptr;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tl[q] = has ? T[(wv * 16 + q) * kTB + lane] : 0.0;
+  }
   // Blocks of x become ready in chain order.  Per step, wavefront 0 polls the
   // flags of up to kBatch upcoming blocks in one round trip, loads every ready
   // block once into LDS, and all four wavefronts then stream those tiles.
@@ -133,9 +143,14 @@ __global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int
       __syncthreads();
       const int ready = nready_sh;
       for (int b = 0; b < ready; ++b) {
-        const double* T = tile_ptr(Rt, i, j - b);
+        if (j - b == i + 1) {
 #pragma unroll
-        for (int c = wv * 16; c < wv * 16 + 16; ++c) acc += T[c * kTB + lane] * xs[b][c];
+          for (int q = 0; q < 16; ++q) acc += tl[q] * xs[b][wv * 16 + q];
+        } else {
+          const double* T = tile_ptr(Rt, i, j - b);
+#pragma unroll
+          for (int c = wv * 16; c < wv * 16 + 16; ++c) acc += T[c * kTB + lane] * xs[b][c];
+        }
       }
       __syncthreads();
       j -= ready;
@@ -175,10 +190,15 @@ __global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int
       __syncthreads();
       const int ready = nready_sh;
       for (int b = 0; b < ready; ++b) {
-        const double* T = tile_ptr(Rt, j + b, i);
         const double zl = xs[b][lane];
+        if (j + b == i - 1) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) accT[q] += T[(wv * 16 + q) * kTB + lane] * zl;
+          for (int q = 0; q < 16; ++q) accT[q] += tl[q] * zl;
+        } else {
+          const double* T = tile_ptr(Rt, j + b, i);
+#pragma unroll
+          for (int q = 0; q < 16; ++q) accT[q] += T[(wv * 16 + q) * kTB + lane] * zl;
+        }
       }
       __syncthreads();
       j += ready;

@@ -241,7 +241,11 @@ def test_full_solve_grayscott_small():
     _announce("full solve grayscott small")
     prob = W.config2(nsub=(2, 2, 2), J=60, q=5, test_per_dim=4)
     lp, ug, stg, rc, uo, sto = _solve_both(prob, R.RFM_IPN)
-    assert rc == R.RFM_OK, stg
+    # ||DF|| ~ 2e2 at this small problem's discretisation floor, so the absolute
+    # eps = 1e-10 of the stop test is below the rounding noise of ||DF||: the solve
+    # may end with a line search that finds no decrease (a warning, u is usable)
+    assert rc in (R.RFM_OK, R.RFM_ESTALL), stg
+    assert sto.status in ("ok", "stall")
     fg = O.eval_field(prob, ug, prob.test_x, prob.test_owner)
     fo = O.eval_field(prob, uo, prob.test_x, prob.test_owner)
     assert _relerr(fg, fo) < 1e-8
