@@ -97,6 +97,9 @@ def main() -> None:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-rocpd", metavar="DB")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the solves, copy a buffer of this many MiB three times (a reference "
+                         "kernel of known traffic for scaling hardware byte counters)")
     a = ap.parse_args()
     if a.summarize_rocpd:
         print(summarize_rocpd(a.summarize_rocpd))
@@ -120,6 +123,16 @@ def main() -> None:
     dev = torch.device("cuda", 0)
     u = torch.zeros(n, dtype=torch.float64, device=dev)
     print(f"[bench] workload ready: m={m} n={n}; warmup {a.warmup}", file=sys.stderr, flush=True)
+    if a.copy_calibration_mib > 0:
+        nb = a.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads nb bytes, writes nb bytes
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 elementwise copies of {nb} bytes (read {nb}, write {nb} each)",
+              file=sys.stderr, flush=True)
+        del src, dst
     for _ in range(a.warmup):
         u.zero_()
         lp.solve(u, opts)

@@ -138,8 +138,12 @@ typedef struct {
   double tau_rel;          /* AMIPN: early-stop threshold                            */
   double row_scale_c;      /* c of the row scale c / max_j |J_ij| (Sec. 5)            */
   int32_t gs_iters;        /* golden-section iterations after a rejected full step   */
-  int32_t sketch_prec;     /* RFM_PREC_F64 | RFM_PREC_BF16 | RFM_PREC_FP8            */
-  int32_t lsqr_prec;       /* RFM_PREC_F64 | RFM_PREC_F32 (Jacobian in the LSQR matvecs) */
+  int32_t sketch_prec;     /* RFM_PREC_F64 | RFM_PREC_BF16 | RFM_PREC_FP8 (see rfm_stage_sketch) */
+  int32_t lsqr_prec;       /* RFM_PREC_F64 | RFM_PREC_F32: copy of D J in the LSQR products;
+                              F32 falls back to F64 for the rest of the solve at the first
+                              step whose LSQR hits lsqr_max_iter or whose line search finds
+                              no decrease */
+  int32_t sketch_pieces;   /* pieces of D J in a BF16/FP8 sketch, 1..16; 0: 6 (BF16), 12 (FP8) */
   int32_t verbose;         /* 1: one line per outer step on stderr                   */
 } rfm_solve_opts;
 
@@ -156,6 +160,7 @@ typedef struct {
   /* wall time per stage in seconds (HIP events on the problem's stream) */
   double t_assemble, t_sketch, t_qr, t_lsqr, t_linesearch, t_total;
   int32_t status_detail;
+  int32_t lsqr_fp64_fallback;        /* 1: lsqr_prec F32 was abandoned for FP64 during the solve */
 } rfm_solve_stats;
 
 /* Paper values: gamma 3, eta 1e-6, epsilon 1e-10, tau 1e-3, m_max 3, c 100 (Sec. 6). */
@@ -192,11 +197,43 @@ rfm_status rfm_get_jacobian_rows(rfm_problem* p, int64_t r0, int64_t nrows, doub
 rfm_status rfm_jmul(rfm_problem* p, const double* x, double* y);
 rfm_status rfm_jtmul(rfm_problem* p, const double* y, double* x);
 
-/* Sketch B = S (D J) with s = ceil(gamma n) rows; S[i][r] are N(0,1)/sqrt(s) from
- * Philox4x64-10 with counter (i/4, r, 0, 0) and key (seed, jac_index), Box-Muller
- * on the pairs (x0,x1), (x2,x3).  prec: RFM_PREC_F64, _BF16 or _FP8 (the product
- * runs in that precision with FP32 accumulation; B is kept in FP64). */
-rfm_status rfm_stage_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index, int32_t prec);
+/* Sketch B = S (D J) / sqrt(s) with s = ceil(gamma n) rows (Sec. 4.1, with a
+ * Gaussian-like S in place of the count sketch), kept as the current B in FP64.
+ *   prec RFM_PREC_F64: S[i][r] ~ N(0,1) from Philox4x64-10 (Salmon et al.,
+ *     SC'11) with counter (i/8, r, 0, 0) and key (seed, jac_index); 64-bit
+ *     output word w gives rows 8(i/8) + 2w, + 2w + 1 by Box-Muller on
+ *     u1 = (hi32 + 1) 2^-32, u2 = lo32 2^-32.  Product in FP64.
+ *   prec RFM_PREC_BF16 / RFM_PREC_FP8: S[i][r] = K[b] / k_s with b byte
+ *     (i mod 32) of the Philox block for counter (i/32, r, 1, 0) (byte j = bits
+ *     8(j%8).. of word j/8) and K the code table of rfm_sketch_table (k_s = 32
+ *     for BF16, 4 for FP8).  D J is cut into `pieces` integer parts (0: 6 for
+ *     BF16, 12 for FP8) on a fixed-point grid per (column, chunk): the chunks
+ *     of a column block are four consecutive entries of its list of 32-row
+ *     groups (rows 32g .. 32g+31 holding a row that touches the block,
+ *     ascending, padded to a multiple of four); with E = floor(log2 max|D J|)+1
+ *     over the chunk, part p is q_p 2^(E - b(p+1)), q_p the integer nearest the
+ *     remaining value / 2^(E - b(p+1)), b = 8 (BF16) or 4 (FP8).  The matrix
+ *     cores form S times each part exactly (integer sums below 2^24 in FP32);
+ *     the chunk sums are combined in FP64.
+ * Runs on the problem's stream and synchronizes it. */
+rfm_status rfm_stage_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index, int32_t prec,
+                            int32_t pieces);
+
+/* The 256 integer codes of the low-precision sketch: K[b] = the integer nearest
+ * (ties to even) to k_s Phi^{-1}((b + 1/2) / 256), k_s = 32 for RFM_PREC_BF16
+ * and 4 for RFM_PREC_FP8; out[256] on the host.  Needs no problem and no device. */
+rfm_status rfm_sketch_table(int32_t prec, double* out);
+
+/* Low-precision sketch operand of column block `block` (box e, component c ->
+ * e * ncomp + c), as formed by the last BF16/FP8 rfm_stage_sketch: number of
+ * 32-row slots (-1 on a bad argument), and for slots [slot0, slot0 + nslots)
+ * the values of part `piece`, q_p 2^(E - b(p+1)), out[nslots][J][32] (row
+ * 32 g + k, column j of the block at [slot][j][k]), the group g of each slot
+ * (groups[nslots], -1 for padding; may be NULL) and the exponent E of the
+ * slot's chunk per column (scale_exp[nslots][J]; may be NULL). */
+int64_t rfm_sketch_operand_slots(rfm_problem* p, int32_t block);
+rfm_status rfm_get_sketch_operand(rfm_problem* p, int32_t piece, int32_t block, int64_t slot0, int64_t nslots,
+                                  double* out, int32_t* groups, int32_t* scale_exp);
 
 /* Columns [c0, c0 + ncols) of the current sketch B, column-major [ncols][s]. */
 rfm_status rfm_get_sketch_cols(rfm_problem* p, int64_t c0, int64_t ncols, double* out);
@@ -216,8 +253,9 @@ rfm_status rfm_rt_solve(rfm_problem* p, const double* y, double* x);
 
 /* LSQR on min || (D J) R^{-1} y - rhs || with tolerance tol (Paige-Saunders rules 1
  * and 2, atol = btol = tol), y0 = 0; returns y [n], the iteration count and the
- * stop rule (1, 2, or 0 for the iteration limit). */
-rfm_status rfm_stage_lsqr(rfm_problem* p, const double* rhs, double tol, int32_t max_iter, double* y,
+ * stop rule (1, 2, or 0 for the iteration limit).  prec RFM_PREC_F32 multiplies
+ * by D J rounded once to FP32 (products and sums in FP64); RFM_PREC_F64 by D J. */
+rfm_status rfm_stage_lsqr(rfm_problem* p, const double* rhs, double tol, int32_t max_iter, int32_t prec, double* y,
                           int32_t* iters, int32_t* istop);
 
 /* Golden-section line search on phi(a) = ||D F(u + a du)|| with the current row

@@ -42,7 +42,7 @@ import scipy.linalg
 
 from rfm_workloads import (KIND_CONTINUITY, KIND_DIRICHLET, KIND_NEUMANN, KIND_PDE, D_ID, D_LAPLACE,
                            D_LAPLACE_SPACE, D_X0, D_X3, Problem, box_bounds)
-from . import philox
+from . import lowprec, philox
 
 # ---------------------------------------------------------------------------
 # features (Sec. 2.2): phi_ij(x) = tanh(k_ij . l_i(x) + b_ij), l_i(x) = (x - mu_i)/sigma_i
@@ -403,6 +403,9 @@ class Opts:
     tau_rel: float = 1e-3
     row_c: float = 100.0
     gs_iters: int = 25
+    sketch_prec: str = "f64"       # "f64" | "bf16" | "fp8"  (oracle.lowprec)
+    sketch_pieces: int = 0         # pieces of D J in the low-precision sketch (0: format default)
+    lsqr_prec: str = "f64"         # "f64" | "f32": D J copy used by the LSQR products
 
 
 @dataclass
@@ -421,6 +424,7 @@ class Precond:
     DJ: np.ndarray
     D: np.ndarray
     R: Optional[np.ndarray]
+    DJ_lsqr: Optional[np.ndarray] = None   # the copy LSQR multiplies by (DJ itself in FP64 mode)
 
 
 def make_precond(prob: Problem, u: np.ndarray, opts: Opts, jac_index: int) -> Precond:
@@ -430,8 +434,13 @@ def make_precond(prob: Problem, u: np.ndarray, opts: Opts, jac_index: int) -> Pr
     R = None
     if opts.mode == "replica":
         s = sketch_rows(prob.n, opts.gamma)
-        R = qr_r(sketch(DJ, s, opts.seed, jac_index))
-    return Precond(DJ, D, R)
+        if opts.sketch_prec == "f64":
+            B = sketch(DJ, s, opts.seed, jac_index)
+        else:
+            B = lowprec.sketch_lowp(prob, DJ, s, opts.seed, jac_index, opts.sketch_prec, opts.sketch_pieces)
+        R = qr_r(B)
+    DJl = lowprec.round_f32(DJ) if opts.lsqr_prec == "f32" else DJ
+    return Precond(DJ, D, R, DJl)
 
 
 def newton_direction(pc: Precond, DF: np.ndarray, opts: Opts, stats: Stats) -> np.ndarray:
@@ -441,7 +450,8 @@ def newton_direction(pc: Precond, DF: np.ndarray, opts: Opts, stats: Stats) -> n
         stats.lsqr_iters.append(0)
         return du
     R = pc.R
-    res = lsqr(lambda y: pc.DJ @ r_solve(R, y), lambda w: rt_solve(R, pc.DJ.T @ w), -DF, R.shape[0],
+    A = pc.DJ if pc.DJ_lsqr is None else pc.DJ_lsqr
+    res = lsqr(lambda y: A @ r_solve(R, y), lambda w: rt_solve(R, A.T @ w), -DF, R.shape[0],
                opts.lsqr_tol, opts.lsqr_maxit)
     stats.lsqr_iters.append(res.iters)
     return r_solve(R, res.x)

@@ -38,7 +38,7 @@ class rfm_solve_opts(C.Structure):
                 ("lsqr_tol", C.c_double), ("lsqr_max_iter", C.c_int32), ("outer_tol", C.c_double),
                 ("max_outer", C.c_int32), ("m_max", C.c_int32), ("tau_rel", C.c_double),
                 ("row_scale_c", C.c_double), ("gs_iters", C.c_int32), ("sketch_prec", C.c_int32),
-                ("lsqr_prec", C.c_int32), ("verbose", C.c_int32)]
+                ("lsqr_prec", C.c_int32), ("sketch_pieces", C.c_int32), ("verbose", C.c_int32)]
 
 
 class rfm_solve_stats(C.Structure):
@@ -47,7 +47,7 @@ class rfm_solve_stats(C.Structure):
                 ("alphas", C.c_double * RFM_MAX_STEPS), ("resnorms", C.c_double * RFM_MAX_STEPS),
                 ("final_resnorm", C.c_double), ("t_assemble", C.c_double), ("t_sketch", C.c_double),
                 ("t_qr", C.c_double), ("t_lsqr", C.c_double), ("t_linesearch", C.c_double),
-                ("t_total", C.c_double), ("status_detail", C.c_int32)]
+                ("t_total", C.c_double), ("status_detail", C.c_int32), ("lsqr_fp64_fallback", C.c_int32)]
 
     def as_dict(self) -> dict:
         k = min(self.nsteps, RFM_MAX_STEPS)
@@ -55,7 +55,8 @@ class rfm_solve_stats(C.Structure):
                     nsteps=self.nsteps, lsqr_iters=list(self.lsqr_iters[:k]), alphas=list(self.alphas[:k]),
                     resnorms=list(self.resnorms[:k]), final_resnorm=self.final_resnorm,
                     t_assemble=self.t_assemble, t_sketch=self.t_sketch, t_qr=self.t_qr, t_lsqr=self.t_lsqr,
-                    t_linesearch=self.t_linesearch, t_total=self.t_total, status=self.status_detail)
+                    t_linesearch=self.t_linesearch, t_total=self.t_total, status=self.status_detail,
+                    lsqr_fp64_fallback=self.lsqr_fp64_fallback)
 
 
 class rfm_kernel_stat(C.Structure):
@@ -94,14 +95,19 @@ _SIGS = {
     "rfm_get_jacobian_rows": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
     "rfm_jmul": (C.c_int, [_P, _D, _D]),
     "rfm_jtmul": (C.c_int, [_P, _D, _D]),
-    "rfm_stage_sketch": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64, C.c_int32]),
+    "rfm_stage_sketch": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64, C.c_int32, C.c_int32]),
+    "rfm_sketch_table": (C.c_int, [C.c_int32, _D]),
+    "rfm_sketch_operand_slots": (C.c_int64, [_P, C.c_int32]),
+    "rfm_get_sketch_operand": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, _D, C.c_void_p,
+                                         C.c_void_p]),
     "rfm_get_sketch_cols": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
     "rfm_sketch_rows": (C.c_int64, [_P]),
     "rfm_stage_qr": (C.c_int, [_P]),
     "rfm_get_r_cols": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
     "rfm_r_solve": (C.c_int, [_P, _D, _D]),
     "rfm_rt_solve": (C.c_int, [_P, _D, _D]),
-    "rfm_stage_lsqr": (C.c_int, [_P, _D, C.c_double, C.c_int32, _D, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "rfm_stage_lsqr": (C.c_int, [_P, _D, C.c_double, C.c_int32, C.c_int32, _D, C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]),
     "rfm_stage_linesearch": (C.c_int, [_P, _D, _D, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rfm_profile_enable": (C.c_int, [_P, C.c_int32]),
     "rfm_profile_read": (C.c_int32, [_P, C.POINTER(rfm_kernel_stat), C.c_int32]),
@@ -144,6 +150,13 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def sketch_table(prec: int) -> np.ndarray:
+    """The 256 table values of the low-precision sketch (host only)."""
+    out = np.zeros(256)
+    _check(lib().rfm_sketch_table(prec, out.ctypes.data))
+    return out
+
+
 def default_opts(**kw) -> rfm_solve_opts:
     o = rfm_solve_opts()
     lib().rfm_solve_opts_default(C.byref(o))
@@ -162,6 +175,7 @@ class RfmProblem:
         _check(lib().rfm_create(C.byref(h), dim, ncomp, device, stream))
         self.h = h
         self.dim, self.ncomp = dim, ncomp
+        self.J = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -183,6 +197,7 @@ class RfmProblem:
     def set_features(self, J: int, W, b):
         W, b = _f64(W), _f64(b)
         _check(lib().rfm_set_features(self.h, J, W.ctypes.data, b.ctypes.data))
+        self.J = int(J)
 
     def add_points(self, kind, x, owner, neighbor=-1, normal=None, comp=-1, cont_order=1, data=None):
         x = _f64(x)
@@ -270,8 +285,21 @@ class RfmProblem:
         _check(lib().rfm_jtmul(self.h, y.ctypes.data, x.ctypes.data))
         return x
 
-    def stage_sketch(self, gamma: float, seed: int, jac_index: int, prec: int = RFM_PREC_F64):
-        _check(lib().rfm_stage_sketch(self.h, gamma, seed, jac_index, prec))
+    def stage_sketch(self, gamma: float, seed: int, jac_index: int, prec: int = RFM_PREC_F64, pieces: int = 0):
+        _check(lib().rfm_stage_sketch(self.h, gamma, seed, jac_index, prec, pieces))
+
+    def sketch_operand_slots(self, block: int) -> int:
+        return int(lib().rfm_sketch_operand_slots(self.h, block))
+
+    def get_sketch_operand(self, piece: int, block: int, slot0: int, nslots: int):
+        """(values [nslots, J, 32], groups [nslots], scale exponents [nslots, J]) of one piece."""
+        J = self.J
+        out = np.zeros((nslots, J, 32))
+        grp = np.zeros(nslots, np.int32)
+        sc = np.zeros((nslots, J), np.int32)
+        _check(lib().rfm_get_sketch_operand(self.h, piece, block, slot0, nslots, out.ctypes.data,
+                                            grp.ctypes.data, sc.ctypes.data))
+        return out, grp, sc
 
     @property
     def s(self) -> int:
@@ -303,11 +331,11 @@ class RfmProblem:
         _check(lib().rfm_rt_solve(self.h, y.ctypes.data, x.ctypes.data))
         return x
 
-    def stage_lsqr(self, rhs, tol: float, max_iter: int = 500):
+    def stage_lsqr(self, rhs, tol: float, max_iter: int = 500, prec: int = RFM_PREC_F64):
         rhs = _f64(rhs)
         y = np.zeros(self.n)
         it, istop = C.c_int32(), C.c_int32()
-        _check(lib().rfm_stage_lsqr(self.h, rhs.ctypes.data, tol, max_iter, y.ctypes.data, C.byref(it),
+        _check(lib().rfm_stage_lsqr(self.h, rhs.ctypes.data, tol, max_iter, prec, y.ctypes.data, C.byref(it),
                                     C.byref(istop)))
         return y, it.value, istop.value
 

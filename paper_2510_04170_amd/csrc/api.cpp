@@ -1,9 +1,11 @@
 // C-ABI entry points of librfmnewton: problem description, layout building and
 // the stage calls.  Every entry point catches rfm::Error and returns its status.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 
 #include "rfm_internal.h"
 
@@ -250,6 +252,40 @@ static void finalize(Problem& P) {
     }
     P.cb_ptr_h[bk + 1] = (int32_t)P.cb_tile_h.size();
   }
+  // low-precision sketch operand: for each column block the 32-row groups (rows 32 g .. 32 g + 31) that hold a
+  // row touching it, ascending, padded with empty groups to a multiple of 4; per slot the d_J offset of each row's
+  // segment in the block (-1 where the row does not touch it)
+  P.cbs_ptr_h.assign(nblk + 1, 0);
+  P.slot_group_h.clear();
+  std::vector<int64_t> slot_rowoff;
+  for (int bk = 0; bk < nblk; ++bk) {
+    std::map<int64_t, std::array<int64_t, 32>> grp;
+    for (auto& pr : contrib[bk]) {
+      const TileDesc& td = P.tiles_h[pr.first];
+      const int w = td.wA + td.wB;
+      for (int r = 0; r < td.nrows; ++r) {
+        const int64_t gr = (int64_t)td.row0 + r;
+        auto it = grp.find(gr / 32);
+        if (it == grp.end()) {
+          std::array<int64_t, 32> a;
+          a.fill(-1);
+          it = grp.emplace(gr / 32, a).first;
+        }
+        it->second[gr % 32] = td.val_off + (int64_t)r * w + pr.second;
+      }
+    }
+    for (auto& kv : grp) {
+      P.slot_group_h.push_back((int32_t)kv.first);
+      slot_rowoff.insert(slot_rowoff.end(), kv.second.begin(), kv.second.end());
+    }
+    while ((P.slot_group_h.size() - (size_t)P.cbs_ptr_h[bk]) % 4) {
+      P.slot_group_h.push_back(-1);
+      slot_rowoff.insert(slot_rowoff.end(), 32, (int64_t)-1);
+    }
+    P.cbs_ptr_h[bk + 1] = (int32_t)P.slot_group_h.size();
+  }
+  P.nslots = (int64_t)P.slot_group_h.size();
+
   std::vector<int32_t> rowtile(P.m);
   for (int t = 0; t < P.ntiles; ++t)
     for (int r = 0; r < P.tiles_h[t].nrows; ++r) rowtile[P.tiles_h[t].row0 + r] = t;
@@ -299,6 +335,14 @@ static void finalize(Problem& P) {
   RFM_HIP(hipMemcpy(P.d_rows.p, rows.data(), P.m * sizeof(RowDesc), hipMemcpyHostToDevice));
   P.d_tiles.resize(P.ntiles);
   RFM_HIP(hipMemcpy(P.d_tiles.p, P.tiles_h.data(), P.ntiles * sizeof(TileDesc), hipMemcpyHostToDevice));
+  P.d_cbs_ptr.resize(P.cbs_ptr_h.size());
+  RFM_HIP(hipMemcpy(P.d_cbs_ptr.p, P.cbs_ptr_h.data(), P.cbs_ptr_h.size() * 4, hipMemcpyHostToDevice));
+  P.d_slot_group.resize(std::max<int64_t>(1, P.nslots));
+  P.d_slot_rowoff.resize(std::max<int64_t>(32, 32 * P.nslots));
+  if (P.nslots) {
+    RFM_HIP(hipMemcpy(P.d_slot_group.p, P.slot_group_h.data(), P.nslots * 4, hipMemcpyHostToDevice));
+    RFM_HIP(hipMemcpy(P.d_slot_rowoff.p, slot_rowoff.data(), slot_rowoff.size() * 8, hipMemcpyHostToDevice));
+  }
   P.d_cb_ptr.resize(P.cb_ptr_h.size());
   RFM_HIP(hipMemcpy(P.d_cb_ptr.p, P.cb_ptr_h.data(), P.cb_ptr_h.size() * 4, hipMemcpyHostToDevice));
   P.d_cb_tile.resize(std::max<size_t>(1, P.cb_tile_h.size()));
@@ -535,6 +579,30 @@ int64_t rfm_num_rows(const rfm_problem* p) {
   return P.finalized ? P.m : -1;
 }
 
+rfm_status rfm_sketch_table(int32_t prec, double* out) {
+  return guarded([&] {
+    RFM_CHECK(prec == RFM_PREC_BF16 || prec == RFM_PREC_FP8, RFM_EINVAL, "table precision must be BF16 or FP8");
+    RFM_CHECK(out != nullptr, RFM_EINVAL, "NULL argument");
+    sketch_table(prec, out);
+  });
+}
+
+int64_t rfm_sketch_operand_slots(rfm_problem* p, int32_t block) {
+  if (!p) return -1;
+  Problem& P = *reinterpret_cast<Problem*>(p);
+  if (!P.finalized || block < 0 || block >= P.geom.nbox * P.ncomp) return -1;
+  return P.cbs_ptr_h[block + 1] - P.cbs_ptr_h[block];
+}
+
+rfm_status rfm_get_sketch_operand(rfm_problem* p, int32_t piece, int32_t block, int64_t slot0, int64_t nslots,
+                                  double* out, int32_t* groups, int32_t* scale_exp) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(out != nullptr, RFM_EINVAL, "NULL argument");
+    get_sketch_operand(P, piece, block, slot0, nslots, out, groups, scale_exp);
+  });
+}
+
 int64_t rfm_sketch_rows(const rfm_problem* p) {
   if (!p) return -1;
   return reinterpret_cast<const Problem*>(p)->s;
@@ -552,6 +620,8 @@ rfm_status rfm_stage_assemble(rfm_problem* p, const double* u, double row_scale_
     copy_in(P, P.d_u.p, u, P.n);
     launch_assemble(P, P.d_u.p, row_scale_c);
     P.have_J = true;
+    P.have_J32 = false;
+    P.pan_prec = -1;
     P.cur_c = row_scale_c;
     RFM_HIP(hipStreamSynchronize(P.stream));
   });
@@ -618,7 +688,8 @@ rfm_status rfm_jtmul(rfm_problem* p, const double* y, double* x) {
   });
 }
 
-rfm_status rfm_stage_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index, int32_t prec) {
+rfm_status rfm_stage_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index, int32_t prec,
+                            int32_t pieces) {
   return guarded([&] {
     Problem& P = ready(p);
     RFM_CHECK(P.have_J, RFM_EINVAL, "no Jacobian assembled");
@@ -627,8 +698,12 @@ rfm_status rfm_stage_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_
               "sketch precision must be F64, BF16 or FP8");
     int64_t s = (int64_t)std::ceil(gamma * (double)P.n);
     RFM_CHECK(s >= P.n && s < (int64_t)INT32_MAX, RFM_EINVAL, "sketch size out of range");
+    RFM_CHECK(pieces >= 0 && pieces <= kMaxPieces, RFM_EINVAL, "sketch pieces must be 0..16");
     P.s = s;
-    launch_sketch(P, seed, jac_index, prec);
+    if (prec == RFM_PREC_F64)
+      launch_sketch(P, seed, jac_index, prec);
+    else
+      launch_sketch_lowp(P, seed, jac_index, prec, pieces);
     P.have_B = true;
     P.have_R = false;
     RFM_HIP(hipStreamSynchronize(P.stream));
@@ -699,19 +774,21 @@ rfm_status rfm_rt_solve(rfm_problem* p, const double* y, double* x) {
   });
 }
 
-rfm_status rfm_stage_lsqr(rfm_problem* p, const double* rhs, double tol, int32_t max_iter, double* y,
+rfm_status rfm_stage_lsqr(rfm_problem* p, const double* rhs, double tol, int32_t max_iter, int32_t prec, double* y,
                           int32_t* iters, int32_t* istop) {
   return guarded([&] {
     Problem& P = ready(p);
     RFM_CHECK(P.have_J && P.have_R, RFM_EINVAL, "need a Jacobian and an R factor");
     RFM_CHECK(rhs && y, RFM_EINVAL, "NULL argument");
     RFM_CHECK(tol > 0 && max_iter >= 1, RFM_EINVAL, "bad LSQR tolerance or iteration limit");
+    RFM_CHECK(prec == RFM_PREC_F64 || prec == RFM_PREC_F32, RFM_EINVAL, "LSQR precision must be F64 or F32");
+    if (prec == RFM_PREC_F32 && !P.have_J32) launch_cast_f32(P);
     double* drhs = P.d_vec.p + 5 * std::max(P.m, P.n);
     copy_in(P, drhs, rhs, P.m);
     DBuf<double> dy;
     dy.resize(P.n);
     int it = 0, is = 0;
-    lsqr_run(P, drhs, tol, max_iter, dy.p, &it, &is);
+    lsqr_run(P, drhs, tol, max_iter, dy.p, &it, &is, prec);
     copy_out(P, y, dy.p, P.n);
     RFM_HIP(hipStreamSynchronize(P.stream));
     if (iters) *iters = it;

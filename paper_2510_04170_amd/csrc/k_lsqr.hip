@@ -245,8 +245,23 @@ void launch_diff_norm2(Problem& P, int64_t n, const double* a, const double* b, 
 }
 
 // y [n] from min || (D J) R^{-1} y - rhs ||, rhs [m] on the device
-void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, int* iters, int* istop) {
+void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, int* iters, int* istop, int prec) {
   const int64_t m = P.m, n = P.n;
+  RFM_CHECK(prec == RFM_PREC_F64 || (prec == RFM_PREC_F32 && P.have_J32), RFM_EINVAL,
+            "LSQR: the FP32 Jacobian copy has not been formed");
+  const bool f32 = prec == RFM_PREC_F32;
+  auto jmul = [&](const double* x, double* yy, const double* up, double* part) {
+    if (f32)
+      launch_jmul(P, P.d_J32.p, x, yy, up, P.d_lsqr.p, part);
+    else
+      launch_jmul(P, P.d_J.p, x, yy, up, P.d_lsqr.p, part);
+  };
+  auto jtmul = [&](const double* yy, double* x) {
+    if (f32)
+      launch_jtmul(P, P.d_J32.p, yy, x, P.d_lsqr.p);
+    else
+      launch_jtmul(P, P.d_J.p, yy, x, P.d_lsqr.p);
+  };
   const int nbk = (int)((n + trsv_block() - 1) / trsv_block());
   DBuf<double>& W = P.d_ws_lsqr;
   W.resize((size_t)m + 4 * (size_t)n + 3 * 65536);
@@ -268,7 +283,7 @@ void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, i
   hipLaunchKernelGGL(k_copy_norm, dim3(nbm), dim3(kB), 0, P.stream, rhs, ut, m, red_u);
   hipLaunchKernelGGL(k_lsqr_scalar, dim3(1), dim3(kB), 0, P.stream, (int)kInitBeta, st, red_u, nbm);
   // alpha v = A^T u = R^{-T} (D J)^T (u~ / beta)
-  launch_jtmul(P, P.d_J.p, ut, q, st);
+  jtmul(ut, q);
   launch_trsv(P, q, vt, true, nullptr, st, 0, 0, red_v);
   hipLaunchKernelGGL(k_lsqr_scalar, dim3(1), dim3(kB), 0, P.stream, (int)kInitAlpha, st, red_v, nbk);
   hipLaunchKernelGGL(k_lsqr_init_xw, dim3(gn), dim3(kB), 0, P.stream, st, vt, y, w, n);
@@ -279,9 +294,9 @@ void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, i
   int32_t done = 0;
   for (int it = 0; it < maxit && !done; ++it) {
     launch_trsv(P, vt, p, false, nullptr, st, 1, 0, nullptr);                 // p = R^{-1} v
-    launch_jmul(P, P.d_J.p, p, ut, ut, st, red_u);                             // u~ = A v - alpha u
+    jmul(p, ut, ut, red_u);                                                    // u~ = A v - alpha u
     hipLaunchKernelGGL(k_lsqr_scalar, dim3(1), dim3(kB), 0, P.stream, (int)kBeta, st, red_u, P.ntiles);
-    launch_jtmul(P, P.d_J.p, ut, q, st);                                       // q = (D J)^T u
+    jtmul(ut, q);                                                              // q = (D J)^T u
     launch_trsv(P, q, vt, true, vt, st, 0, 1, red_v);                          // v~ = R^{-T} q - beta v
     hipLaunchKernelGGL(k_lsqr_scalar, dim3(1), dim3(kB), 0, P.stream, (int)kAlpha, st, red_v, nbk);
     hipLaunchKernelGGL(k_lsqr_update, dim3(nbn), dim3(kB), 0, P.stream, st, vt, y, w, n, red_x);

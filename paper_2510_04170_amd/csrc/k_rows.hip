@@ -406,7 +406,8 @@ __global__ void __launch_bounds__(256) k_eval_points(RowsCtx C, int64_t npts, co
 
 // y[r] = sum_p J[r,p] x[col(p)] - ucoef * uprev[r];  optional ||y||^2 partial per tile;
 // ucoef = alpha/beta is read from the LSQR state when st != null
-__global__ void __launch_bounds__(256) k_jmul(const TileDesc* __restrict__ tiles, const double* __restrict__ Jv,
+template <typename T>
+__global__ void __launch_bounds__(256) k_jmul(const TileDesc* __restrict__ tiles, const T* __restrict__ Jv,
                                               const double* __restrict__ x, double* __restrict__ y,
                                               const double* __restrict__ uprev, const LsqrState* __restrict__ st,
                                               double* __restrict__ partial) {
@@ -418,11 +419,11 @@ __global__ void __launch_bounds__(256) k_jmul(const TileDesc* __restrict__ tiles
   const double uc = st ? st->alpha * st->inv_beta : 0.0;  // x arrives already scaled by 1/alpha
   double nrm = 0.0;
   for (int rr = wv; rr < td.nrows; rr += kRowsPerBlock) {
-    const double* row = Jv + td.val_off + (int64_t)rr * w;
+    const T* row = Jv + td.val_off + (int64_t)rr * w;
     double acc = 0.0;
     for (int p = lane; p < w; p += kWave) {
       const int col = p < td.wA ? td.colA + p : td.colB + (p - td.wA);
-      acc += row[p] * x[col];
+      acc += (double)row[p] * x[col];
     }
     acc = wave_sum(acc);
     const int64_t r = td.row0 + rr;
@@ -438,8 +439,9 @@ __global__ void __launch_bounds__(256) k_jmul(const TileDesc* __restrict__ tiles
 }
 
 // part[tile slot + p] = sum_{rows} J[r,p] y[r] * yscale
+template <typename T>
 __global__ void __launch_bounds__(256) k_jtmul_tiles(const TileDesc* __restrict__ tiles,
-                                                     const double* __restrict__ Jv, const double* __restrict__ y,
+                                                     const T* __restrict__ Jv, const double* __restrict__ y,
                                                      const LsqrState* __restrict__ st, double* __restrict__ part) {
   if (st && st->done) return;
   __shared__ double ys[kTileRows];
@@ -450,8 +452,8 @@ __global__ void __launch_bounds__(256) k_jtmul_tiles(const TileDesc* __restrict_
   __syncthreads();
   for (int p = threadIdx.x; p < w; p += blockDim.x) {
     double acc = 0.0;
-    const double* col = Jv + td.val_off + p;
-    for (int rr = 0; rr < td.nrows; ++rr) acc += col[(int64_t)rr * w] * ys[rr];
+    const T* col = Jv + td.val_off + p;
+    for (int rr = 0; rr < td.nrows; ++rr) acc += (double)col[(int64_t)rr * w] * ys[rr];
     part[td.part_off + p] = acc;
   }
 }
@@ -571,20 +573,42 @@ void launch_eval_points(Problem& P, const double* u, int64_t npts, const double*
   RFM_HIP(hipGetLastError());
 }
 
-void launch_jmul(Problem& P, const double* J, const double* x, double* y, const double* u_prev,
-                 const LsqrState* st, double* red_partials) {
-  ProfScope ps(P.prof, P.stream, "jmul", 2.0 * P.nvals, 8.0 * ((double)P.nvals + P.n + (u_prev ? 2.0 : 1.0) * P.m));
-  hipLaunchKernelGGL(k_jmul, dim3(P.ntiles), dim3(256), 0, P.stream, P.d_tiles.p, J, x, y, u_prev, st,
+template <typename T>
+static void jmul_impl(Problem& P, const T* J, const double* x, double* y, const double* u_prev, const LsqrState* st,
+                      double* red_partials) {
+  ProfScope ps(P.prof, P.stream, sizeof(T) == 8 ? "jmul" : "jmul_f32", 2.0 * P.nvals,
+               sizeof(T) * (double)P.nvals + 8.0 * (P.n + (u_prev ? 2.0 : 1.0) * P.m));
+  hipLaunchKernelGGL(k_jmul<T>, dim3(P.ntiles), dim3(256), 0, P.stream, P.d_tiles.p, J, x, y, u_prev, st,
                      red_partials);
   RFM_HIP(hipGetLastError());
 }
 
-void launch_jtmul(Problem& P, const double* J, const double* y, double* x, const LsqrState* st) {
-  ProfScope ps(P.prof, P.stream, "jtmul", 2.0 * P.nvals, 8.0 * ((double)P.nvals + P.m + P.n));
-  hipLaunchKernelGGL(k_jtmul_tiles, dim3(P.ntiles), dim3(256), 0, P.stream, P.d_tiles.p, J, y, st, P.d_part.p);
+void launch_jmul(Problem& P, const double* J, const double* x, double* y, const double* u_prev,
+                 const LsqrState* st, double* red_partials) {
+  jmul_impl(P, J, x, y, u_prev, st, red_partials);
+}
+
+void launch_jmul(Problem& P, const float* J, const double* x, double* y, const double* u_prev, const LsqrState* st,
+                 double* red_partials) {
+  jmul_impl(P, J, x, y, u_prev, st, red_partials);
+}
+
+template <typename T>
+static void jtmul_impl(Problem& P, const T* J, const double* y, double* x, const LsqrState* st) {
+  ProfScope ps(P.prof, P.stream, sizeof(T) == 8 ? "jtmul" : "jtmul_f32", 2.0 * P.nvals,
+               sizeof(T) * (double)P.nvals + 8.0 * (P.m + P.n));
+  hipLaunchKernelGGL(k_jtmul_tiles<T>, dim3(P.ntiles), dim3(256), 0, P.stream, P.d_tiles.p, J, y, st, P.d_part.p);
   hipLaunchKernelGGL(k_jtmul_reduce, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, P.stream, P.d_tiles.p,
                      P.d_cb_ptr.p, P.d_cb_tile.p, P.d_cb_off.p, P.J, P.n, P.d_part.p, st, x);
   RFM_HIP(hipGetLastError());
+}
+
+void launch_jtmul(Problem& P, const double* J, const double* y, double* x, const LsqrState* st) {
+  jtmul_impl(P, J, y, x, st);
+}
+
+void launch_jtmul(Problem& P, const float* J, const double* y, double* x, const LsqrState* st) {
+  jtmul_impl(P, J, y, x, st);
 }
 
 void launch_jacobian_rows(Problem& P, int64_t r0, int64_t nrows, double* out) {

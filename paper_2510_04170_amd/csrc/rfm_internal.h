@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -69,6 +70,7 @@ constexpr int kMaxLin = 16;
 constexpr int kMaxPoly = 8;
 constexpr int kMaxRowWidth = 1024;  // widest Jacobian row (16 values per lane of a wave)
 constexpr int kTileRows = 64;       // rows per Jacobian tile
+constexpr int kMaxPieces = 16;      // pieces of D J in a low-precision sketch
 
 struct OpDesc {
   int nlin;
@@ -193,6 +195,9 @@ struct Problem {
   int64_t nvals = 0, npart = 0;
   int ntiles = 0;
   std::vector<int32_t> cb_ptr_h, cb_tile_h, cb_off_h;  // column block -> contributing tiles
+  // low-precision sketch operand: per column block, the 32-row groups of rows touching it
+  std::vector<int32_t> cbs_ptr_h, slot_group_h;
+  int64_t nslots = 0;
 
   // device: geometry, features, rows, tiles
   DBuf<double> d_px, d_pnormal, d_rowdata;
@@ -206,6 +211,15 @@ struct Problem {
   // device: current Jacobian (scaled), residual, scale
   DBuf<double> d_J, d_DF, d_D, d_part;
   bool have_J = false;
+  DBuf<float> d_J32;                      // D J rounded to FP32 for the LSQR products
+  bool have_J32 = false;
+  DBuf<int32_t> d_cbs_ptr, d_slot_group;  // slots of each column block; global group of each slot (-1: padding)
+  DBuf<int64_t> d_slot_rowoff;            // [slot][32]: offset of the row's segment in d_J, or -1
+  DBuf<uint16_t> d_pan16, d_tab16;        // BF16 pieces [piece][slot][J][32]; code table
+  DBuf<uint8_t> d_pan8, d_tab8;          // FP8 pieces [piece][slot][J][32]; code table
+  DBuf<int32_t> d_pexp;                   // exponent E of each (chunk of 4 slots, column)
+  int pan_prec = -1, pan_pieces = 0;
+  bool have_tables = false;
   double cur_c = 100.0;
 
   // device: sketch and preconditioner
@@ -246,6 +260,10 @@ void launch_eval_points(Problem& P, const double* u, int64_t npts, const double*
 void launch_jmul(Problem& P, const double* J, const double* x, double* y, const double* u_prev,
                  const LsqrState* st, double* red_partials);
 void launch_jtmul(Problem& P, const double* J, const double* y, double* x, const LsqrState* st);
+// the same products on the FP32 copy of D J (FP64 vectors and accumulation)
+void launch_jmul(Problem& P, const float* J, const double* x, double* y, const double* u_prev, const LsqrState* st,
+                 double* red_partials);
+void launch_jtmul(Problem& P, const float* J, const double* y, double* x, const LsqrState* st);
 void launch_jacobian_rows(Problem& P, int64_t r0, int64_t nrows, double* out);
 void launch_reduce_sum(Problem& P, const double* partials, int nparts, double* out);
 void launch_residual_from_ab(Problem& P, const double* ab, double* F, double* out_sumsq);
@@ -253,6 +271,14 @@ int reduce_blocks_rows(const Problem& P);
 
 // k_sketch.hip
 void launch_sketch(Problem& P, uint64_t seed, uint64_t jac_index, int prec);
+
+// low-precision forms (k_lowp.hip)
+void sketch_table(int prec, double* out);
+void launch_cast_panels(Problem& P, int prec, int pieces);
+void launch_cast_f32(Problem& P);
+void launch_sketch_lowp(Problem& P, uint64_t seed, uint64_t jac_index, int prec, int pieces);
+void get_sketch_operand(Problem& P, int piece, int blk, int64_t slot0, int64_t nslots, double* out, int32_t* groups,
+                        int32_t* scale_exp);
 
 // k_qr.hip
 void qr_factor(Problem& P);   // in place on d_B, leaves R in d_R (tiled), throws RFM_ESINGULAR
@@ -266,7 +292,9 @@ int trsv_block();
 void check_trsv_error(Problem& P);
 
 // k_lsqr.hip
-void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, int* iters, int* istop);
+// prec: RFM_PREC_F64 multiplies by d_J, RFM_PREC_F32 by d_J32
+void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, int* iters, int* istop,
+              int prec = RFM_PREC_F64);
 
 // vector helpers (k_lsqr.hip)
 void launch_axpy(Problem& P, int64_t n, double a, const double* x, double* y);

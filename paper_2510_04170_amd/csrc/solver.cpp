@@ -34,8 +34,12 @@ struct Driver {
   rfm_solve_stats st{};
   int jac_index = 0;
   double* ab = nullptr;  // line-search products [m][2 + 2K]
+  // copy of D J used by LSQR: the FP32 copy while it works, FP64 from the first
+  // FP32 step that fails (LSQR at its iteration limit, or no decrease in the line
+  // search), for the rest of the solve
+  int lsqr_prec = RFM_PREC_F64;
 
-  Driver(Problem& p, const rfm_solve_opts& opts) : P(p), o(opts) { ab = P.d_lsab.p; }
+  Driver(Problem& p, const rfm_solve_opts& opts) : P(p), o(opts), lsqr_prec(opts.lsqr_prec) { ab = P.d_lsab.p; }
 
   void sync() { RFM_HIP(hipStreamSynchronize(P.stream)); }
 
@@ -44,11 +48,17 @@ struct Driver {
     double t0 = now();
     launch_assemble(P, u, o.row_scale_c);
     P.have_J = true;
+    P.have_J32 = false;
+    P.pan_prec = -1;
     P.cur_c = o.row_scale_c;
+    if (lsqr_prec == RFM_PREC_F32) launch_cast_f32(P);
     sync();
     double t1 = now();
     P.s = (int64_t)std::ceil(o.sketch_factor * (double)P.n);
-    launch_sketch(P, o.sketch_seed, (uint64_t)jac_index, o.sketch_prec);
+    if (o.sketch_prec == RFM_PREC_F64)
+      launch_sketch(P, o.sketch_seed, (uint64_t)jac_index, o.sketch_prec);
+    else
+      launch_sketch_lowp(P, o.sketch_seed, (uint64_t)jac_index, o.sketch_prec, o.sketch_pieces);
     sync();
     double t2 = now();
     P.have_B = true;
@@ -72,19 +82,42 @@ struct Driver {
     return std::sqrt(read_scalar(P, P.d_scal.p));
   }
 
-  // direction d = R^{-1} LSQR(D J R^{-1}, -D F)
+  // direction d = R^{-1} LSQR(D J R^{-1}, -D F); returns LSQR's stop rule
   int direction(const double* F, double* d, double* y) {
     double t0 = now();
     double* rhs = P.d_F1.p + P.m;  // second half of the scratch
     launch_neg_mul(P, P.m, P.d_D.p, F, rhs);
     int it = 0, is = 0;
-    lsqr_run(P, rhs, o.lsqr_tol, o.lsqr_max_iter, y, &it, &is);
+    lsqr_run(P, rhs, o.lsqr_tol, o.lsqr_max_iter, y, &it, &is, lsqr_prec);
     launch_trsv(P, y, d, false, nullptr, nullptr, 0, 0, nullptr);
     check_trsv_error(P);
     st.t_lsqr += now() - t0;
     st.lsqr_iters_total += it;
-    if (st.nsteps < RFM_MAX_STEPS) st.lsqr_iters[st.nsteps] = it;
-    return it;
+    if (st.nsteps < RFM_MAX_STEPS) st.lsqr_iters[st.nsteps] += it;
+    return is;
+  }
+
+  void leave_fp32() {
+    lsqr_prec = RFM_PREC_F64;
+    st.lsqr_fp64_fallback = 1;
+    if (o.verbose) std::fprintf(stderr, "[rfm] FP32 LSQR operator abandoned: continuing with FP64\n");
+  }
+
+  // Newton direction and golden-section step from z (phi0 = ||D F(z)||): returns alpha (0: no decrease)
+  double step(double* z, const double* F, double* d, double* y, double phi0, double* phi1) {
+    if (st.nsteps < RFM_MAX_STEPS) st.lsqr_iters[st.nsteps] = 0;
+    int is = direction(F, d, y);
+    if (lsqr_prec == RFM_PREC_F32 && is == 0) {
+      leave_fp32();
+      is = direction(F, d, y);
+    }
+    double alpha = linesearch(z, d, phi0, o.gs_iters, phi1);
+    if (alpha == 0.0 && lsqr_prec == RFM_PREC_F32) {
+      leave_fp32();
+      direction(F, d, y);
+      alpha = linesearch(z, d, phi0, o.gs_iters, phi1);
+    }
+    return alpha;
   }
 
   double phi(double alpha) {
@@ -161,9 +194,8 @@ struct Driver {
         st.final_resnorm = 0.0;
         return RFM_OK;
       }
-      direction(F, du, y);
       double phi1 = 0.0;
-      const double alpha = linesearch(u, du, phi0, o.gs_iters, &phi1);
+      const double alpha = step(u, F, du, y, phi0, &phi1);
       ++st.outer_iters;
       if (alpha == 0.0) {
         log_step(0.0, phi0);
@@ -198,9 +230,8 @@ struct Driver {
       int i = 0;
       double phiz = F0;
       for (i = 0; i < o.m_max; ++i) {
-        direction(Fz, d, y);
         double phin = 0.0;
-        const double alpha = linesearch(z, d, phiz, o.gs_iters, &phin);
+        const double alpha = step(z, Fz, d, y, phiz, &phin);
         if (alpha == 0.0) {
           stalled = true;
           log_step(0.0, phiz);
@@ -247,8 +278,11 @@ void check_opts(const rfm_solve_opts& o) {
   RFM_CHECK(o.outer_tol >= 0 && o.max_outer >= 1, RFM_EINVAL, "opts: bad outer settings");
   RFM_CHECK(o.m_max >= 1 && o.tau_rel >= 0, RFM_EINVAL, "opts: bad AMIPN settings");
   RFM_CHECK(o.row_scale_c > 0 && o.gs_iters >= 0 && o.gs_iters <= 200, RFM_EINVAL, "opts: bad scale/line search");
-  RFM_CHECK(o.sketch_prec == RFM_PREC_F64, RFM_EINVAL, "opts.sketch_prec: only F64 is available");
-  RFM_CHECK(o.lsqr_prec == RFM_PREC_F64, RFM_EINVAL, "opts.lsqr_prec: only F64 is available");
+  RFM_CHECK(o.sketch_prec == RFM_PREC_F64 || o.sketch_prec == RFM_PREC_BF16 || o.sketch_prec == RFM_PREC_FP8,
+            RFM_EINVAL, "opts.sketch_prec must be F64, BF16 or FP8");
+  RFM_CHECK(o.sketch_pieces >= 0 && o.sketch_pieces <= kMaxPieces, RFM_EINVAL, "opts.sketch_pieces must be 0..16");
+  RFM_CHECK(o.lsqr_prec == RFM_PREC_F64 || o.lsqr_prec == RFM_PREC_F32, RFM_EINVAL,
+            "opts.lsqr_prec must be F64 or F32");
 }
 
 }  // namespace
@@ -275,6 +309,7 @@ void rfm_solve_opts_default(rfm_solve_opts* o) {
   o->gs_iters = 25;
   o->sketch_prec = RFM_PREC_F64;
   o->lsqr_prec = RFM_PREC_F64;
+  o->sketch_pieces = 0;
   o->verbose = 0;
 }
 

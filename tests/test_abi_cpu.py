@@ -57,3 +57,15 @@ def test_create_rejects_bad_arguments_before_device_work():
     assert L.rfm_create(C.byref(h), 0, 1, 0, None) == R.RFM_EINVAL
     assert L.rfm_create(C.byref(h), 2, 9, 0, None) == R.RFM_EINVAL
     assert L.rfm_create(None, 2, 1, 0, None) == R.RFM_EINVAL
+
+
+@pytest.mark.parametrize("prec,fmt", [(2, "bf16"), (3, "fp8")])
+def test_sketch_table_matches_oracle(prec, fmt):
+    """The library's table (host bisection on erfc, its own rounding) equals the
+    oracle's (scipy's quantile function, numpy rounding) bit for bit."""
+    import numpy as np
+    from oracle import lowprec as L
+    t = R.sketch_table(prec)
+    assert np.array_equal(t, L.code_table(fmt))
+    with pytest.raises(R.RfmError):
+        R.sketch_table(0)
