@@ -2,13 +2,19 @@
 """Throughput of the randomized preconditioned Newton solver on one MI355X.
 
 A step is one complete Newton solve from the zero guess: assembly with the row
-scale, Gaussian sketch, QR, preconditioned LSQR, back-transform, line search and
-update, repeated until the stop test fires.  The workload is the steady 3-D
-Gray-Scott system on the unit cube, 4 x 4 x 4 boxes, 300 tanh features per box and
+scale, sketch, QR, preconditioned LSQR, back-transform, line search and update,
+repeated until the stop test fires.  The workload is the steady 3-D Gray-Scott
+system on the unit cube, 4 x 4 x 4 boxes, 300 tanh features per box and
 component (n = 38,400 unknowns), 10^3 collocation points per box and 10 x 10 face
-grids (m = 204,800 rows), sketch s = 2n, LSQR tolerance 1e-10, FP64 throughout.
+grids (m = 204,800 rows), sketch s = 2n, LSQR tolerance 1e-10.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+The timed solver is the mixed-precision form by default: the sketch on the BF16
+matrix cores (error-free fixed-point pieces, FP64 chunk sums), LSQR products on
+an FP32 copy of D J (falling back to FP64 if a step stalls), QR, triangular
+solves, residuals and the update in FP64.  The plain FP64 solver is timed after
+it on the same problem (one solve) for comparison.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sketch-prec bf16|fp8|f64] [--lsqr-prec f32|f64]
 
 prints one JSON line.  The problem description is uploaded before the timed
 region; the coefficient vector lives in device memory.  Kernel times for the
@@ -35,7 +41,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix
+PEAK_FP8_TFLOPS = 5000.0     # MI355X dense FP8 matrix
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
 
 METRIC = "Newton solves/s at relL2<=1e-6; sketch-GEMM TFLOP/s; LSQR SpMV HBM GB/s"
 
@@ -94,6 +103,9 @@ def main() -> None:
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", choices=["ipn", "amipn"], default="ipn")
+    ap.add_argument("--sketch-prec", choices=["bf16", "fp8", "f64"], default="bf16")
+    ap.add_argument("--lsqr-prec", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-rocpd", metavar="DB")
@@ -119,7 +131,9 @@ def main() -> None:
     lp = R.from_description(prob)
     n, m = lp.n, lp.m
     method = R.RFM_AMIPN if a.method == "amipn" else R.RFM_IPN
-    opts = R.default_opts(method=method, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5)
+    opts = R.default_opts(method=method, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5,
+                          sketch_prec=PREC[a.sketch_prec], lsqr_prec=PREC[a.lsqr_prec])
+    opts64 = R.default_opts(method=method, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5)
     dev = torch.device("cuda", 0)
     u = torch.zeros(n, dtype=torch.float64, device=dev)
     print(f"[bench] workload ready: m={m} n={n}; warmup {a.warmup}", file=sys.stderr, flush=True)
@@ -158,6 +172,27 @@ def main() -> None:
     ex = prob.exact(prob.test_x)
     rel = (np.linalg.norm(val - ex, axis=0) / np.linalg.norm(ex, axis=0)).tolist()
 
+    ref64 = None
+    if not a.no_fp64_reference and (a.sketch_prec != "f64" or a.lsqr_prec != "f64"):
+        # the plain FP64 solver on the same problem, for the throughput ratio and the field difference
+        u64 = torch.zeros(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _, st64, rc64 = lp.solve(u64, opts64)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        print(f"[bench] FP64 reference solve: status {rc64}, IT {st64['outer_iters']}, {t3 - t2:.2f} s",
+              file=sys.stderr, flush=True)
+        v64 = lp.eval(u64, prob.test_x, prob.test_owner)
+        rel64 = (np.linalg.norm(v64 - ex, axis=0) / np.linalg.norm(ex, axis=0)).tolist()
+        ref64 = {"solves_per_s": 1.0 / (t3 - t2), "s_per_solve": t3 - t2, "status": rc64,
+                 "outer_iters": st64["outer_iters"], "lsqr_iters": st64["lsqr_iters"], "relL2": rel64,
+                 "field_diff_vs_mixed": float(np.linalg.norm(val - v64) / np.linalg.norm(v64)),
+                 "speedup_of_mixed": (t3 - t2) / (elapsed / a.steps)}
+
+    sk_name = {"f64": "sketch_f64", "bf16": "sketch_bf16", "fp8": "sketch_fp8"}[a.sketch_prec]
+    sk_peak = {"f64": PEAK_FP64_TFLOPS, "bf16": PEAK_BF16_TFLOPS, "fp8": PEAK_FP8_TFLOPS}[a.sketch_prec]
+
     def rate(name, what):
         k = kern.get(name)
         if not k or k["seconds"] <= 0:
@@ -189,6 +224,9 @@ def main() -> None:
                 "per_launch_bytes": dk["bytes"] / dk["launches"],
                 "avg_launch_us": round(1e6 * dk["seconds"] / dk["launches"], 2)}
 
+    dtype = "f64" if (a.sketch_prec, a.lsqr_prec) == ("f64", "f64") else \
+        f"f64 QR/TRSV/residual; {a.sketch_prec} sketch; {a.lsqr_prec} LSQR operator"
+    sk = rate(sk_name, "flops")
     out = {
         "metric": METRIC,
         "value": a.steps / elapsed,
@@ -200,17 +238,23 @@ def main() -> None:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": "gray_scott_3d_4x4x4_J300_q10", "n": n, "m": m, "s": 2 * n, "method": a.method,
-                   "sketch": "gaussian_philox4x64_f64", "lsqr_tol": 1e-10, "outer_tol": 1e-10,
+                   "sketch": ("gaussian_philox4x64_f64" if a.sketch_prec == "f64" else
+                              f"philox4x64_code_table_{a.sketch_prec}_exact_pieces"),
+                   "sketch_prec": a.sketch_prec, "lsqr_prec": a.lsqr_prec, "lsqr_tol": 1e-10, "outer_tol": 1e-10,
                    "row_scale_c": 100.0, "initial_guess": "zero"},
         "relL2": rel,
         "relL2_target_met": bool(max(rel) <= 1e-6),
         "newton": {"outer_iters": stats["outer_iters"], "jac_evals": stats["jac_evals"],
-                   "lsqr_iters": stats["lsqr_iters"], "final_resnorm": stats["final_resnorm"]},
-        "sketch_tflops": rate("sketch_f64", "flops"),
-        "lsqr_spmv_gbs": {"jmul": rate("jmul", "bytes"), "jtmul": rate("jtmul", "bytes")},
+                   "lsqr_iters": stats["lsqr_iters"], "final_resnorm": stats["final_resnorm"],
+                   "status": stats["status"], "lsqr_fp64_fallback": stats["lsqr_fp64_fallback"]},
+        "sketch_tflops": sk,
+        "sketch_frac_of_peak": None if sk is None else sk / sk_peak,
+        "sketch_peak_tflops": sk_peak,
+        "lsqr_spmv_gbs": {k: rate(k, "bytes") for k in ("jmul", "jtmul", "jmul_f32", "jtmul_f32") if k in kern},
+        "fp64_path": ref64,
         "roofline": roof,
         "kernels": kernels,
     }

@@ -112,6 +112,14 @@ rfm_status rfm_add_points(rfm_problem* p, int32_t kind, int64_t npts, const doub
 rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nlin,
                             const rfm_poly_term* nl, int32_t nnl);
 
+/* Replaces the data of point group `group` (numbered in rfm_add_points order;
+ * not a continuity group): data [npts][ncomp] for comp = -1, else [npts].
+ * rfm_set_operator and rfm_set_group_data may be called again after
+ * rfm_finalize -- the layout does not depend on coefficients or data -- so one
+ * problem object (and the projection factor it keeps) can serve a family of
+ * solves that differ only in parameters. */
+rfm_status rfm_set_group_data(rfm_problem* p, int32_t group, const double* data);
+
 /* Finish the description: builds the row and tile layout and uploads it.  Called
  * implicitly by the first compute call; no points may be added afterwards. */
 rfm_status rfm_finalize(rfm_problem* p);
@@ -263,6 +271,81 @@ rfm_status rfm_stage_lsqr(rfm_problem* p, const double* rhs, double tol, int32_t
  * iterations on [0, 1]; returns the step (0 when nothing decreases phi) and phi. */
 rfm_status rfm_stage_linesearch(rfm_problem* p, const double* u, const double* du, int32_t gs_iters,
                                 double* alpha, double* phi);
+
+/* ------------------------------------------------------------------------
+ * Learned initial guess.  A coordinate network maps (PDE parameters, x) to
+ * the solution values; its output at the PDE collocation points is projected
+ * onto the random-feature basis by one sketched least-squares fit, giving the
+ * first Newton iterate.  The plain zero guess stays the fallback and the
+ * FP64 solver decides the final error.  (Not part of the paper's method.)
+ * ---------------------------------------------------------------------- */
+
+typedef struct rfm_mlp rfm_mlp;
+
+/* Network in_dim -> width (tanh) x depth -> out_dim (linear last layer),
+ * Glorot-uniform weights from `seed`, zero biases; device memory on `device`,
+ * work on `stream` (NULL: the null stream).  Parameters are FP32; layer l
+ * holds W_l [dout][din] row-major, then b_l [dout], layers in order. */
+rfm_status rfm_mlp_create(rfm_mlp** out, int32_t in_dim, int32_t width, int32_t depth, int32_t out_dim,
+                          uint64_t seed, int32_t device, void* stream);
+void rfm_mlp_destroy(rfm_mlp* net);
+int64_t rfm_mlp_num_params(const rfm_mlp* net);                 /* -1 for NULL */
+rfm_status rfm_mlp_get_params(rfm_mlp* net, float* out);        /* [num_params], host or device */
+rfm_status rfm_mlp_set_params(rfm_mlp* net, const float* in);   /* also clears the Adam state */
+
+/* RFM_PREC_BF16 (default): layer products on the BF16 matrix cores with FP32
+ * accumulation; RFM_PREC_F32: the same products in FP32 (for checking). */
+rfm_status rfm_mlp_set_precision(rfm_mlp* net, int32_t prec);
+
+/* Y [n][out_dim] = net(X [n][in_dim]) (host or device arrays). */
+rfm_status rfm_mlp_predict(rfm_mlp* net, const float* X, int64_t n, float* Y);
+
+/* Mean-squared error mean((net(X) - Y)^2) over all n * out_dim entries and
+ * its gradient with respect to the parameters (grad [num_params] or NULL). */
+rfm_status rfm_mlp_loss_grad(rfm_mlp* net, const float* X, const float* Y, int64_t n, double* loss, float* grad);
+
+typedef struct {
+  int32_t steps;           /* Adam steps                                          */
+  int32_t batch;           /* samples per step (the whole set, in order, if >= n) */
+  float lr, beta1, beta2, eps;
+  float lr_final;          /* > 0: step size decays geometrically from lr to lr_final over the steps */
+  uint64_t seed;           /* batch draw: row Philox4x64-10((step, i, 2, 0), (seed, 0))[0] mod n */
+} rfm_train_opts;
+
+/* steps 2000, batch 8192, lr 1e-3 (constant: lr_final 0), betas 0.9 / 0.999, eps 1e-8, seed 1 */
+void rfm_train_opts_default(rfm_train_opts* o);
+
+/* Minimises the mean-squared error on (X [n][in_dim], Y [n][out_dim]) with
+ * Adam (Kingma & Ba 2015); loss_log [steps] (or NULL) gets each step's batch
+ * loss before the update. */
+rfm_status rfm_mlp_train(rfm_mlp* net, const float* X, const float* Y, int64_t n, const rfm_train_opts* opts,
+                         double* loss_log);
+
+/* The PDE collocation points of a problem, in row order: their number, and
+ * x [npde][dim] with owner boxes [npde] (either may be NULL). */
+int64_t rfm_num_pde_points(rfm_problem* p);
+rfm_status rfm_get_pde_points(rfm_problem* p, double* x, int32_t* owner);
+
+/* Sketched least-squares fit of field values at the PDE points onto the
+ * feature basis: u_out [n] = argmin || D (Phi u - values) ||, Phi the feature
+ * values at the PDE points (values [npde][ncomp]), D the row scale
+ * c / max |Phi_row| (c = opts->row_scale_c); solved by LSQR (opts->lsqr_tol,
+ * lsqr_max_iter) preconditioned with the R of a Gaussian sketch of D Phi
+ * (opts->sketch_factor, sketch_seed), which is formed on the first call and
+ * kept.  resnorm (or NULL) gets the weighted residual norm. */
+rfm_status rfm_project(rfm_problem* p, const rfm_solve_opts* opts, const double* values, double* u_out,
+                       double* resnorm);
+
+/* Initial coefficients from a network with in_dim = nparam + dim: its inputs
+ * at PDE point x are (params[0..nparam), x), its outputs the ncomp field
+ * values; they are projected by rfm_project.  u_out [n] gets the projected
+ * coefficients if the solver's merit ||D0 F(u)|| is smaller there than at the
+ * zero vector, else zeros (D0: the row scale of the Jacobian at u = 0, the
+ * same for both).  info (or NULL) gets {||D0 F(projected)||, ||D0 F(0)||,
+ * 1 if the projection was kept}.  Leaves the Jacobian at u = 0 as the
+ * problem's current one. */
+rfm_status rfm_warm_start(rfm_problem* p, rfm_mlp* net, const rfm_solve_opts* opts, const double* params,
+                          int32_t nparam, double* u_out, double* info);
 
 /* ------------------------------------------------------------------------
  * Kernel timing.  While enabled, the main kernels are bracketed by HIP events

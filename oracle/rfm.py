@@ -588,3 +588,49 @@ def rel_l2(prob: Problem, u: np.ndarray) -> np.ndarray:
     un = eval_field(prob, u, prob.test_x, prob.test_owner)
     us = prob.exact(prob.test_x)
     return np.linalg.norm(un - us, axis=0) / np.linalg.norm(us, axis=0)
+
+
+# ---------------------------------------------------------------------------
+# projection of field values onto the feature basis (initial-guess fit)
+# ---------------------------------------------------------------------------
+
+def pde_points(prob: Problem):
+    """PDE collocation points in row order: (x [npde, d], owner [npde])."""
+    xs, ows = [], []
+    for g in prob.groups:
+        if g.kind == KIND_PDE:
+            xs.append(g.x)
+            ows.append(np.full(len(g.x), g.owner, np.int32))
+    return np.concatenate(xs), np.concatenate(ows)
+
+
+def feature_matrix_pde(prob: Problem) -> np.ndarray:
+    """Phi [npde * ncomp, n]: row (group, component k, point) holds the features
+    of (owner box, k) at the point -- the identity operator on the PDE points."""
+    rows = []
+    for g in prob.groups:
+        if g.kind != KIND_PDE:
+            continue
+        for k in range(prob.ncomp):
+            blk = np.zeros((len(g.x), prob.n))
+            phi, _, _ = feature_jet(prob, g.owner, k, g.x)
+            blk[:, col_slice(prob, g.owner, k)] = phi
+            rows.append(blk)
+    return np.concatenate(rows)
+
+
+def project(prob: Problem, values: np.ndarray, c: float = 100.0) -> np.ndarray:
+    """argmin_u || D (Phi u - f) || with D = c / max |Phi_row| (values [npde, ncomp])."""
+    Phi = feature_matrix_pde(prob)
+    f = []
+    base = 0
+    for g in prob.groups:
+        if g.kind != KIND_PDE:
+            continue
+        n = len(g.x)
+        for k in range(prob.ncomp):
+            f.append(values[base:base + n, k])
+        base += n
+    f = np.concatenate(f)
+    D = row_scale(Phi, c)
+    return np.linalg.lstsq(D[:, None] * Phi, D * f, rcond=None)[0]

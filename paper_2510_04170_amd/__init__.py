@@ -64,6 +64,11 @@ class rfm_kernel_stat(C.Structure):
                 ("bytes", C.c_double)]
 
 
+class rfm_train_opts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("lr_final", C.c_float), ("seed", C.c_uint64)]
+
+
 class RfmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"rfm status {status}: {msg}")
@@ -83,6 +88,7 @@ _SIGS = {
     "rfm_add_points": (C.c_int, [_P, C.c_int32, C.c_int64, _D, C.c_int32, C.c_int32, _D, C.c_int32, C.c_int32, _D]),
     "rfm_set_operator": (C.c_int, [_P, C.POINTER(rfm_lin_term), C.c_int32, C.POINTER(rfm_poly_term), C.c_int32]),
     "rfm_finalize": (C.c_int, [_P]),
+    "rfm_set_group_data": (C.c_int, [_P, C.c_int32, _D]),
     "rfm_num_unknowns": (C.c_int64, [_P]),
     "rfm_num_rows": (C.c_int64, [_P]),
     "rfm_solve_opts_default": (None, [C.POINTER(rfm_solve_opts)]),
@@ -109,6 +115,21 @@ _SIGS = {
     "rfm_stage_lsqr": (C.c_int, [_P, _D, C.c_double, C.c_int32, C.c_int32, _D, C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32)]),
     "rfm_stage_linesearch": (C.c_int, [_P, _D, _D, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "rfm_mlp_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_int32,
+                                 C.c_void_p]),
+    "rfm_mlp_destroy": (None, [_P]),
+    "rfm_mlp_num_params": (C.c_int64, [_P]),
+    "rfm_mlp_get_params": (C.c_int, [_P, C.c_void_p]),
+    "rfm_mlp_set_params": (C.c_int, [_P, C.c_void_p]),
+    "rfm_mlp_set_precision": (C.c_int, [_P, C.c_int32]),
+    "rfm_mlp_predict": (C.c_int, [_P, C.c_void_p, C.c_int64, C.c_void_p]),
+    "rfm_mlp_loss_grad": (C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.c_void_p]),
+    "rfm_train_opts_default": (None, [C.POINTER(rfm_train_opts)]),
+    "rfm_mlp_train": (C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(rfm_train_opts), C.c_void_p]),
+    "rfm_num_pde_points": (C.c_int64, [_P]),
+    "rfm_get_pde_points": (C.c_int, [_P, _D, C.c_void_p]),
+    "rfm_project": (C.c_int, [_P, C.POINTER(rfm_solve_opts), _D, _D, C.POINTER(C.c_double)]),
+    "rfm_warm_start": (C.c_int, [_P, _P, C.POINTER(rfm_solve_opts), _D, C.c_int32, _D, _D]),
     "rfm_profile_enable": (C.c_int, [_P, C.c_int32]),
     "rfm_profile_read": (C.c_int32, [_P, C.POINTER(rfm_kernel_stat), C.c_int32]),
 }
@@ -155,6 +176,78 @@ def sketch_table(prec: int) -> np.ndarray:
     out = np.zeros(256)
     _check(lib().rfm_sketch_table(prec, out.ctypes.data))
     return out
+
+
+def train_opts(**kw) -> rfm_train_opts:
+    o = rfm_train_opts()
+    lib().rfm_train_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class RfmMLP:
+    """An rfm_mlp handle: in_dim -> width (tanh) x depth -> out_dim."""
+
+    def __init__(self, in_dim: int, width: int, depth: int, out_dim: int, seed: int = 1, device: int = 0,
+                 stream: Optional[int] = None):
+        h = _P()
+        _check(lib().rfm_mlp_create(C.byref(h), in_dim, width, depth, out_dim, seed, device, stream))
+        self.h = h
+        self.in_dim, self.width, self.depth, self.out_dim = in_dim, width, depth, out_dim
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rfm_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(lib().rfm_mlp_num_params(self.h))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.num_params, np.float32)
+        _check(lib().rfm_mlp_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, p):
+        p = _f32(p)
+        assert p.size == self.num_params
+        _check(lib().rfm_mlp_set_params(self.h, p.ctypes.data))
+
+    def set_precision(self, prec: int):
+        _check(lib().rfm_mlp_set_precision(self.h, prec))
+
+    def predict(self, X) -> np.ndarray:
+        X = _f32(X)
+        Y = np.zeros((X.shape[0], self.out_dim), np.float32)
+        _check(lib().rfm_mlp_predict(self.h, X.ctypes.data, X.shape[0], Y.ctypes.data))
+        return Y
+
+    def loss_grad(self, X, Y):
+        X, Y = _f32(X), _f32(Y)
+        loss = C.c_double()
+        g = np.zeros(self.num_params, np.float32)
+        _check(lib().rfm_mlp_loss_grad(self.h, X.ctypes.data, Y.ctypes.data, X.shape[0], C.byref(loss),
+                                       g.ctypes.data))
+        return loss.value, g
+
+    def train(self, X, Y, **kw) -> np.ndarray:
+        X, Y = _f32(X), _f32(Y)
+        o = train_opts(**kw)
+        log = np.zeros(max(o.steps, 1))
+        _check(lib().rfm_mlp_train(self.h, X.ctypes.data, Y.ctypes.data, X.shape[0], C.byref(o), log.ctypes.data))
+        return log[:o.steps]
 
 
 def default_opts(**kw) -> rfm_solve_opts:
@@ -219,6 +312,18 @@ class RfmProblem:
 
     def finalize(self):
         _check(lib().rfm_finalize(self.h))
+
+    def set_group_data(self, group: int, data):
+        data = _f64(data)
+        _check(lib().rfm_set_group_data(self.h, group, data.ctypes.data))
+
+    def update_from(self, desc):
+        """Take the operator and point data of another description with the same
+        partition, features and points (a member of the same parameter family)."""
+        self.set_operator(desc.lin_terms, desc.poly_terms)
+        for i, g in enumerate(desc.groups):
+            if g.data is not None and len(g.x):
+                self.set_group_data(i, g.data)
 
     @property
     def n(self) -> int:
@@ -338,6 +443,33 @@ class RfmProblem:
         _check(lib().rfm_stage_lsqr(self.h, rhs.ctypes.data, tol, max_iter, prec, y.ctypes.data, C.byref(it),
                                     C.byref(istop)))
         return y, it.value, istop.value
+
+    # -- learned initial guess ---------------------------------------------------
+    def pde_points(self):
+        k = int(lib().rfm_num_pde_points(self.h))
+        x = np.zeros((k, self.dim))
+        ow = np.zeros(k, np.int32)
+        _check(lib().rfm_get_pde_points(self.h, x.ctypes.data, ow.ctypes.data))
+        return x, ow
+
+    def project(self, values, opts=None):
+        """Coefficients of the weighted least-squares fit of values [npde, ncomp] (and the residual norm)."""
+        values = _f64(values)
+        opts = opts or default_opts()
+        u = np.zeros(self.n)
+        rn = C.c_double()
+        _check(lib().rfm_project(self.h, C.byref(opts), values.ctypes.data, u.ctypes.data, C.byref(rn)))
+        return u, rn.value
+
+    def warm_start(self, net: "RfmMLP", params, opts=None):
+        """(u0, info): info = (||F(projection)||, ||F(0)||, kept)."""
+        params = _f64(params)
+        opts = opts or default_opts()
+        u = np.zeros(self.n)
+        info = np.zeros(3)
+        _check(lib().rfm_warm_start(self.h, net.h, C.byref(opts), params.ctypes.data, params.size, u.ctypes.data,
+                                    info.ctypes.data))
+        return u, info
 
     def profile_enable(self, on: bool = True):
         _check(lib().rfm_profile_enable(self.h, 1 if on else 0))

@@ -13,24 +13,7 @@ namespace rfm {
 
 static thread_local std::string g_last_error;
 
-static rfm_status fail(rfm_status c, const std::string& m) {
-  g_last_error = m;
-  return c;
-}
-
-template <class F>
-static rfm_status guarded(F&& f) {
-  try {
-    f();
-    return RFM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::bad_alloc&) {
-    return fail(RFM_ENOMEM, "host allocation failed");
-  } catch (const std::exception& e) {
-    return fail(RFM_EDEVICE, e.what());
-  }
-}
+void set_last_error(const std::string& m) { g_last_error = m; }
 
 bool is_device_ptr(const void* p) {
   if (!p) return false;
@@ -419,6 +402,7 @@ void rfm_destroy(rfm_problem* p) {
   Problem* P = reinterpret_cast<Problem*>(p);
   (void)hipSetDevice(P->device);
   (void)hipStreamSynchronize(P->stream);
+  if (P->proj) rfm_destroy(P->proj);
   delete P;
 }
 
@@ -526,7 +510,6 @@ rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nli
                             int32_t nnl) {
   return guarded([&] {
     Problem& P = get(p);
-    RFM_CHECK(!P.finalized, RFM_EINVAL, "rfm_set_operator: problem already finalized");
     RFM_CHECK(nlin >= 0 && nlin <= kMaxLin && nnl >= 0 && nnl <= kMaxPoly, RFM_EINVAL,
               "rfm_set_operator: at most 16 linear and 8 polynomial terms");
     RFM_CHECK((nlin == 0 || lin) && (nnl == 0 || nl), RFM_EINVAL, "rfm_set_operator: NULL terms");
@@ -560,6 +543,31 @@ rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nli
     }
     P.op = op;
     P.have_operator = true;
+  });
+}
+
+rfm_status rfm_set_group_data(rfm_problem* p, int32_t group, const double* data) {
+  return guarded([&] {
+    Problem& P = get(p);
+    RFM_CHECK(group >= 0 && group < (int32_t)P.groups.size(), RFM_EINVAL, "rfm_set_group_data: no such group");
+    const GroupH& g = P.groups[group];
+    RFM_CHECK(g.kind != RFM_CONTINUITY, RFM_EINVAL, "rfm_set_group_data: continuity rows take no data");
+    RFM_CHECK(data != nullptr || g.npts == 0, RFM_EINVAL, "rfm_set_group_data: data is NULL");
+    const int nsel = g.comp < 0 ? P.ncomp : 1;
+    int64_t off = 0;
+    for (int32_t k = 0; k < group; ++k) {
+      const GroupH& h = P.groups[k];
+      off += h.npts * (h.comp < 0 ? P.ncomp : 1) * h.cont_order;
+    }
+    const std::vector<double> dh = host_doubles(data, (size_t)g.npts * nsel);
+    RFM_CHECK(all_finite(dh), RFM_ENUMERIC, "rfm_set_group_data: non-finite data");
+    for (int k = 0; k < nsel; ++k)
+      for (int64_t q = 0; q < g.npts; ++q) P.rowdata[off + k * g.npts + q] = dh[(size_t)q * nsel + k];
+    if (P.finalized && g.npts) {
+      RFM_HIP(hipMemcpyAsync(P.d_rowdata.p + off, P.rowdata.data() + off, (size_t)nsel * g.npts * sizeof(double),
+                             hipMemcpyHostToDevice, P.stream));
+      RFM_HIP(hipStreamSynchronize(P.stream));
+    }
   });
 }
 

@@ -209,11 +209,12 @@ __global__ void __launch_bounds__(256) k_sketch_fixed(const int32_t* __restrict_
     __syncthreads();  // previous chunk's reads of sS are done (and tab is in place)
     gen_chunk<TC, LDW>(sS, tab, slot_group, slot0, i0, seed, jac);
     __syncthreads();
-    int ex[kCT];
+    int ex[kCT], colc[kCT];
 #pragma unroll
     for (int tc = 0; tc < kCT; ++tc) {
       const int col = colw + 16 * tc + c16;
-      ex[tc] = col < J ? pexp[(slot0 / 4) * J + col] : 0;
+      colc[tc] = col < J ? col : J - 1;
+      ex[tc] = pexp[(slot0 / 4) * J + colc[tc]];
     }
     if constexpr (!FP8) {
       for (int p = 0; p < npc; ++p) {
@@ -222,25 +223,32 @@ __global__ void __launch_bounds__(256) k_sketch_fixed(const int32_t* __restrict_
         for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
           for (int tc = 0; tc < kCT; ++tc) a32[rt][tc] = v4f{0, 0, 0, 0};
+        // B fragments two k-steps at a time (ten independent loads in flight); a column past J reads
+        // column J - 1 instead, which only feeds output columns that are never stored
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          v8bf a[kRT], b[kCT];
+        for (int kh = 0; kh < 4; kh += 2) {
+          uint4 braw[2][kCT];
 #pragma unroll
-          for (int rt = 0; rt < kRT; ++rt)
-            a[rt] = *reinterpret_cast<const v8bf*>(&sS[wr * 64 + rt * 16 + c16][32 * ks + 8 * q]);
+          for (int k2 = 0; k2 < 2; ++k2)
 #pragma unroll
-          for (int tc = 0; tc < kCT; ++tc) {
-            const int col = colw + 16 * tc + c16;
-            if (col < J)
-              b[tc] = *reinterpret_cast<const v8bf*>(pan + p * piece_stride + ((slot0 + ks) * J + col) * 32 + 8 * q);
-            else
-              b[tc] = v8bf{};
-          }
+            for (int tc = 0; tc < kCT; ++tc)
+              braw[k2][tc] = *reinterpret_cast<const uint4*>(pan + p * piece_stride +
+                                                             ((slot0 + kh + k2) * J + colc[tc]) * 32 + 8 * q);
 #pragma unroll
-          for (int tc = 0; tc < kCT; ++tc)
+          for (int k2 = 0; k2 < 2; ++k2) {
+            v8bf a[kRT];
 #pragma unroll
             for (int rt = 0; rt < kRT; ++rt)
-              a32[rt][tc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b[tc], a32[rt][tc], 0, 0, 0);
+              a[rt] = __builtin_bit_cast(
+                  v8bf, *reinterpret_cast<const uint4*>(&sS[wr * 64 + rt * 16 + c16][32 * (kh + k2) + 8 * q]));
+#pragma unroll
+            for (int tc = 0; tc < kCT; ++tc) {
+              const v8bf b = __builtin_bit_cast(v8bf, braw[k2][tc]);
+#pragma unroll
+              for (int rt = 0; rt < kRT; ++rt)
+                a32[rt][tc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, a32[rt][tc], 0, 0, 0);
+            }
+          }
         }
 #pragma unroll
         for (int tc = 0; tc < kCT; ++tc) {
@@ -272,16 +280,11 @@ __global__ void __launch_bounds__(256) k_sketch_fixed(const int32_t* __restrict_
           v8i b[kCT];
 #pragma unroll
           for (int tc = 0; tc < kCT; ++tc) {
-            const int col = colw + 16 * tc + c16;
-            if (col < J) {
-              const TC* base = pan + p * piece_stride;
-              const uint4 lo = *reinterpret_cast<const uint4*>(base + ((slot0 + q / 2) * J + col) * 32 + 16 * (q % 2));
-              const uint4 hi =
-                  *reinterpret_cast<const uint4*>(base + ((slot0 + 2 + q / 2) * J + col) * 32 + 16 * (q % 2));
-              b[tc] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-            } else {
-              b[tc] = v8i{0, 0, 0, 0, 0, 0, 0, 0};
-            }
+            const TC* base = pan + p * piece_stride;
+            const uint4 lo = *reinterpret_cast<const uint4*>(base + ((slot0 + q / 2) * J + colc[tc]) * 32 + 16 * (q % 2));
+            const uint4 hi =
+                *reinterpret_cast<const uint4*>(base + ((slot0 + 2 + q / 2) * J + colc[tc]) * 32 + 16 * (q % 2));
+            b[tc] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
           }
 #pragma unroll
           for (int tc = 0; tc < kCT; ++tc)

@@ -196,7 +196,7 @@ __global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, 
 __global__ void k_neg_mul(int64_t n, const double* __restrict__ D, const double* __restrict__ F,
                           double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (i < n) out[i] = -(D[i] * F[i]);
+  if (i < n) out[i] = D ? -(D[i] * F[i]) : -F[i];
 }
 
 // partial sum of (D (a - b))^2, D optional

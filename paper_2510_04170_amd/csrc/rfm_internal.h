@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -35,6 +36,27 @@ struct Error : std::runtime_error {
   do {                                                \
     if (!(cond)) throw ::rfm::Error((code), (msg));   \
   } while (0)
+
+// error text of the last failed call on this thread (rfm_last_error)
+void set_last_error(const std::string& m);
+
+// runs f, mapping exceptions to status codes for the C ABI
+template <class F>
+rfm_status guarded(F&& f) {
+  try {
+    f();
+    return RFM_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return (rfm_status)e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return RFM_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return RFM_EDEVICE;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // device buffer (owned by the problem object)
@@ -220,6 +242,11 @@ struct Problem {
   DBuf<int32_t> d_pexp;                   // exponent E of each (chunk of 4 slots, column)
   int pan_prec = -1, pan_pieces = 0;
   bool have_tables = false;
+
+  // projection onto the feature basis at the PDE points (identity operator), R kept between calls
+  rfm_problem* proj = nullptr;
+  double proj_gamma = 0.0, proj_c = 0.0;
+  uint64_t proj_seed = 0;
   double cur_c = 100.0;
 
   // device: sketch and preconditioner
@@ -272,6 +299,9 @@ int reduce_blocks_rows(const Problem& P);
 // k_sketch.hip
 void launch_sketch(Problem& P, uint64_t seed, uint64_t jac_index, int prec);
 
+// network shape check (mlp.hip): throws RFM_EINVAL unless in_dim / out_dim match
+void mlp_check_shape(rfm_mlp* net, int in_dim, int out_dim);
+
 // low-precision forms (k_lowp.hip)
 void sketch_table(int prec, double* out);
 void launch_cast_panels(Problem& P, int prec, int pieces);
@@ -299,7 +329,7 @@ void lsqr_run(Problem& P, const double* rhs, double tol, int maxit, double* y, i
 // vector helpers (k_lsqr.hip)
 void launch_axpy(Problem& P, int64_t n, double a, const double* x, double* y);
 void launch_scale_copy(Problem& P, int64_t n, double a, const double* x, double* y);
-void launch_neg_mul(Problem& P, int64_t n, const double* D, const double* F, double* out);  // out = -D*F
+void launch_neg_mul(Problem& P, int64_t n, const double* D, const double* F, double* out);  // out = -D*F (D may be null)
 void launch_diff_norm2(Problem& P, int64_t n, const double* a, const double* b, const double* D, double* out);
 
 // C-ABI bodies (solver.cpp)
@@ -310,7 +340,8 @@ rfm_status api_linesearch(Problem& P, const double* u, const double* du, int gs_
 
 // utilities
 bool is_device_ptr(const void* p);
-void copy_in(Problem& P, double* dst, const double* src, size_t count);    // src host or device
+void copy_in(Problem& P, double* dst, const double* src, size_t count);
+double read_scalar(Problem& P, const double* d);  // one device double, after the stream drains    // src host or device
 void copy_out(Problem& P, double* dst, const double* src, size_t count);   // dst host or device
 
 }  // namespace rfm

@@ -15,14 +15,14 @@
 
 namespace rfm {
 
-namespace {
-
 double read_scalar(Problem& P, const double* d) {
   double h = 0.0;
   RFM_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, P.stream));
   RFM_HIP(hipStreamSynchronize(P.stream));
   return h;
 }
+
+namespace {
 
 double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();

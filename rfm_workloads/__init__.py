@@ -389,6 +389,36 @@ def config4_nohole(nsub=(4, 4, 8), J=400, q=12, seed=0, R=1.0, test_per_dim=None
                   seed=seed, dirichlet_faces=faces, test_per_dim=test_per_dim)
 
 
+# Gray-Scott parameter family for the learned initial guess: F, k of the
+# reaction terms and the amplitude a of u* = 1 - a sin(pi x) sin(pi y) sin(pi z)
+GS_FAMILY = {"F": (0.02, 0.06), "k": (0.04, 0.07), "amp": (0.3, 0.7)}
+
+
+def gray_scott_family_draw(seed: int) -> tuple:
+    """One (F, k, amp) draw, uniform on the family's ranges."""
+    rng = np.random.default_rng(seed)
+    return tuple(float(rng.uniform(*GS_FAMILY[key])) for key in ("F", "k", "amp"))
+
+
+def gray_scott_member(F: float, k: float, amp: float, **kw) -> Problem:
+    """A member of the family: the Gray-Scott workload with these parameters;
+    partition, features and points depend only on kw (not on F, k, amp)."""
+    return config2(F=F, k=k, amp=amp, **kw)
+
+
+def mlp_params(in_dim: int, width: int, depth: int, out_dim: int, seed: int) -> np.ndarray:
+    """Seeded network parameters (Glorot-uniform weights, small random biases),
+    packed per layer as W [dout][din] row-major then b [dout]; float32."""
+    rng = np.random.default_rng(seed)
+    d = [in_dim] + [width] * depth + [out_dim]
+    parts = []
+    for i, o in zip(d[:-1], d[1:]):
+        lim = np.sqrt(6.0 / (i + o))
+        parts.append(rng.uniform(-lim, lim, size=o * i))
+        parts.append(rng.uniform(-0.1, 0.1, size=o))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def make_config(i: int, **kw) -> Problem:
     return [config1, config2, config3_nohole, config4_nohole][i](**kw)
 
