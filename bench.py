@@ -46,6 +46,11 @@ PEAK_FP8_TFLOPS = 5000.0     # MI355X dense FP8 matrix
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
 
+# HBM bytes per launch of the dominant kernel on this workload, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, scaled by 2.0 and 1.0: what the same counters read
+# for an elementwise copy of 1 GiB); valid while the kernel is unchanged
+TRAFFIC_BYTES = {"qr_gemm_nn": (14847208.0 * 2.0 + 9626800.5 * 1.0) * 1024.0}
+
 METRIC = "Newton solves/s at relL2<=1e-6; sketch-GEMM TFLOP/s; LSQR SpMV HBM GB/s"
 
 
@@ -82,7 +87,7 @@ def cpu_baseline(quick: bool) -> dict:
         threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    nsub, J, q = ((2, 1, 1), 30, 4) if quick else ((2, 2, 2), 60, 5)
+    nsub, J, q = ((2, 1, 1), 30, 4) if quick else ((2, 2, 2), 110, 6)
     prob = W.config2(nsub=nsub, J=J, q=q, test_per_dim=2)
     t0 = time.perf_counter()
     u, st = O.ipn(prob, opts=O.Opts(gamma=2.0, lsqr_tol=1e-10))
@@ -106,6 +111,7 @@ def main() -> None:
     ap.add_argument("--sketch-prec", choices=["bf16", "fp8", "f64"], default="bf16")
     ap.add_argument("--lsqr-prec", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--no-warm-start-study", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-rocpd", metavar="DB")
@@ -214,7 +220,8 @@ def main() -> None:
     if mfma_bound:
         achieved = dk["flops"] / dk["seconds"] / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": TRAFFIC_BYTES.get(dom),
+                "per_launch_alg_bytes": dk["bytes"] / dk["launches"],
                 "per_launch_flops": dk["flops"] / dk["launches"],
                 "avg_launch_us": round(1e6 * dk["seconds"] / dk["launches"], 2)}
     else:
@@ -258,6 +265,17 @@ def main() -> None:
         "roofline": roof,
         "kernels": kernels,
     }
+    if not a.no_warm_start_study:
+        # learned initial guess on a small member family of the same system (the full-size
+        # family would need hundreds of full-size training solves): Newton steps and time
+        # against the zero guess on held-out members, the FP64 solver deciding the answer
+        from paper_2510_04170_amd import warmstart as WS
+        print("[bench] warm-start study ...", file=sys.stderr, flush=True)
+        ws = WS.run(n_train=48, n_test=4)
+        out["warm_start"] = {"family": ws["family"], "network": ws["network"], "seconds": ws["seconds"],
+                             "mean": ws["mean"],
+                             "max_field_diff_vs_zero_guess": max(r["field_diff"] for r in ws["per_draw"]),
+                             "kept": [r["warm"]["kept"] for r in ws["per_draw"]]}
     if rank == 0 and not a.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.quick_cpu_baseline)
