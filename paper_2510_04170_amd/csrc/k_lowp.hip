@@ -174,7 +174,7 @@ __device__ __forceinline__ void gen_chunk(TS (*sS)[LDW], const TS* __restrict__ 
 
 // B[:, block columns] for one 128-row slab and up to 160 columns of one column block
 template <bool FP8>
-__global__ void __launch_bounds__(256) k_sketch_fixed(const int32_t* __restrict__ cbs_ptr,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_sketch_fixed(const int32_t* __restrict__ cbs_ptr,
                                                       const int32_t* __restrict__ slot_group,
                                                       const void* __restrict__ pan_, const int32_t* __restrict__ pexp,
                                                       int64_t piece_stride, int npc, int J, int64_t s,
@@ -223,32 +223,40 @@ __global__ void __launch_bounds__(256) k_sketch_fixed(const int32_t* __restrict_
         for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
           for (int tc = 0; tc < kCT; ++tc) a32[rt][tc] = v4f{0, 0, 0, 0};
-        // B fragments two k-steps at a time (ten independent loads in flight); a column past J reads
-        // column J - 1 instead, which only feeds output columns that are never stored
+        // B fragments one k-step ahead of the products that use them (five loads in flight while
+        // twenty products run); a column past J reads column J - 1 instead, which only feeds output
+        // columns that are never stored
+        const TC* pb = pan + p * piece_stride + 8 * q;
+        // re-read the A fragments from LDS in every piece (keeps 64 registers free for loads in flight
+        // instead of holding the piece-invariant fragments across the loop)
+        int aoff = (wr * 64 + c16) * LDW + 8 * q;
+        asm volatile("" : "+v"(aoff));
+        uint4 bn[kCT];
 #pragma unroll
-        for (int kh = 0; kh < 4; kh += 2) {
-          uint4 braw[2][kCT];
+        for (int tc = 0; tc < kCT; ++tc) bn[tc] = *reinterpret_cast<const uint4*>(pb + (slot0 * J + colc[tc]) * 32);
 #pragma unroll
-          for (int k2 = 0; k2 < 2; ++k2)
+        for (int ks = 0; ks < 4; ++ks) {
+          uint4 bc[kCT];
+#pragma unroll
+          for (int tc = 0; tc < kCT; ++tc) bc[tc] = bn[tc];
+          if (ks < 3) {
 #pragma unroll
             for (int tc = 0; tc < kCT; ++tc)
-              braw[k2][tc] = *reinterpret_cast<const uint4*>(pan + p * piece_stride +
-                                                             ((slot0 + kh + k2) * J + colc[tc]) * 32 + 8 * q);
+              bn[tc] = *reinterpret_cast<const uint4*>(pb + ((slot0 + ks + 1) * J + colc[tc]) * 32);
+          }
+          __builtin_amdgcn_sched_barrier(0);  // keep the next k-step's loads ahead of these products
+          v8bf a[kRT];
 #pragma unroll
-          for (int k2 = 0; k2 < 2; ++k2) {
-            v8bf a[kRT];
+          for (int rt = 0; rt < kRT; ++rt)
+            a[rt] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(&sS[0][0] + aoff + rt * 16 * LDW + 32 * ks));
+#pragma unroll
+          for (int tc = 0; tc < kCT; ++tc) {
+            const v8bf b = __builtin_bit_cast(v8bf, bc[tc]);
 #pragma unroll
             for (int rt = 0; rt < kRT; ++rt)
-              a[rt] = __builtin_bit_cast(
-                  v8bf, *reinterpret_cast<const uint4*>(&sS[wr * 64 + rt * 16 + c16][32 * (kh + k2) + 8 * q]));
-#pragma unroll
-            for (int tc = 0; tc < kCT; ++tc) {
-              const v8bf b = __builtin_bit_cast(v8bf, braw[k2][tc]);
-#pragma unroll
-              for (int rt = 0; rt < kRT; ++rt)
-                a32[rt][tc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, a32[rt][tc], 0, 0, 0);
-            }
+              a32[rt][tc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b, a32[rt][tc], 0, 0, 0);
           }
+          __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int tc = 0; tc < kCT; ++tc) {
@@ -286,12 +294,14 @@ __global__ void __launch_bounds__(256) k_sketch_fixed(const int32_t* __restrict_
                 *reinterpret_cast<const uint4*>(base + ((slot0 + 2 + q / 2) * J + colc[tc]) * 32 + 16 * (q % 2));
             b[tc] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
           }
+          __builtin_amdgcn_sched_barrier(0);  // all ten loads of this piece in flight before its products
 #pragma unroll
           for (int tc = 0; tc < kCT; ++tc)
 #pragma unroll
             for (int rt = 0; rt < kRT; ++rt)
               a32[rt][tc] =
                   __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[rt], b[tc], a32[rt][tc], 0, 0, 0, 127, 0, scb);
+          __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int tc = 0; tc < kCT; ++tc) {
