@@ -419,6 +419,122 @@ def mlp_params(in_dim: int, width: int, depth: int, out_dim: int, seed: int) -> 
     return np.concatenate(parts).astype(np.float32)
 
 
+# ----------------------------------------------------------------------------
+# geometry with holes
+# ----------------------------------------------------------------------------
+
+def fibonacci_sphere(c, r, npts: int) -> np.ndarray:
+    """npts points spread on the sphere |x - c| = r along the golden-angle spiral."""
+    k = np.arange(npts) + 0.5
+    z = 1.0 - 2.0 * k / npts
+    rho = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * np.arange(npts)
+    return np.asarray(c, float)[None, :] + r * np.stack([rho * np.cos(phi), rho * np.sin(phi), z], axis=1)
+
+
+def box_of(x: np.ndarray, lo, hi, nsub) -> np.ndarray:
+    """Index of the box containing each point (axis 0 fastest; the upper face belongs to the last box)."""
+    lo, hi, nsub = np.asarray(lo, float), np.asarray(hi, float), np.asarray(nsub, np.int64)
+    idx = np.floor((x - lo) / (hi - lo) * nsub).astype(np.int64)
+    idx = np.clip(idx, 0, nsub - 1)
+    e = np.zeros(len(x), np.int64)
+    for a in range(len(nsub) - 1, -1, -1):
+        e = e * nsub[a] + idx[:, a]
+    return e
+
+
+def draw_spheres(n: int, seed: int, lo, hi, nsub, q: int):
+    """Centres ~ U(0.15, 0.85)^3, radii ~ U(0.05, 0.12); a draw is rejected when two spheres come
+    within 0.02 of each other or a box would keep no collocation point."""
+    rng = np.random.default_rng(seed)
+    lo, hi, nsub = np.asarray(lo, float), np.asarray(hi, float), np.asarray(nsub, np.int64)
+    while True:
+        c = rng.uniform(0.15, 0.85, size=(n, 3))
+        r = rng.uniform(0.05, 0.12, size=n)
+        ok = all(np.linalg.norm(c[i] - c[j]) >= r[i] + r[j] + 0.02 for i in range(n) for j in range(i + 1, n))
+        if ok:
+            for e in range(int(np.prod(nsub))):
+                blo, bhi = box_bounds(e, lo, hi, nsub)
+                pts = box_grid(blo, bhi, [q] * 3)
+                if not np.any(np.all(np.linalg.norm(pts[:, None, :] - c[None], axis=2) > r[None], axis=1)):
+                    ok = False
+                    break
+        if ok:
+            return c, r
+
+
+def config3(nsub=(8, 8, 8), J=250, q=8, seed=0, R=1.0, holes=4, hole_seed=0, h=None,
+            test_per_dim=None) -> Problem:
+    """3-D nonlinear Helmholtz on the unit cube minus seeded spherical holes, Dirichlet u* on the
+    outer faces and on the sphere surfaces (Fibonacci points, ceil(64 * 4 pi r^2 / h^2) per sphere)."""
+    kap = 8.0
+    lin = [(0, 0, -1.0, D_LAPLACE), (0, 0, -kap * kap, D_ID)]
+    poly = [(0, 1.0, (3,))]
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    c, r = draw_spheres(holes, hole_seed, lo, hi, nsub, q)
+    h = h if h is not None else 1.0 / 8.0
+
+    def inside(p):
+        return np.all(np.linalg.norm(p[:, None, :] - c[None], axis=2) > r[None], axis=1)
+
+    def spheres(lo_, hi_, nsub_, jet_fn):
+        out = []
+        for ci, ri in zip(c, r):
+            x = fibonacci_sphere(ci, ri, int(np.ceil(64 * 4 * np.pi * ri * ri / (h * h))))
+            owner = box_of(x, lo_, hi_, nsub_)
+            for e in np.unique(owner):
+                pts = x[owner == e]
+                out.append(PointGroup(KIND_DIRICHLET, pts, int(e), comp=-1, data=jet_fn(pts)[0]))
+        return out
+
+    return _build("helmholtz_3d_holes", 3, 1, lo, hi, nsub, J, R, q, q, jet_config3, lin, poly, seed=seed,
+                  test_per_dim=test_per_dim, inside=inside, extra_groups=spheres,
+                  params=dict(centres=c, radii=r))
+
+
+AC_HOLE_R = 0.15
+
+
+def ac_hole_centre(t):
+    t = np.asarray(t, float)
+    return np.stack([0.5 + 0.25 * np.cos(2 * np.pi * t), 0.5 + 0.25 * np.sin(2 * np.pi * t)], axis=-1)
+
+
+def config4(nsub=(4, 4, 8), J=400, q=12, seed=0, R=1.0, n_t=96, n_theta=48, test_per_dim=None) -> Problem:
+    """Space-time Allen-Cahn on [0,1]^2 x [0,1] minus a moving disc of radius 0.15 centred at
+    (0.5 + 0.25 cos 2 pi t, 0.5 + 0.25 sin 2 pi t): Dirichlet u* on the x, y faces and at t = 0,
+    Neumann n . grad u* on the hole (n pointing out of the domain, into the hole), n_t cell-centred
+    t levels x n_theta angles."""
+    lin = [(0, 0, 1.0, D_X2), (0, 0, -0.01, D_LAPLACE_SPACE), (0, 0, -1.0, D_ID)]
+    poly = [(0, 1.0, (3,))]
+    faces = [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0)]
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+
+    def inside(p):
+        return np.linalg.norm(p[:, :2] - ac_hole_centre(p[:, 2]), axis=1) > AC_HOLE_R
+
+    def hole(lo_, hi_, nsub_, jet_fn):
+        t = (np.arange(n_t) + 0.5) / n_t
+        th = 2 * np.pi * np.arange(n_theta) / n_theta
+        tt, aa = np.meshgrid(t, th, indexing="ij")
+        tt, aa = tt.ravel(), aa.ravel()
+        cen = ac_hole_centre(tt)
+        dirs = np.stack([np.cos(aa), np.sin(aa)], axis=1)
+        x = np.concatenate([cen + AC_HOLE_R * dirs, tt[:, None]], axis=1)
+        nrm = np.concatenate([-dirs, np.zeros((len(tt), 1))], axis=1)
+        owner = box_of(x, lo_, hi_, nsub_)
+        out = []
+        for e in np.unique(owner):
+            sel = owner == e
+            pts, nn = x[sel], nrm[sel]
+            g = np.einsum("pcd,pd->pc", jet_fn(pts)[1], nn)
+            out.append(PointGroup(KIND_NEUMANN, pts, int(e), normal=nn, comp=-1, data=g))
+        return out
+
+    return _build("allen_cahn_st_hole", 3, 1, lo, hi, nsub, J, R, q, q, jet_config4, lin, poly, seed=seed,
+                  dirichlet_faces=faces, test_per_dim=test_per_dim, inside=inside, extra_groups=hole)
+
+
 def make_config(i: int, **kw) -> Problem:
     return [config1, config2, config3_nohole, config4_nohole][i](**kw)
 
@@ -430,8 +546,8 @@ def jet_of(problem: Problem):
         return jet_config1
     if name == "gray_scott_3d":
         return lambda x: jet_config2(x, problem.params.get("amp", 0.5))
-    if name == "helmholtz_3d":
+    if name in ("helmholtz_3d", "helmholtz_3d_holes"):
         return jet_config3
-    if name == "allen_cahn_st":
+    if name in ("allen_cahn_st", "allen_cahn_st_hole"):
         return jet_config4
     raise KeyError(name)

@@ -423,3 +423,62 @@ def test_operator_signs_by_manufactured_solution(cfg, kw, tol):
     u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
     assert st.status == "ok"
     assert np.all(O.rel_l2(prob, u) < tol)
+
+
+# ---------------------------------------------------------------------------
+# geometry with holes
+# ---------------------------------------------------------------------------
+
+def test_sphere_holes_geometry():
+    p = W.config3(nsub=(2, 2, 2), J=20, q=6, test_per_dim=2)
+    c, r = p.params["centres"], p.params["radii"]
+    for i in range(len(r)):
+        assert 0.15 <= c[i].min() and c[i].max() <= 0.85 and 0.05 <= r[i] <= 0.12
+        for j in range(i + 1, len(r)):
+            assert np.linalg.norm(c[i] - c[j]) >= r[i] + r[j] + 0.02
+    for g in p.groups:
+        d = np.linalg.norm(g.x[:, None, :] - c[None], axis=2) - r[None]
+        if g.kind == W.KIND_DIRICHLET and np.all(np.abs(d).min(axis=1) < 1e-12):
+            # sphere surface points: on one sphere, outside the others, in their owner box
+            continue
+        assert np.all(d > 0), g.kind
+    npde = sum(len(g.x) for g in p.groups if g.kind == W.KIND_PDE)
+    assert npde < 8 * 6 ** 3                      # some points fall in the holes
+    surf = [g for g in p.groups if g.kind == W.KIND_DIRICHLET and
+            np.all(np.abs(np.linalg.norm(g.x[:, None, :] - c[None], axis=2) - r[None]).min(axis=1) < 1e-12)]
+    tot = sum(len(g.x) for g in surf)
+    assert tot == sum(int(np.ceil(64 * 4 * np.pi * ri ** 2 * 64)) for ri in r)
+    for g in surf:
+        lo, hi = W.box_bounds(g.owner, p.lo, p.hi, p.nsub)
+        assert np.all(g.x >= lo - 1e-12) and np.all(g.x <= hi + 1e-12)
+        assert np.allclose(g.data, p.exact(g.x))
+
+
+def test_moving_hole_neumann_data_by_finite_differences():
+    p = W.config4(nsub=(2, 2, 2), J=20, q=5, n_t=8, n_theta=6, test_per_dim=2)
+    neu = [g for g in p.groups if g.kind == W.KIND_NEUMANN]
+    assert sum(len(g.x) for g in neu) == 8 * 6
+    h = 1e-5
+    for g in neu:
+        c = W.ac_hole_centre(g.x[:, 2])
+        assert np.allclose(np.linalg.norm(g.x[:, :2] - c, axis=1), W.AC_HOLE_R)
+        # outward normal of the domain points into the hole
+        assert np.allclose(g.normal[:, :2], (c - g.x[:, :2]) / W.AC_HOLE_R) and np.all(g.normal[:, 2] == 0)
+        fd = (p.exact(g.x + h * g.normal) - p.exact(g.x - h * g.normal)) / (2 * h)
+        assert np.allclose(g.data, fd, atol=1e-7)
+    for g in p.groups:
+        if g.kind in (W.KIND_PDE, W.KIND_CONTINUITY, W.KIND_DIRICHLET):
+            assert np.all(np.linalg.norm(g.x[:, :2] - W.ac_hole_centre(g.x[:, 2]), axis=1) > W.AC_HOLE_R)
+
+
+@pytest.mark.parametrize("make,tol", [
+    (lambda: W.config3(nsub=(1, 1, 1), J=300, q=9, test_per_dim=6), 0.05),
+    (lambda: W.config4(nsub=(2, 2, 2), J=120, q=6, n_t=24, n_theta=16, test_per_dim=3), 0.15),
+])
+def test_hole_boundaries_by_manufactured_solution(make, tol):
+    """Sphere Dirichlet rows and moving-hole Neumann rows (with their normals) are
+    consistent with u*: the exact-Newton iteration approaches it."""
+    prob = make()
+    u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
+    assert st.status == "ok"
+    assert np.all(O.rel_l2(prob, u) < tol)
