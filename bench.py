@@ -109,6 +109,8 @@ def main() -> None:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", choices=["ipn", "amipn"], default="ipn")
     ap.add_argument("--sketch-prec", choices=["bf16", "fp8", "f64"], default="bf16")
+    ap.add_argument("--sketch-kind", choices=["gaussian", "count"], default="gaussian",
+                    help="count: the paper's count sketch (FP64; implies --sketch-prec f64)")
     ap.add_argument("--lsqr-prec", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-warm-start-study", action="store_true")
@@ -137,8 +139,11 @@ def main() -> None:
     lp = R.from_description(prob)
     n, m = lp.n, lp.m
     method = R.RFM_AMIPN if a.method == "amipn" else R.RFM_IPN
+    if a.sketch_kind == "count":
+        a.sketch_prec = "f64"
     opts = R.default_opts(method=method, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5,
-                          sketch_prec=PREC[a.sketch_prec], lsqr_prec=PREC[a.lsqr_prec])
+                          sketch_prec=PREC[a.sketch_prec], lsqr_prec=PREC[a.lsqr_prec],
+                          sketch_kind=R.RFM_SKETCH_COUNT if a.sketch_kind == "count" else R.RFM_SKETCH_GAUSSIAN)
     opts64 = R.default_opts(method=method, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5)
     dev = torch.device("cuda", 0)
     u = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -179,7 +184,7 @@ def main() -> None:
     rel = (np.linalg.norm(val - ex, axis=0) / np.linalg.norm(ex, axis=0)).tolist()
 
     ref64 = None
-    if not a.no_fp64_reference and (a.sketch_prec != "f64" or a.lsqr_prec != "f64"):
+    if not a.no_fp64_reference and (a.sketch_prec != "f64" or a.lsqr_prec != "f64" or a.sketch_kind == "count"):
         # the plain FP64 solver on the same problem, for the throughput ratio and the field difference
         u64 = torch.zeros(n, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
@@ -196,7 +201,8 @@ def main() -> None:
                  "field_diff_vs_mixed": float(np.linalg.norm(val - v64) / np.linalg.norm(v64)),
                  "speedup_of_mixed": (t3 - t2) / (elapsed / a.steps)}
 
-    sk_name = {"f64": "sketch_f64", "bf16": "sketch_bf16", "fp8": "sketch_fp8"}[a.sketch_prec]
+    sk_name = "sketch_count" if a.sketch_kind == "count" else \
+        {"f64": "sketch_f64", "bf16": "sketch_bf16", "fp8": "sketch_fp8"}[a.sketch_prec]
     sk_peak = {"f64": PEAK_FP64_TFLOPS, "bf16": PEAK_BF16_TFLOPS, "fp8": PEAK_FP8_TFLOPS}[a.sketch_prec]
 
     def rate(name, what):
@@ -248,7 +254,8 @@ def main() -> None:
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": "gray_scott_3d_4x4x4_J300_q10", "n": n, "m": m, "s": 2 * n, "method": a.method,
-                   "sketch": ("gaussian_philox4x64_f64" if a.sketch_prec == "f64" else
+                   "sketch": ("count_sketch_philox4x64_f64" if a.sketch_kind == "count" else
+                              "gaussian_philox4x64_f64" if a.sketch_prec == "f64" else
                               f"philox4x64_code_table_{a.sketch_prec}_exact_pieces"),
                    "sketch_prec": a.sketch_prec, "lsqr_prec": a.lsqr_prec, "lsqr_tol": 1e-10, "outer_tol": 1e-10,
                    "row_scale_c": 100.0, "initial_guess": "zero"},

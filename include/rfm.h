@@ -133,6 +133,7 @@ int64_t rfm_num_rows(const rfm_problem* p);      /* m (after rfm_finalize), else
 
 enum { RFM_IPN = 0, RFM_AMIPN = 1 };
 enum { RFM_PREC_F64 = 0, RFM_PREC_F32 = 1, RFM_PREC_BF16 = 2, RFM_PREC_FP8 = 3 };
+enum { RFM_SKETCH_GAUSSIAN = 0, RFM_SKETCH_COUNT = 1 };
 
 typedef struct {
   int32_t method;          /* RFM_IPN or RFM_AMIPN                                  */
@@ -152,6 +153,7 @@ typedef struct {
                               step whose LSQR hits lsqr_max_iter or whose line search finds
                               no decrease */
   int32_t sketch_pieces;   /* pieces of D J in a BF16/FP8 sketch, 1..16; 0: 6 (BF16), 12 (FP8) */
+  int32_t sketch_kind;     /* RFM_SKETCH_GAUSSIAN (default) or RFM_SKETCH_COUNT (FP64 only) */
   int32_t verbose;         /* 1: one line per outer step on stderr                   */
 } rfm_solve_opts;
 
@@ -226,6 +228,14 @@ rfm_status rfm_jtmul(rfm_problem* p, const double* y, double* x);
  * Runs on the problem's stream and synchronizes it. */
 rfm_status rfm_stage_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index, int32_t prec,
                             int32_t pieces);
+
+/* Count sketch B = S (D J) (Sec. 4.1 as the paper states it), s = ceil(gamma n)
+ * rows, kept as the current B: S[h(r)][r] = sigma(r), the only non-zero of
+ * column r, with h(r) = w0 mod s and sigma(r) = +1 if bit 0 of w1 is clear, else
+ * -1, where (w0, w1, ..) = Philox4x64-10 at counter (r, 0, 2, 0), key (seed,
+ * jac_index).  One pass over D J; sums within a bucket in row order (no
+ * atomics).  Runs on the problem's stream and synchronizes it. */
+rfm_status rfm_stage_count_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index);
 
 /* The 256 integer codes of the low-precision sketch: K[b] = the integer nearest
  * (ties to even) to k_s Phi^{-1}((b + 1/2) / 256), k_s = 32 for RFM_PREC_BF16

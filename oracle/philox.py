@@ -9,7 +9,9 @@ multiply-xor bijection on a 4x64-bit counter block under a 2x64-bit key that
 is bumped by two Weyl constants between rounds.  Written here in plain numpy
 uint64 arithmetic (the 128-bit product is assembled from 32-bit halves).
 
-Sketch entries (a reading of the sketch S_k of Sec. 4.1, made Gaussian):
+Count sketch (Sec. 4.1 as the paper states it): see count_sketch_hash below.
+
+Gaussian sketch entries (a reading of the sketch S_k of Sec. 4.1, made Gaussian):
 S[i, r] for sketch row i and Jacobian row r uses the counter (i // 8, r, 0, 0)
 and the key (seed, jac_index).  Each of the four 64-bit outputs x_w is one
 Box-Muller pair: with u1 = ((x_w >> 32) + 1) 2^-32 in (0, 1] and
@@ -100,3 +102,29 @@ def sketch_matrix(seed: int, jac_index: int, s: int, m: int) -> np.ndarray:
     octs = gaussian_octets(seed, jac_index, qq, rr).reshape(nq, m, 8)
     G = octs.transpose(0, 2, 1).reshape(8 * nq, m)[:s]
     return G / np.sqrt(s)
+
+
+# ---------------------------------------------------------------------------
+# count sketch (the sketch of Sec. 4.1): one +-1 per column of S
+# ---------------------------------------------------------------------------
+
+def count_sketch_hash(seed: int, jac_index: int, r: np.ndarray, s: int):
+    """Bucket h(r) in [0, s) and sign sigma(r) of Jacobian row r: Philox4x64-10 at
+    counter (r, 0, 2, 0), key (seed, jac_index); h = word 0 mod s, sigma = +1 if bit 0
+    of word 1 is clear, else -1."""
+    r = np.asarray(r, np.int64).ravel()
+    ctr = np.zeros((r.size, 4), np.uint64)
+    ctr[:, 0] = r.astype(np.uint64)
+    ctr[:, 2] = 2
+    x = philox4x64(ctr, (seed, jac_index))
+    h = (x[:, 0] % np.uint64(s)).astype(np.int64)
+    sig = np.where((x[:, 1] & np.uint64(1)) == 0, 1.0, -1.0)
+    return h, sig
+
+
+def count_sketch_matrix(seed: int, jac_index: int, s: int, m: int) -> np.ndarray:
+    """Dense S in R^{s x m}: S[h(r), r] = sigma(r), zero elsewhere (small problems only)."""
+    h, sig = count_sketch_hash(seed, jac_index, np.arange(m), s)
+    S = np.zeros((s, m))
+    S[h, np.arange(m)] = sig
+    return S

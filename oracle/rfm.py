@@ -403,6 +403,7 @@ class Opts:
     tau_rel: float = 1e-3
     row_c: float = 100.0
     gs_iters: int = 25
+    sketch_kind: str = "gaussian"  # "gaussian" | "count" (the count sketch of Sec. 4.1, FP64)
     sketch_prec: str = "f64"       # "f64" | "bf16" | "fp8"  (oracle.lowprec)
     sketch_pieces: int = 0         # pieces of D J in the low-precision sketch (0: format default)
     lsqr_prec: str = "f64"         # "f64" | "f32": D J copy used by the LSQR products
@@ -434,7 +435,9 @@ def make_precond(prob: Problem, u: np.ndarray, opts: Opts, jac_index: int) -> Pr
     R = None
     if opts.mode == "replica":
         s = sketch_rows(prob.n, opts.gamma)
-        if opts.sketch_prec == "f64":
+        if opts.sketch_kind == "count":
+            B = philox.count_sketch_matrix(opts.seed, jac_index, s, DJ.shape[0]) @ DJ
+        elif opts.sketch_prec == "f64":
             B = sketch(DJ, s, opts.seed, jac_index)
         else:
             B = lowprec.sketch_lowp(prob, DJ, s, opts.seed, jac_index, opts.sketch_prec, opts.sketch_pieces)

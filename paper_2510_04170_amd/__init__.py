@@ -22,6 +22,7 @@ RFM_ENOCONV, RFM_ESTALL = 1, 2
 RFM_PDE, RFM_DIRICHLET, RFM_NEUMANN, RFM_CONTINUITY = 0, 1, 2, 3
 RFM_IPN, RFM_AMIPN = 0, 1
 RFM_PREC_F64, RFM_PREC_F32, RFM_PREC_BF16, RFM_PREC_FP8 = 0, 1, 2, 3
+RFM_SKETCH_GAUSSIAN, RFM_SKETCH_COUNT = 0, 1
 RFM_MAX_STEPS = 64
 
 
@@ -38,7 +39,8 @@ class rfm_solve_opts(C.Structure):
                 ("lsqr_tol", C.c_double), ("lsqr_max_iter", C.c_int32), ("outer_tol", C.c_double),
                 ("max_outer", C.c_int32), ("m_max", C.c_int32), ("tau_rel", C.c_double),
                 ("row_scale_c", C.c_double), ("gs_iters", C.c_int32), ("sketch_prec", C.c_int32),
-                ("lsqr_prec", C.c_int32), ("sketch_pieces", C.c_int32), ("verbose", C.c_int32)]
+                ("lsqr_prec", C.c_int32), ("sketch_pieces", C.c_int32), ("sketch_kind", C.c_int32),
+                ("verbose", C.c_int32)]
 
 
 class rfm_solve_stats(C.Structure):
@@ -103,6 +105,7 @@ _SIGS = {
     "rfm_jtmul": (C.c_int, [_P, _D, _D]),
     "rfm_stage_sketch": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64, C.c_int32, C.c_int32]),
     "rfm_sketch_table": (C.c_int, [C.c_int32, _D]),
+    "rfm_stage_count_sketch": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64]),
     "rfm_sketch_operand_slots": (C.c_int64, [_P, C.c_int32]),
     "rfm_get_sketch_operand": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, _D, C.c_void_p,
                                          C.c_void_p]),
@@ -392,6 +395,9 @@ class RfmProblem:
 
     def stage_sketch(self, gamma: float, seed: int, jac_index: int, prec: int = RFM_PREC_F64, pieces: int = 0):
         _check(lib().rfm_stage_sketch(self.h, gamma, seed, jac_index, prec, pieces))
+
+    def stage_count_sketch(self, gamma: float, seed: int, jac_index: int):
+        _check(lib().rfm_stage_count_sketch(self.h, gamma, seed, jac_index))
 
     def sketch_operand_slots(self, block: int) -> int:
         return int(lib().rfm_sketch_operand_slots(self.h, block))

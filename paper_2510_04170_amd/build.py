@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "librfmnewton.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "solver.cpp", "k_rows.hip", "k_sketch.hip", "k_qr.hip", "k_trsv.hip", "k_lsqr.hip", "k_lowp.hip", "mlp.hip", "warm.cpp"]
+SOURCES = ["api.cpp", "solver.cpp", "k_rows.hip", "k_sketch.hip", "k_qr.hip", "k_trsv.hip", "k_lsqr.hip", "k_lowp.hip", "mlp.hip", "warm.cpp", "k_count.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable", "-Wno-unused-result"]

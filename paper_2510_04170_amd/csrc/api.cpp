@@ -240,7 +240,8 @@ static void finalize(Problem& P) {
   // segment in the block (-1 where the row does not touch it)
   P.cbs_ptr_h.assign(nblk + 1, 0);
   P.slot_group_h.clear();
-  std::vector<int64_t> slot_rowoff;
+  std::vector<int64_t>& slot_rowoff = P.slot_rowoff_h;
+  slot_rowoff.clear();
   for (int bk = 0; bk < nblk; ++bk) {
     std::map<int64_t, std::array<int64_t, 32>> grp;
     for (auto& pr : contrib[bk]) {
@@ -585,6 +586,21 @@ int64_t rfm_num_rows(const rfm_problem* p) {
   if (!p) return -1;
   const Problem& P = *reinterpret_cast<const Problem*>(p);
   return P.finalized ? P.m : -1;
+}
+
+rfm_status rfm_stage_count_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_J, RFM_EINVAL, "no Jacobian assembled");
+    RFM_CHECK(gamma > 1.0 && std::isfinite(gamma), RFM_EINVAL, "gamma must be > 1");
+    const int64_t s = (int64_t)std::ceil(gamma * (double)P.n);
+    RFM_CHECK(s >= P.n && s < (int64_t)INT32_MAX, RFM_EINVAL, "sketch size out of range");
+    P.s = s;
+    launch_count_sketch(P, seed, jac_index);
+    P.have_B = true;
+    P.have_R = false;
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
 }
 
 rfm_status rfm_sketch_table(int32_t prec, double* out) {

@@ -219,6 +219,7 @@ struct Problem {
   std::vector<int32_t> cb_ptr_h, cb_tile_h, cb_off_h;  // column block -> contributing tiles
   // low-precision sketch operand: per column block, the 32-row groups of rows touching it
   std::vector<int32_t> cbs_ptr_h, slot_group_h;
+  std::vector<int64_t> slot_rowoff_h;     // [slot][32]: offset of the row's segment in d_J, or -1
   int64_t nslots = 0;
 
   // device: geometry, features, rows, tiles
@@ -239,6 +240,9 @@ struct Problem {
   DBuf<int64_t> d_slot_rowoff;            // [slot][32]: offset of the row's segment in d_J, or -1
   DBuf<uint16_t> d_pan16, d_tab16;        // BF16 pieces [piece][slot][J][32]; code table
   DBuf<uint8_t> d_pan8, d_tab8;          // FP8 pieces [piece][slot][J][32]; code table
+  DBuf<int64_t> d_cs_eoff;                // count sketch: d_J offsets of the grouped rows
+  DBuf<double> d_cs_sign;                 //               their signs
+  DBuf<char> d_cs_runs;                   //               runs of equal bucket
   DBuf<int32_t> d_pexp;                   // exponent E of each (chunk of 4 slots, column)
   int pan_prec = -1, pan_pieces = 0;
   bool have_tables = false;
@@ -301,6 +305,10 @@ void launch_sketch(Problem& P, uint64_t seed, uint64_t jac_index, int prec);
 
 // network shape check (mlp.hip): throws RFM_EINVAL unless in_dim / out_dim match
 void mlp_check_shape(rfm_mlp* net, int in_dim, int out_dim);
+
+// count sketch (k_count.hip)
+void count_sketch_hash(int64_t r, int64_t s, uint64_t seed, uint64_t jac, int64_t* h, double* sigma);
+void launch_count_sketch(Problem& P, uint64_t seed, uint64_t jac_index);
 
 // low-precision forms (k_lowp.hip)
 void sketch_table(int prec, double* out);

@@ -55,7 +55,9 @@ struct Driver {
     sync();
     double t1 = now();
     P.s = (int64_t)std::ceil(o.sketch_factor * (double)P.n);
-    if (o.sketch_prec == RFM_PREC_F64)
+    if (o.sketch_kind == RFM_SKETCH_COUNT)
+      launch_count_sketch(P, o.sketch_seed, (uint64_t)jac_index);
+    else if (o.sketch_prec == RFM_PREC_F64)
       launch_sketch(P, o.sketch_seed, (uint64_t)jac_index, o.sketch_prec);
     else
       launch_sketch_lowp(P, o.sketch_seed, (uint64_t)jac_index, o.sketch_prec, o.sketch_pieces);
@@ -281,6 +283,10 @@ void check_opts(const rfm_solve_opts& o) {
   RFM_CHECK(o.sketch_prec == RFM_PREC_F64 || o.sketch_prec == RFM_PREC_BF16 || o.sketch_prec == RFM_PREC_FP8,
             RFM_EINVAL, "opts.sketch_prec must be F64, BF16 or FP8");
   RFM_CHECK(o.sketch_pieces >= 0 && o.sketch_pieces <= kMaxPieces, RFM_EINVAL, "opts.sketch_pieces must be 0..16");
+  RFM_CHECK(o.sketch_kind == RFM_SKETCH_GAUSSIAN || o.sketch_kind == RFM_SKETCH_COUNT, RFM_EINVAL,
+            "opts.sketch_kind must be GAUSSIAN or COUNT");
+  RFM_CHECK(o.sketch_kind == RFM_SKETCH_GAUSSIAN || o.sketch_prec == RFM_PREC_F64, RFM_EINVAL,
+            "the count sketch is formed in FP64 (its entries are signed copies of D J)");
   RFM_CHECK(o.lsqr_prec == RFM_PREC_F64 || o.lsqr_prec == RFM_PREC_F32, RFM_EINVAL,
             "opts.lsqr_prec must be F64 or F32");
 }
@@ -310,6 +316,7 @@ void rfm_solve_opts_default(rfm_solve_opts* o) {
   o->sketch_prec = RFM_PREC_F64;
   o->lsqr_prec = RFM_PREC_F64;
   o->sketch_pieces = 0;
+  o->sketch_kind = RFM_SKETCH_GAUSSIAN;
   o->verbose = 0;
 }
 

@@ -130,6 +130,22 @@ def test_sketch_matches_oracle(case):
     assert _relerr(Bg, Bo) < 1e-12
 
 
+def test_count_sketch_matches_oracle(case):
+    lp, DJ = case["lp"], case["DJ"]
+    lp.stage_assemble(case["u"], 100.0)
+    lp.stage_count_sketch(2.0, 1, 3)
+    s = lp.s
+    Bg = lp.get_sketch_cols(0, lp.n)
+    Bo = PH.count_sketch_matrix(1, 3, s, DJ.shape[0]) @ DJ
+    # each entry is a signed sum of a few entries of D J, in row order on both sides
+    assert _relerr(Bg, Bo) < 1e-13
+    lp.stage_qr()
+    Rg = lp.get_r_cols(0, lp.n)
+    sv = np.linalg.svd(DJ @ np.linalg.inv(Rg), compute_uv=False)
+    print(f"{case['name']}: kappa(D J R^-1) with the count sketch {sv[0] / sv[-1]:.2f}")
+    assert sv[0] / sv[-1] < 100.0
+
+
 def test_qr_invariants_and_conditioning(case):
     lp, DJ = case["lp"], case["DJ"]
     lp.stage_assemble(case["u"], 100.0)
@@ -323,4 +339,22 @@ def test_full_solve_with_holes(name, method):
     assert abs(st["outer_iters"] - so.outer_iters) <= 2 and abs(st["jac_evals"] - so.jac_evals) <= 2
     assert e_or < (1e-8 if method == "ipn" else 1e-6)
     assert abs(_relerr(fg, ex) - _relerr(fo, ex)) <= 1e-7 + 1e-3 * _relerr(fo, ex)
+    lp.close()
+
+
+@pytest.mark.parametrize("name", ["poisson2d_full", "grayscott_small"])
+def test_full_solve_count_sketch(name):
+    _announce(f"full solve with the count sketch: {name}")
+    prob = CASES[name]()
+    lp = R.from_description(prob)
+    opts = R.default_opts(sketch_factor=2.0, lsqr_tol=1e-10, m_max=5, sketch_kind=R.RFM_SKETCH_COUNT)
+    ug, st, rc = lp.solve(None, opts)
+    assert rc in (R.RFM_OK, R.RFM_ESTALL), (rc, st)
+    uo, so = O.ipn(prob, opts=O.Opts(gamma=2.0, lsqr_tol=1e-10, sketch_kind="count"))
+    fg = O.eval_field(prob, ug, prob.test_x, prob.test_owner)
+    fo = O.eval_field(prob, uo, prob.test_x, prob.test_owner)
+    ex = prob.exact(prob.test_x)
+    print(f"{name} count sketch: IT {st['outer_iters']} LSQR {st['lsqr_iters']} (oracle {so.lsqr_iters}); field vs "
+          f"oracle {_relerr(fg, fo):.2e}; relL2 vs u* {_relerr(fg, ex):.3e}")
+    assert _relerr(fg, fo) < 1e-8
     lp.close()

@@ -482,3 +482,47 @@ def test_hole_boundaries_by_manufactured_solution(make, tol):
     u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
     assert st.status == "ok"
     assert np.all(O.rel_l2(prob, u) < tol)
+
+
+# ---------------------------------------------------------------------------
+# count sketch
+# ---------------------------------------------------------------------------
+
+def test_count_sketch_structure():
+    s, m = 300, 5000
+    S = P.count_sketch_matrix(4, 1, s, m)
+    # one +-1 per column: S^T S = I exactly
+    assert np.array_equal((S != 0).sum(axis=0), np.ones(m))
+    assert set(np.unique(S[S != 0])) <= {-1.0, 1.0}
+    assert np.array_equal(np.diag(S.T @ S), np.ones(m))
+    # buckets and signs are uniform: counts per bucket ~ Poisson(m/s), signs balanced
+    cnt = (S != 0).sum(axis=1)
+    lam = m / s
+    assert abs(cnt.mean() - lam) < 1e-12
+    assert abs(cnt.var() - lam) < 6 * lam * np.sqrt(2 / s)
+    nz = S[S != 0]
+    assert abs(nz.mean()) < 5 / np.sqrt(m)
+    # byte-independent check of the hash: word 0 mod s, bit 0 of word 1
+    w = P.philox4x64(np.array([[7, 0, 2, 0]], np.uint64), (4, 1))[0]
+    h, sig = P.count_sketch_hash(4, 1, np.array([7]), s)
+    assert h[0] == int(w[0]) % s and sig[0] == (1.0 if int(w[1]) % 2 == 0 else -1.0)
+    # a different Jacobian index rehashes
+    S2 = P.count_sketch_matrix(4, 2, s, m)
+    assert (np.argmax(S2 != 0, axis=0) != np.argmax(S != 0, axis=0)).mean() > 0.9
+
+
+def test_count_sketch_preconditions():
+    """With s = 3n (the paper's gamma) the count sketch embeds the column space well
+    enough that D J R^-1 is well conditioned although D J is not, and LSQR converges."""
+    prob = W.config1(nsub=(2, 2), J=100, q=14)
+    F, J = O.assemble(prob, np.zeros(prob.n))
+    D = O.row_scale(J)
+    DJ = D[:, None] * J
+    s = O.sketch_rows(prob.n, 3.0)
+    R = O.qr_r(P.count_sketch_matrix(1, 0, s, DJ.shape[0]) @ DJ)
+    sa = np.linalg.svd(DJ @ np.linalg.inv(R), compute_uv=False)
+    sv = np.linalg.svd(DJ, compute_uv=False)
+    assert sv[0] / sv[-1] > 1e8
+    assert sa[0] / sa[-1] < 100.0
+    res = O.lsqr(lambda v: DJ @ O.r_solve(R, v), lambda w: O.rt_solve(R, DJ.T @ w), -D * F, prob.n, 1e-10, 1000)
+    assert res.istop in (1, 2)
