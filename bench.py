@@ -48,8 +48,9 @@ PREC = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
 
 # HBM bytes per launch of the dominant kernel on this workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, scaled by 2.0 and 1.0: what the same counters read
-# for an elementwise copy of 1 GiB); valid while the kernel is unchanged
-TRAFFIC_BYTES = {"qr_gemm_nn": (14847208.0 * 2.0 + 9626800.5 * 1.0) * 1024.0}
+# for an elementwise copy of 1 GiB); valid only while the kernel is unchanged, so a kernel without
+# counters taken on its current code reports null
+TRAFFIC_BYTES = {}
 
 METRIC = "Newton solves/s at relL2<=1e-6; sketch-GEMM TFLOP/s; LSQR SpMV HBM GB/s"
 

@@ -13,9 +13,13 @@
 //     beta = -sign(alpha) ||(alpha, x)||.
 //  2. The Gram V^T V (k_gemm_tn) and the compact-WY factor T (k_build_t), with
 //     H_1 ... H_ib = I - V T V^T (Schreiber and Van Loan, 1989).
-//  3. Trailing update C <- (I - V T^T V^T) C as W = V^T C (k_gemm_tn, split over
-//     rows with a fixed-order reduction), W2 = -T^T W (k_reduce_w) and
-//     C += V W2 (k_gemm_nn), both products on v_mfma_f64_16x16x4.
+//  3. Inside a 256-column outer panel, each 64-column block updates the rest of
+//     the outer panel: W = V^T C (k_gemm_tn, split over rows with a fixed-order
+//     reduction), W2 = -T^T W (k_reduce_w) and C += V W2 (k_gemm_nn), on
+//     v_mfma_f64_16x16x4.  The four blocks' T factors are merged into the T of
+//     the outer panel (k_combine_t, then the 256-wide assembly), and the
+//     trailing matrix gets one update with K = 256 (k_gemm_tn128, k_reduce_w256,
+//     k_gemm_nn128) on v_mfma_f64_4x4x4_4b.
 // Finally k_extract_r copies R (rows flipped to a positive diagonal) into the
 // tiled upper storage used by the triangular solves and flags a zero or
 // non-finite diagonal entry.
@@ -361,171 +365,206 @@ __global__ void __launch_bounds__(256) k_gemm_nn(double* __restrict__ C, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// 128 x 128 tiles for the trailing update of 128-column outer panels.
-// Four wavefronts in a 2 x 2 arrangement each own a 64 x 64 block (4 x 4 MFMA
-// tiles, 64 accumulator doubles per lane); operands are staged through LDS 16
-// values of k at a time, with the next chunk's global loads issued before the
-// current chunk's MFMAs.
+// 128 x 128 tiles for the trailing update of 256-column outer panels.
+// Four wavefronts in a 2 x 2 arrangement each own a 64 x 64 block of 64
+// accumulators per lane on v_mfma_f64_4x4x4_4b_f64 (measured on gfx950 at
+// about 1.5x the FP64 rate of the 16x16x4 form).  Operands are staged through
+// LDS 16 values of k at a time; the next chunk's global loads (16 bytes per
+// lane) are issued before the current chunk's MFMAs.
 // ---------------------------------------------------------------------------
 constexpr int kBig = 128;
 constexpr int kKC = 16;
 
-// One 16-deep k-chunk of MFMAs on LDS tiles As[k][m], Bs[k][n] for a 2 x 2 wavefront grid.
-__device__ __forceinline__ void mfma_chunk(const double (*As)[kBig + 1], const double (*Bs)[kBig + 1], int lane,
-                                           int wr, int wc, v4d (&acc)[4][4]) {
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// One 16-deep k-chunk on LDS tiles Xs[k][row], Ys[k][col] (row and column of the output).
+// v_mfma_f64_4x4x4_4b_f64 holds, for block b, A(i,k) in lane 16k+4b+i, B(k,j) in lane 16k+4b+j
+// and D(i,j) in lane 16i+4b+j.  With the A operand carrying 4 output columns (the same in every
+// block) and the B operand 16 output rows, acc[rg][cg] in lane l is output row rg*16 + l%16 and
+// column cg*4 + l/16 of the wavefront's 64 x 64 block: 16 consecutive rows of one column per
+// 16 lanes, which suits column-major stores.
+__device__ __forceinline__ void mfma4_chunk(const double (*Xs)[kBig + 1], const double (*Ys)[kBig + 1], int lane,
+                                            int wr, int wc, double (&acc)[4][16]) {
 #pragma unroll
   for (int ks = 0; ks < kKC / 4; ++ks) {
     const int kr = ks * 4 + lane / 16;
-    double a[4], b[4];
+    double x[4];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) a[rt] = As[kr][wr * 64 + rt * 16 + lane % 16];
+    for (int rg = 0; rg < 4; ++rg) x[rg] = Xs[kr][wr * 64 + rg * 16 + lane % 16];
+    // the column operands in two halves keep the kernel within 256 VGPRs
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) b[ct] = Bs[kr][wc * 64 + ct * 16 + lane % 16];
+    for (int h = 0; h < 2; ++h) {
+      double y[8];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+      for (int cg = 0; cg < 8; ++cg) y[cg] = Ys[kr][wc * 64 + (h * 8 + cg) * 4 + lane % 4];
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
+      for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+        for (int cg = 0; cg < 8; ++cg)
+          acc[rg][h * 8 + cg] = __builtin_amdgcn_mfma_f64_4x4x4f64(y[cg], x[rg], acc[rg][h * 8 + cg], 0, 0, 0);
+    }
   }
 }
 
-// C[M x N] += A[M x K] B, A column-major (lda), B[k][n] = Bt[n * ldb + k]; K a multiple of 16.
-// LDS is double-buffered: chunk c+1 is loaded to registers while chunk c runs on the
-// MFMA units and stored to the other buffer afterwards, one barrier per chunk.
+// C[M x N] += A[M x K] B, A column-major (lda even, 16-byte aligned), B[k][n] = Bt[n * ldb + k] (ldb even,
+// aligned); K a multiple of 16.  Loaders: A as row pairs (m = 2 (tid % 64), k = tid / 64 + 4 i), B as k pairs
+// (k = 2 (tid % 8), n = tid / 8 + 32 i); tiles wholly inside M x N take unguarded 16-byte loads.
 __global__ void __launch_bounds__(256, 2) k_gemm_nn128(double* __restrict__ C, int64_t ldc,
-                                                       const double* __restrict__ A, int64_t lda,
-                                                       const double* __restrict__ Bt, int64_t ldb, int M, int N,
-                                                       int K) {
+                                                      const double* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ Bt, int64_t ldb, int M, int N,
+                                                      int K) {
   __shared__ double As[2][kKC][kBig + 1];
   __shared__ double Bs[2][kKC][kBig + 1];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
   const int r0 = blockIdx.x * kBig, n0 = blockIdx.y * kBig;
-  // accumulate from zero and add C in the epilogue, so that no C values are live
-  // during the K loop (keeps the kernel at two wavefronts per SIMD)
-  v4d acc[4][4];
+  const bool full = (r0 + kBig <= M) && (n0 + kBig <= N);
+  double acc[4][16];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = v4d{0, 0, 0, 0};
-  // loader roles: A: m = tid % 128, k = tid / 128 + 2 i;  B: k = tid % 16, n = tid / 16 + 16 i
-  const int am = tid % kBig, ak = tid / kBig;
-  const int bk = tid % kKC, bn = tid / kKC;
-  double ra0[8], rb0[8];
-  auto load = [&](double (&ra)[8], double (&rb)[8], int k0) {
+    for (int cg = 0; cg < 16; ++cg) acc[rg][cg] = 0.0;
+  const int am = 2 * (tid % 64), ak = tid / 64;
+  const int bk = 2 * (tid % 8), bn = tid / 8;
+  v2d ra[4], rb[4];
+  auto load = [&](int k0) {
+    if (full) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = k0 + ak + 2 * i;
-      ra[i] = (r0 + am < M) ? A[(int64_t)k * lda + r0 + am] : 0.0;
-      const int n = n0 + bn + 16 * i;
-      rb[i] = (n < N) ? Bt[(int64_t)n * ldb + k0 + bk] : 0.0;
+      for (int i = 0; i < 4; ++i) {
+        ra[i] = *reinterpret_cast<const v2d*>(A + (int64_t)(k0 + ak + 4 * i) * lda + r0 + am);
+        rb[i] = *reinterpret_cast<const v2d*>(Bt + (int64_t)(n0 + bn + 32 * i) * ldb + k0 + bk);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double* ap = A + (int64_t)(k0 + ak + 4 * i) * lda + r0 + am;
+        ra[i].x = (r0 + am < M) ? ap[0] : 0.0;
+        ra[i].y = (r0 + am + 1 < M) ? ap[1] : 0.0;
+        const int n = n0 + bn + 32 * i;
+        const double* bp = Bt + (int64_t)n * ldb + k0 + bk;
+        rb[i].x = (n < N) ? bp[0] : 0.0;
+        rb[i].y = (n < N) ? bp[1] : 0.0;
+      }
     }
   };
-  auto stash = [&](const double (&ra)[8], const double (&rb)[8], int buf) {
+  auto stash = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      As[buf][ak + 2 * i][am] = ra[i];
-      Bs[buf][bk][bn + 16 * i] = rb[i];
+    for (int i = 0; i < 4; ++i) {
+      As[buf][ak + 4 * i][am] = ra[i].x;
+      As[buf][ak + 4 * i][am + 1] = ra[i].y;
+      Bs[buf][bk][bn + 32 * i] = rb[i].x;
+      Bs[buf][bk + 1][bn + 32 * i] = rb[i].y;
     }
   };
-  load(ra0, rb0, 0);
-  stash(ra0, rb0, 0);
+  load(0);
+  stash(0);
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < K; k0 += kKC) {
     const bool more = k0 + kKC < K;
-    if (more) load(ra0, rb0, k0 + kKC);
-    mfma_chunk(As[buf], Bs[buf], lane, wr, wc, acc);
-    if (more) stash(ra0, rb0, buf ^ 1);
+    if (more) load(k0 + kKC);
+    mfma4_chunk(As[buf], Bs[buf], lane, wr, wc, acc);
+    if (more) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
-  // epilogue: per column tile, 16 loads of C in flight, then add and store
+  const int row_l = lane % 16, col_l = lane / 16;
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int col = n0 + wc * 64 + ct * 16 + lane % 16;
-    if (col >= N) continue;
-    double* ccol = C + (int64_t)col * ldc;
-    double cv[4][4];
+  for (int rg = 0; rg < 4; ++rg) {
+    const int r = r0 + wr * 64 + rg * 16 + row_l;
+    if (r >= M) continue;
+    double cv[16];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int cg = 0; cg < 16; ++cg) {
+      const int col = n0 + wc * 64 + cg * 4 + col_l;
+      cv[cg] = col < N ? C[(int64_t)col * ldc + r] : 0.0;
+    }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int r = r0 + wr * 64 + rt * 16 + (lane / 16) + 4 * t;
-        cv[rt][t] = r < M ? ccol[r] : 0.0;
-      }
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int r = r0 + wr * 64 + rt * 16 + (lane / 16) + 4 * t;
-        if (r < M) ccol[r] = cv[rt][t] + acc[rt][ct][t];
-      }
+    for (int cg = 0; cg < 16; ++cg) {
+      const int col = n0 + wc * 64 + cg * 4 + col_l;
+      if (col < N) C[(int64_t)col * ldc + r] = cv[cg] + acc[rg][cg];
+    }
   }
 }
 
 // part[split][n][p] = sum_{k in split} A[k][p] B[k][n]; A: K x 128 (lda), B: K x N (ldb), both
-// column-major; rows of a split: [split * krange, ...), krange a multiple of 16
+// column-major; rows of a split: [split * krange, ...), krange a multiple of 16.  Grid: (P halves
+// of a 256-wide V, column tiles, row splits).  VEC: lda, ldb even and both bases 16-byte aligned,
+// so k pairs load as 16 bytes.
+template <bool VEC>
 __global__ void __launch_bounds__(256, 2) k_gemm_tn128(const double* __restrict__ A, int64_t lda,
-                                                       const double* __restrict__ B, int64_t ldb, int K, int N,
-                                                       int krange, double* __restrict__ part, int pstride) {
+                                                     const double* __restrict__ B, int64_t ldb, int K, int N,
+                                                     int krange, double* __restrict__ part, int pstride) {
   __shared__ double As[2][kKC][kBig + 1];
   __shared__ double Bs[2][kKC][kBig + 1];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
-  // grid: (P halves of a 256-wide V, column tiles, row splits); the two halves of one
-  // column tile are neighbours in launch order, so the second read of C hits cache
   const int half = blockIdx.x;
   const int n0 = blockIdx.y * kBig;
   const int split = blockIdx.z;
   A += (int64_t)half * kBig * lda;
   const int kb = split * krange, ke = min(K, kb + krange);
-  v4d acc[4][4];
+  const bool ncols_full = n0 + kBig <= N;
+  double acc[4][16];
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = v4d{0, 0, 0, 0};
-  const int lk = tid % kKC, lc = tid / kKC;  // k = lk, column lc + 16 i
-  double ra0[8], rb0[8];
-  auto load = [&](double (&ra)[8], double (&rb)[8], int k0) {
+    for (int cg = 0; cg < 16; ++cg) acc[rg][cg] = 0.0;
+  const int lk = 2 * (tid % 8), lc = tid / 8;  // k pair lk, lk + 1; column lc + 32 i
+  v2d ra[4], rb[4];
+  auto load = [&](int k0) {
     const int k = k0 + lk;
-    const bool kv = k < ke;
+    if (VEC && ncols_full && k0 + kKC <= ke) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int c = lc + 16 * i;
-      ra[i] = kv ? A[(int64_t)c * lda + k] : 0.0;
-      rb[i] = (kv && n0 + c < N) ? B[(int64_t)(n0 + c) * ldb + k] : 0.0;
+      for (int i = 0; i < 4; ++i) {
+        const int c = lc + 32 * i;
+        ra[i] = *reinterpret_cast<const v2d*>(A + (int64_t)c * lda + k);
+        rb[i] = *reinterpret_cast<const v2d*>(B + (int64_t)(n0 + c) * ldb + k);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = lc + 32 * i;
+        const bool cv = n0 + c < N;
+        ra[i].x = k < ke ? A[(int64_t)c * lda + k] : 0.0;
+        ra[i].y = k + 1 < ke ? A[(int64_t)c * lda + k + 1] : 0.0;
+        rb[i].x = (k < ke && cv) ? B[(int64_t)(n0 + c) * ldb + k] : 0.0;
+        rb[i].y = (k + 1 < ke && cv) ? B[(int64_t)(n0 + c) * ldb + k + 1] : 0.0;
+      }
     }
   };
-  auto stash = [&](const double (&ra)[8], const double (&rb)[8], int buf) {
+  auto stash = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      As[buf][lk][lc + 16 * i] = ra[i];
-      Bs[buf][lk][lc + 16 * i] = rb[i];
+    for (int i = 0; i < 4; ++i) {
+      const int c = lc + 32 * i;
+      As[buf][lk][c] = ra[i].x;
+      As[buf][lk + 1][c] = ra[i].y;
+      Bs[buf][lk][c] = rb[i].x;
+      Bs[buf][lk + 1][c] = rb[i].y;
     }
   };
   if (kb < ke) {
-    load(ra0, rb0, kb);
-    stash(ra0, rb0, 0);
+    load(kb);
+    stash(0);
   }
   __syncthreads();
   int buf = 0;
   for (int k0 = kb; k0 < ke; k0 += kKC) {
     const bool more = k0 + kKC < ke;
-    if (more) load(ra0, rb0, k0 + kKC);
-    mfma_chunk(As[buf], Bs[buf], lane, wr, wc, acc);
-    if (more) stash(ra0, rb0, buf ^ 1);
+    if (more) load(k0 + kKC);
+    mfma4_chunk(As[buf], Bs[buf], lane, wr, wc, acc);
+    if (more) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
   double* o = part + (size_t)split * N * pstride + (size_t)half * kBig;
+  const int row_l = lane % 16, col_l = lane / 16;
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int col = n0 + wc * 64 + ct * 16 + lane % 16;
+  for (int cg = 0; cg < 16; ++cg) {
+    const int col = n0 + wc * 64 + cg * 4 + col_l;
     if (col >= N) continue;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) o[(int64_t)col * pstride + wr * 64 + rt * 16 + (lane / 16) + 4 * t] = acc[rt][ct][t];
+    for (int rg = 0; rg < 4; ++rg) o[(int64_t)col * pstride + wr * 64 + rg * 16 + row_l] = acc[rg][cg];
   }
 }
 
@@ -609,6 +648,16 @@ __global__ void k_zero_block(double* __restrict__ V, int64_t ldv, int c0, int nc
 __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) p[e] = v;
+}
+
+// G[b][a] = sum over splits of part[split][b][a] for b < nb (64-wide rows), splits in order; the
+// single-workgroup T builders then read G as a one-split partial
+__global__ void k_gsum64(const double* __restrict__ part, int nsplit, int nb, double* __restrict__ G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * kPanel) return;
+  double g = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) g += part[(size_t)sp * nb * kPanel + e];
+  G[e] = g;
 }
 
 // G[a][b] (row-major 128 x 128) = sum over splits of part[split][b][a] (pstride 128)
@@ -769,9 +818,9 @@ void qr_factor(Problem& P) {
   const int ncu = num_cus(P.device);
   const int max_split = 16;
   // workspace
-  const size_t vb = (size_t)s * kOuter;
+  const size_t vb = (size_t)(s + 1) * kOuter;  // V of an outer panel, leading dimension M rounded up to even
   const size_t tn = (size_t)max_split * std::max<int64_t>(n, kOuter) * kOuter;
-  const size_t small = 4 * kPanel * kPanel + 5 * kBig * kBig + kOuter * kOuter;
+  const size_t small = 5 * kPanel * kPanel + 5 * kBig * kBig + kOuter * kOuter;
   const size_t need = vb + small + 2 * (size_t)ncu * kPanel + 4 * kPanel + tn + (size_t)n * kOuter + 256;
   P.d_ws.resize(need);
   double* Vb = P.d_ws.p;
@@ -781,7 +830,8 @@ void qr_factor(Problem& P) {
   double* X128 = G128 + kBig * kBig;
   double* Y128 = X128 + kBig * kBig;
   double* T256 = Y128 + kBig * kBig;
-  double* Pp = T256 + kOuter * kOuter;
+  double* G64 = T256 + kOuter * kOuter;    // summed 64-wide Gram blocks
+  double* Pp = G64 + kPanel * kPanel;
   double* DR = Pp + 2 * (size_t)ncu * kPanel;
   double* part = DR + 4 * kPanel;
   double* W2 = part + tn;
@@ -803,14 +853,17 @@ void qr_factor(Problem& P) {
     int nsplit, krange;
     tn_split(K, 1, std::max(1, ncu / 16), 64, &nsplit, &krange);
     hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit), dim3(256), 0, P.stream, V, ldv, V, ldv, K, nb, krange, part);
-    hipLaunchKernelGGL(k_build_t, dim3(1), dim3(256), 0, P.stream, part, nsplit, nb, tau, Tout);
+    hipLaunchKernelGGL(k_gsum64, dim3((unsigned)((nb * kPanel + 255) / 256)), dim3(256), 0, P.stream, part, nsplit,
+                       nb, G64);
+    hipLaunchKernelGGL(k_build_t, dim3(1), dim3(256), 0, P.stream, G64, 1, nb, tau, Tout);
   };
   for (int64_t col0 = 0; col0 < n; col0 += kOuter) {
     const int nbo = (int)std::min<int64_t>(kOuter, n - col0);
     const int nsp = (nbo + kPanel - 1) / kPanel;
     const int M = (int)(s - col0);
+    const int Mv = (M + 1) & ~1;  // leading dimension of V: even, so that row pairs load as 16 bytes
     // V columns of sub-panels beyond the last one stay zero
-    if (nsp < 4) zero_block(Vb, M, nsp * kPanel, (4 - nsp) * kPanel, M);
+    if (nsp < 4) zero_block(Vb, Mv, nsp * kPanel, (4 - nsp) * kPanel, M);
     if (nsp < 4) fill(T64 + (size_t)nsp * kPanel * kPanel, (int64_t)(4 - nsp) * kPanel * kPanel);
     int nbs[4] = {0, 0, 0, 0};
     for (int sp = 0; sp < nsp; ++sp) {
@@ -818,10 +871,10 @@ void qr_factor(Problem& P) {
       const int Msp = M - sp * kPanel;
       const int nbsp = std::min(kPanel, nbo - sp * kPanel);
       nbs[sp] = nbsp;
-      double* Vsp = Vb + (int64_t)sp * kPanel * M + sp * kPanel;
-      if (sp > 0) zero_block(Vb, M, sp * kPanel, kPanel, sp * kPanel);
-      launch_panel(P, B + c_sp * s + c_sp, s, Msp, nbsp, P.d_tau.p + c_sp, Pp, DR, Vsp, M);
-      gram_t(Vsp, M, Msp, nbsp, P.d_tau.p + c_sp, T64 + (size_t)sp * kPanel * kPanel);
+      double* Vsp = Vb + (int64_t)sp * kPanel * Mv + sp * kPanel;
+      if (sp > 0) zero_block(Vb, Mv, sp * kPanel, kPanel, sp * kPanel);
+      launch_panel(P, B + c_sp * s + c_sp, s, Msp, nbsp, P.d_tau.p + c_sp, Pp, DR, Vsp, Mv);
+      gram_t(Vsp, Mv, Msp, nbsp, P.d_tau.p + c_sp, T64 + (size_t)sp * kPanel * kPanel);
       const int Nr = nbo - (sp + 1) * kPanel;
       if (Nr > 0) {
         // apply this sub-panel's reflectors to the rest of the outer panel
@@ -829,11 +882,11 @@ void qr_factor(Problem& P) {
         int nsplit, krange;
         tn_split(Msp, (Nr + 63) / 64, ncu, 64, &nsplit, &krange);
         hipLaunchKernelGGL(k_gemm_tn, dim3((unsigned)((Nr + 63) / 64), nsplit), dim3(256), 0, P.stream, Vsp,
-                           (int64_t)M, Cr, s, Msp, Nr, krange, part);
+                           (int64_t)Mv, Cr, s, Msp, Nr, krange, part);
         hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((Nr + 3) / 4)), dim3(256), 0, P.stream, part, nsplit, Nr,
                            T64 + (size_t)sp * kPanel * kPanel, W2);
         hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((Msp + 63) / 64), (unsigned)((Nr + 63) / 64)), dim3(256), 0,
-                           P.stream, Cr, s, Vsp, (int64_t)M, W2, Msp, Nr, kPanel);
+                           P.stream, Cr, s, Vsp, (int64_t)Mv, W2, Msp, Nr, kPanel);
       }
     }
     // T of the 256 reflectors: pairs of 64-blocks into 128-blocks, then the two 128-blocks
@@ -844,11 +897,13 @@ void qr_factor(Problem& P) {
       if (nbs[b] > 0) {
         tn_split(Kab, 1, ncu, 64, &nsplit_ab, &krange);
         hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit_ab), dim3(256), 0, P.stream,
-                           Vb + (int64_t)a * kPanel * M + b * kPanel, (int64_t)M,
-                           Vb + (int64_t)b * kPanel * M + b * kPanel, (int64_t)M, Kab, nbs[b], krange, part);
+                           Vb + (int64_t)a * kPanel * Mv + b * kPanel, (int64_t)Mv,
+                           Vb + (int64_t)b * kPanel * Mv + b * kPanel, (int64_t)Mv, Kab, nbs[b], krange, part);
+        hipLaunchKernelGGL(k_gsum64, dim3((unsigned)((nbs[b] * kPanel + 255) / 256)), dim3(256), 0, P.stream, part,
+                           nsplit_ab, nbs[b], G64);
       }
       hipLaunchKernelGGL(k_combine_t, dim3(1), dim3(256), 0, P.stream, T64 + (size_t)a * kPanel * kPanel,
-                         T64 + (size_t)b * kPanel * kPanel, part, nsplit_ab, nbs[b], T128 + (size_t)pr * kBig * kBig);
+                         T64 + (size_t)b * kPanel * kPanel, G64, 1, nbs[b], T128 + (size_t)pr * kBig * kBig);
     }
     {
       // G = V01^T V23 over rows 128..M-1 (V23 is zero above row 128)
@@ -858,8 +913,8 @@ void qr_factor(Problem& P) {
         tn_split(K2, 1, ncu, max_split, &nsplit, &krange);
         krange = (krange + kKC - 1) / kKC * kKC;
         nsplit = (K2 + krange - 1) / krange;
-        hipLaunchKernelGGL(k_gemm_tn128, dim3(1, 1, nsplit), dim3(256), 0, P.stream, Vb + kBig, (int64_t)M,
-                           Vb + (int64_t)kBig * M + kBig, (int64_t)M, K2, kBig, krange, part, kBig);
+        hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(1, 1, nsplit), dim3(256), 0, P.stream, Vb + kBig, (int64_t)Mv,
+                           Vb + (int64_t)kBig * Mv + kBig, (int64_t)Mv, K2, kBig, krange, part, kBig);
         hipLaunchKernelGGL(k_gsum128, dim3(kBig * kBig / 256), dim3(256), 0, P.stream, part, nsplit, G128);
       } else {
         fill(G128, (int64_t)kBig * kBig);  // no reflectors past column 128 in this block
@@ -882,8 +937,14 @@ void qr_factor(Problem& P) {
       {
         ProfScope ps(P.prof, P.stream, "qr_gemm_tn", 2.0 * M * (double)N * kOuter,
                      8.0 * (2.0 * M * N + (double)M * kOuter + (double)nsplit * N * kOuter));
-        hipLaunchKernelGGL(k_gemm_tn128, dim3(2, ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)M, C, s, M,
-                           (int)N, krange, part, kOuter);
+        // 16-byte loads of C need an even leading dimension and an aligned first column
+        const bool vec = (s % 2 == 0) && (reinterpret_cast<uintptr_t>(C) % 16 == 0);
+        if (vec)
+          hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(2, ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)Mv, C, s,
+                             M, (int)N, krange, part, kOuter);
+        else
+          hipLaunchKernelGGL(k_gemm_tn128<false>, dim3(2, ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)Mv, C,
+                             s, M, (int)N, krange, part, kOuter);
       }
       hipLaunchKernelGGL(k_reduce_w256, dim3((unsigned)((N + 7) / 8)), dim3(256), 0, P.stream, part, nsplit, (int)N,
                          T256, W2);
@@ -891,7 +952,7 @@ void qr_factor(Problem& P) {
         ProfScope ps(P.prof, P.stream, "qr_gemm_nn", 2.0 * M * (double)N * kOuter,
                      8.0 * (2.0 * M * N + (double)M * kOuter + (double)N * kOuter));
         hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)ntile), dim3(256), 0,
-                           P.stream, C, s, Vb, (int64_t)M, W2, (int64_t)kOuter, M, (int)N, kOuter);
+                           P.stream, C, s, Vb, (int64_t)Mv, W2, (int64_t)kOuter, M, (int)N, kOuter);
       }
     }
     RFM_HIP(hipGetLastError());

@@ -166,6 +166,24 @@ def test_qr_invariants_and_conditioning(case):
     assert sv[0] / sv[-1] < 12.0
 
 
+def test_qr_with_odd_sketch_rows(case):
+    """s = 2n + 1: odd leading dimensions take the QR's unaligned load paths."""
+    lp, DJ = case["lp"], case["DJ"]
+    gamma = (2 * lp.n + 0.5) / lp.n
+    lp.stage_assemble(case["u"], 100.0)
+    lp.stage_sketch(gamma, 1, 0, R.RFM_PREC_F64)
+    assert lp.s == 2 * lp.n + 1 == O.sketch_rows(lp.n, gamma)
+    B = lp.get_sketch_cols(0, lp.n)
+    assert _relerr(B, O.sketch(DJ, lp.s, 1, 0)) < 1e-12
+    lp.stage_qr()
+    Rg = lp.get_r_cols(0, lp.n)
+    assert np.array_equal(np.tril(Rg, -1), np.zeros_like(Rg))
+    assert np.all(np.diag(Rg) > 0)
+    G = B.T @ B
+    assert np.abs(Rg.T @ Rg - G).max() < 1e-12 * np.abs(G).max()
+    assert _relerr(Rg, O.qr_r(B)) < max(1e-12, 1e-15 * np.linalg.cond(B))
+
+
 def test_triangular_solves(case):
     lp = case["lp"]
     lp.stage_assemble(case["u"], 100.0)
