@@ -5,10 +5,10 @@
 // Blocked right-looking algorithm with panels of ib <= 64 columns:
 //  1. k_panel: one cooperative launch factors the panel column by column.  Each
 //     workgroup keeps a contiguous chunk of the panel's rows in registers
-//     (thread (rg, c) holds rows rg, rg+4, ... of column c).  A column costs one
-//     grid barrier: the per-workgroup partial sums (sigma = ||x||^2 below the
-//     diagonal and g_c = x^T a_c) are published, every workgroup reduces them in
-//     the same fixed order and applies the reflector to its rows.  The reflector
+//     (thread (rg, c) holds rows rg, rg+8, ... of column c).  Per column the
+//     per-workgroup partial sums (sigma = ||x||^2 below the diagonal and
+//     g_c = x^T a_c) are published at a grid barrier and reduced in a fixed
+//     order; every workgroup then applies the reflector to its rows.  The reflector
 //     follows the usual convention H = I - tau v v^T, v_0 = 1,
 //     beta = -sign(alpha) ||(alpha, x)||.
 //  2. The Gram V^T V (k_gemm_tn) and the compact-WY factor T (k_build_t), with
@@ -51,6 +51,13 @@ __device__ __forceinline__ double ld_dev(const double* p) {
 __device__ __forceinline__ void st_dev(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// value of v in lane k (uniform k) for every lane of the wavefront
+__device__ __forceinline__ double bcast_lane(double v, int k) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, k);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), k);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
 
 // Grid barrier without atomics: workgroup g publishes its phase in its own word
 // (after its data stores are acknowledged); thread t < G polls word t.  Arrival
@@ -84,83 +91,115 @@ __global__ void k_reset_sync(int32_t* sync) {
 }
 
 // Panel factorisation.  A: panel top-left (rows col0.., leading dimension ld),
-// M rows, nb <= 64 columns; chunk rows per workgroup; RPT >= ceil(chunk / 4).
+// M rows, nb <= 64 columns; chunk rows per workgroup; RPT >= ceil(chunk / 8).
 // P: partial-sum buffer [2][G][64] (G <= 256), DR: diagonal rows [2][64] then column totals [2][64].
 // Writes V below the diagonal and R on/above it in place, tau[nb], and the unit
 // lower-trapezoidal V into Vb (M x 64, leading dimension ldv).
-template <int RPT>
-__global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t ld, int M, int nb, int chunk,
+// Thread (rg, c), rg < 8, holds rows rg, rg + 8, ... of column c of its chunk, so wavefront rg
+// holds whole rows and lane j holds column j: the entries x_i of column j reach the other lanes
+// by readlane, and the row tests (above, at or below row j) are uniform in the wavefront.  Per
+// column j: partial sums x^T a_c below the diagonal, a grid-wide fixed-order reduction, then
+// a_c -= tau w_c v with the Householder vector v (1 at row j, x sc below).
+// ONE_BARRIER: every workgroup sums all partials itself (loads first, then a fixed-order sum);
+// otherwise one workgroup per column sums them, publishes the total, and a second barrier follows.
+template <int RPT, bool ONE_BARRIER>
+__global__ void __launch_bounds__(512) k_panel(double* __restrict__ A, int64_t ld, int M, int nb, int chunk,
                                                double* __restrict__ tau, double* __restrict__ P,
                                                double* __restrict__ DR, double* __restrict__ Vb, int64_t ldv,
                                                int32_t* __restrict__ sync) {
-  __shared__ double colj[4][RPT];
-  __shared__ double red[4][kPanel];
+  constexpr int NRG = 8;
+  __shared__ double red[NRG][kPanel];
   __shared__ double scal_sh[4];
-  __shared__ double wsum[4];
+  __shared__ double sa_sh[2];
   const int G = gridDim.x, g = blockIdx.x;
-  const int c = threadIdx.x % kPanel, rg = threadIdx.x / kPanel;
+  const int c = threadIdx.x % kPanel, rg = __builtin_amdgcn_readfirstlane(threadIdx.x / kPanel);  // uniform
   const int r0 = g * chunk;
   const int rend = min(M, r0 + chunk);
   int phase = 0;
 
+  // this wavefront's row i is r0 + rg + 8 i, a row of the chunk for i < nrow (uniform)
+  const int nrow = max(0, min(RPT, (rend - r0 - rg + NRG - 1) / NRG));
   double a[RPT];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int pr = r0 + rg + 4 * i;
-    a[i] = (c < nb && pr < rend) ? A[(int64_t)c * ld + pr] : 0.0;
-  }
+  for (int i = 0; i < RPT; ++i) a[i] = (c < nb && i < nrow) ? A[(int64_t)c * ld + r0 + rg + NRG * i] : 0.0;
 
   for (int j = 0; j < nb; ++j) {
     const int buf = j & 1;
     double* Pb = P + (size_t)buf * G * kPanel;
     double* DRb = DR + (size_t)buf * kPanel;
     double* TOTb = DR + (size_t)(2 + buf) * kPanel;
-    // column j of this chunk to LDS
-    if (c == j) {
+    // rows below row j from i = ilo on, row j itself at i = idiag (or nowhere): uniform, so the
+    // row tests are scalar compares against constants
+    const int dj = j - r0 - rg;
+    const int ilo = dj < 0 ? 0 : dj / NRG + 1;
+    const int idiag = (dj >= 0 && dj % NRG == 0 && dj / NRG < nrow) ? dj / NRG : -1;
+    // the diagonal row, published by the wavefront that holds it
+    if (idiag >= 0 && c >= j && c < nb) {
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) colj[rg][i] = a[i];
+      for (int i = 0; i < RPT; ++i)
+        if (i == idiag) st_dev(&DRb[c], a[i]);
     }
-    __syncthreads();
-    // partials over rows strictly below the diagonal
+    // partial sums over the rows below the diagonal (rows past the chunk hold 0)
     double part = 0.0;
-    if (c >= j && c < nb) {
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int pr = r0 + rg + 4 * i;
-        if (pr > j && pr < rend) part += colj[rg][i] * a[i];
+    for (int i = 0; i < RPT; ++i)
+      if (i >= ilo) part += bcast_lane(a[i], j) * a[i];
+    red[rg][c] = part;
+    __syncthreads();
+    if (rg == 0 && c >= j && c < nb)
+      st_dev(&Pb[(size_t)g * kPanel + c], ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) +
+                                              ((red[4][c] + red[5][c]) + (red[6][c] + red[7][c])));
+    grid_barrier(sync, G, phase);
+    double gc = 0.0, ajc = 0.0;
+    if (ONE_BARRIER) {
+      // partials of workgroups rg, rg + 8, ... (G <= 256): all loads in flight, then the sums
+      if (c >= j && c < nb) {
+        double v[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+          const int gg = rg + NRG * k;
+          v[k] = gg < G ? ld_dev(&Pb[(size_t)gg * kPanel + c]) : 0.0;
+        }
+        ajc = ld_dev(&DRb[c]);
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 32; k += 2) {
+          s0 += v[k];
+          s1 += v[k + 1];
+        }
+        gc = s0 + s1;
+      }
+      red[rg][c] = gc;
+      __syncthreads();
+      gc = ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) + ((red[4][c] + red[5][c]) + (red[6][c] + red[7][c]));
+    } else {
+      // workgroup g sums columns j + g, j + g + G, ... in a fixed order and publishes the totals
+      for (int cc = g; cc < nb - j; cc += G) {
+        const int col = j + cc;
+        double v = (int)threadIdx.x < G ? ld_dev(&Pb[(size_t)threadIdx.x * kPanel + col]) : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][0] = v;
+        __syncthreads();
+        if (threadIdx.x == 0)
+          st_dev(&TOTb[col], ((red[0][0] + red[1][0]) + (red[2][0] + red[3][0])) +
+                                 ((red[4][0] + red[5][0]) + (red[6][0] + red[7][0])));
+        __syncthreads();
+      }
+      grid_barrier(sync, G, phase);
+      if (c >= j && c < nb) {
+        gc = ld_dev(&TOTb[c]);
+        ajc = ld_dev(&DRb[c]);
       }
     }
-    red[rg][c] = part;
-    // the diagonal row
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int pr = r0 + rg + 4 * i;
-      if (pr == j && pr < rend && c >= j && c < nb) st_dev(&DRb[c], a[i]);  // only the owning chunk publishes
+    if (threadIdx.x == j) {
+      sa_sh[0] = gc;   // sigma
+      sa_sh[1] = ajc;  // alpha
     }
-    __syncthreads();
-    if (rg == 0 && c >= j && c < nb) st_dev(&Pb[(size_t)g * kPanel + c], (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]));
-    grid_barrier(sync, G, phase);
-    // stage 1: workgroup g reduces columns j + g, j + g + G, ... over all workgroups'
-    // partials in a fixed order and publishes the totals
-    for (int cc = g; cc < nb - j; cc += G) {
-      const int col = j + cc;
-      double v = threadIdx.x < G ? ld_dev(&Pb[(size_t)threadIdx.x * kPanel + col]) : 0.0;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
-      __syncthreads();
-      if (threadIdx.x == 0) st_dev(&TOTb[col], (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]));
-      __syncthreads();
-    }
-    grid_barrier(sync, G, phase);
-    // stage 2: every workgroup reads the column totals it needs
-    double gc = 0.0;
-    if (c >= j && c < nb) gc = ld_dev(&TOTb[c]);
-    if (threadIdx.x == j) red[0][j] = gc;
     __syncthreads();
     if (threadIdx.x == 0) {
-      const double sigma = red[0][j];
-      const double alpha = ld_dev(&DRb[j]);
+      const double sigma = sa_sh[0];
+      const double alpha = sa_sh[1];
       double beta, t, sc;
       if (sigma == 0.0) {
         beta = alpha;
@@ -178,22 +217,20 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t l
     }
     __syncthreads();
     const double beta = scal_sh[0], t = scal_sh[1], sc = scal_sh[2];
-    if (c > j && c < nb) {
-      const double ajc = ld_dev(&DRb[c]);
-      const double wc = ajc + gc * sc;
-      const double tw = t * wc;
+    // a_c -= tau w_c v for c > j; column j itself becomes (beta, v).  The empty asm keeps the
+    // compiler from carrying the partial phase's broadcasts of column j over the barrier in SGPRs.
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int pr = r0 + rg + 4 * i;
-        if (pr > j && pr < rend) a[i] -= tw * (colj[rg][i] * sc);
-        else if (pr == j && pr < rend) a[i] -= tw;
-      }
-    } else if (c == j) {
+    for (int i = 0; i < RPT; ++i) asm volatile("" : "+v"(a[i]));
+    const double tw = t * (ajc + gc * sc);
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int pr = r0 + rg + 4 * i;
-        if (pr > j && pr < rend) a[i] = colj[rg][i] * sc;
-        else if (pr == j && pr < rend) a[i] = beta;
+    for (int i = 0; i < RPT; ++i) {
+      if (i >= ilo) {
+        const double v = bcast_lane(a[i], j) * sc;
+        if (c == j) a[i] = v;
+        else if (c > j) a[i] -= tw * v;
+      } else if (i == idiag) {
+        if (c == j) a[i] = beta;
+        else if (c > j) a[i] -= tw;
       }
     }
     __syncthreads();
@@ -201,8 +238,8 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t l
   // write back and emit the explicit V
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int pr = r0 + rg + 4 * i;
-    if (pr < rend) {
+    if (i < nrow) {
+      const int pr = r0 + rg + NRG * i;
       if (c < nb) A[(int64_t)c * ld + pr] = a[i];
       double v = 0.0;
       if (c < nb) v = pr > c ? a[i] : (pr == c ? 1.0 : 0.0);
@@ -769,17 +806,20 @@ int num_cus(int device) {
   return g_num_cus;
 }
 
+// one barrier per column (every workgroup reduces all partials) or two (one reducer per column)
+constexpr bool kPanelOneBarrier = true;
+
 template <int RPT>
 void launch_panel_t(Problem& P, dim3 grid, double* A, int64_t ld, int M, int nb, int chunk, double* tau, double* Pp,
                     double* DR, double* Vb, int64_t ldv) {
   int32_t* sync = P.d_sync.p;
   void* args[] = {&A, &ld, &M, &nb, &chunk, &tau, &Pp, &DR, &Vb, &ldv, &sync};
+  const void* fn = reinterpret_cast<const void*>(&k_panel<RPT, kPanelOneBarrier>);
   int maxb = 0;
-  RFM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxb, reinterpret_cast<const void*>(&k_panel<RPT>), 256, 0));
+  RFM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxb, fn, 512, 0));
   RFM_CHECK((int64_t)maxb * num_cus(P.device) >= (int64_t)grid.x, RFM_EDEVICE,
             "QR panel: workgroups cannot all be resident");
-  RFM_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_panel<RPT>), grid, dim3(256), args, 0,
-                                     P.stream));
+  RFM_HIP(hipLaunchCooperativeKernel(fn, grid, dim3(512), args, 0, P.stream));
 }
 
 void launch_panel(Problem& P, double* A, int64_t ld, int M, int nb, double* tau, double* Pp, double* DR, double* Vb,
@@ -787,16 +827,16 @@ void launch_panel(Problem& P, double* A, int64_t ld, int M, int nb, double* tau,
   const int ncu = num_cus(P.device);
   int G = std::max(1, std::min(std::min(ncu, 256), (M + 63) / 64));
   int chunk = (M + G - 1) / G;
-  const int need = (chunk + 3) / 4;
+  const int need = (chunk + 7) / 8;
   hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(256), 0, P.stream, P.d_sync.p);
   ProfScope ps(P.prof, P.stream, "qr_panel", 4.0 * M * (double)nb * nb, 16.0 * M * (double)nb);
   dim3 grid(G);
-  if (need <= 16) launch_panel_t<16>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
+  if (need <= 8) launch_panel_t<8>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
+  else if (need <= 16) launch_panel_t<16>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
+  else if (need <= 24) launch_panel_t<24>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
   else if (need <= 32) launch_panel_t<32>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
-  else if (need <= 48) launch_panel_t<48>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
-  else if (need <= 64) launch_panel_t<64>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
-  else if (need <= 80) launch_panel_t<80>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
-  else if (need <= 104) launch_panel_t<104>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
+  else if (need <= 40) launch_panel_t<40>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
+  else if (need <= 52) launch_panel_t<52>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
   else throw Error(RFM_EINVAL, "QR panel: too many rows per workgroup (sketch too tall)");
 }
 

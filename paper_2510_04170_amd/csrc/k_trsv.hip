@@ -1,14 +1,36 @@
 // Triangular solves with the preconditioner R (Alg. 1 steps 3-5): x = R^{-1} y
 // and x = R^{-T} y, R stored as 64 x 64 column-major tiles of its upper triangle.
 //
-// One launch of nb = ceil(n / 64) workgroups.  A workgroup takes a ticket from
-// an atomic counter and solves row block i = nb-1-ticket (R x = y) or
-// i = ticket (R^T x = y).  It streams its off-diagonal tiles as soon as the
-// block of x they multiply is published, then solves the 64 x 64 diagonal
-// block by substitution in LDS and publishes its own block (data, release
-// fence, per-block flag = epoch).  A workgroup only waits for blocks held by
-// workgroups with smaller tickets, which are already running, so the launch
-// always drains; a spin limit turns a lost flag into an error instead of a hang.
+// The solve is a chain over the nb = ceil(n / 64) blocks of x (R x = y from the
+// last block up, R^T x = y from the first block down): block i needs every
+// block before it in chain order.  One launch of nb + 1 workgroups; each takes
+// a ticket from an atomic counter.
+//  * Ticket 0 is the solver.  It walks the whole chain and keeps the blocks it
+//    solved in LDS, so no step of the chain waits for another workgroup's
+//    stores: per block it applies the kLook = 2 tiles next to the diagonal,
+//    subtracts the helpers' partial sum for the block, solves the 64 x 64
+//    diagonal tile by substitution in LDS and publishes the block (data, then a
+//    flag).  Its eight wavefronts: 0 solves and publishes, with its row of the
+//    diagonal tile in registers (the substitution is the chain's longest part);
+//    1-3 and 4-6 are two sets that hold the two off-diagonal tiles and the
+//    diagonal tile of even and odd steps in registers, each set loading its next
+//    step two steps ahead.  Only the product with the block solved last is left
+//    between two substitutions: the product with the block before it and the
+//    diagonal tile's copy to LDS are done a step early.  Wavefront 7 fetches the
+//    helper partial of the next step (alone, so that its polls do not wait
+//    behind tile loads).
+//  * Ticket t >= 1 is the helper of block t-th in chain order: it streams the
+//    rest of that block's row (R) or column (R^T) of tiles as the solver
+//    publishes the blocks they multiply, and publishes the partial sum.  It
+//    needs blocks up to kLook + 1 steps behind the one it serves, so the solver
+//    finds the partial ready.
+// Published data and flags are written and read with device-scope relaxed
+// atomics (coherent across the XCDs' L2s); a writer waits for its data stores
+// to be acknowledged before it stores the flag, and flags hold the epoch of
+// the launch.  Workgroups only wait for work of smaller tickets (the solver
+// waits for helpers of blocks whose dependencies it has already published,
+// and helpers start in the order the solver needs them), so the launch always
+// drains; a spin limit turns a lost flag into an error instead of a hang.
 //
 // Optional fusion for LSQR: out = yscale-scaled solve minus coef * sub, and a
 // per-block partial of ||out||^2.
@@ -20,23 +42,24 @@ namespace {
 
 constexpr int kTB = 64;
 constexpr int kSpinLimit = 1 << 26;
-// sync words used here: [8] ticket counter, [9] error flag, [16 ...] block flags
-enum { kTicket = 8, kTrsvErr = 9, kFlags = 16 };
-constexpr int kBatch = 8;  // flags polled per round trip
+constexpr int kLook = 2;   // off-diagonal tiles next to the diagonal applied by the solver
+constexpr int kBatch = 8;  // helper: flags polled per round trip
+// sync words used here: [8] ticket counter, [9] error flag, [kXFlags + b] block b of x published,
+// [kXFlags + nb + b] helper partial of block b published (past the QR's grid-barrier words)
+enum { kTicket = 8, kTrsvErr = 9, kXFlags = 2048 };
 
 __device__ __forceinline__ const double* tile_ptr(const double* Rt, int bi, int bj) {
   return Rt + ((size_t)bj * (bj + 1) / 2 + bi) * kTB * kTB;
 }
 
-// Cross-workgroup handoff without cache maintenance: the published block of x
-// and its flag are written and read with device-scope relaxed atomics (sc1,
-// coherent across the XCDs' L2s); the writer waits for its data stores to be
-// acknowledged before it stores the flag.
 __device__ __forceinline__ double ld_dev(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_dev(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_flag(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void stores_done() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -50,213 +73,303 @@ __device__ __forceinline__ double bcast(double v, int k) {
   return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
-// mode 0: R x = y   (back substitution over row blocks)
-// mode 1: R^T x = y (forward substitution over column blocks)
+// Wait (one wavefront) until flag == epoch; false when the spin limit or another
+// workgroup's error ends the wait.
+__device__ bool wait_flag(const int32_t* flag, int32_t* sync, int32_t epoch) {
+  int spins = 0;
+  while (ld_flag(flag) != epoch) {
+    __builtin_amdgcn_s_sleep(1);
+    if ((++spins & 1023) == 0 && ld_flag(&sync[kTrsvErr]) != 0) return false;
+    if (spins > kSpinLimit) {
+      __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  return true;
+}
+
+// mode 0: R x = y   (chain from the last block up)
+// mode 1: R^T x = y (chain from the first block down)
 template <int MODE>
-__global__ void __launch_bounds__(256) k_trsv(const double* __restrict__ Rt, int n, int nbk,
+__global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int n, int nbk,
                                               const double* __restrict__ y, double* __restrict__ z,
-                                              double* __restrict__ out, const double* __restrict__ sub,
-                                              const LsqrState* __restrict__ st, int yscale_sel, int sub_sel,
-                                              double* __restrict__ partial, int32_t* __restrict__ sync,
-                                              int32_t epoch) {
+                                              double* __restrict__ pz, double* __restrict__ out,
+                                              const double* __restrict__ sub, const LsqrState* __restrict__ st,
+                                              int yscale_sel, int sub_sel, double* __restrict__ partial,
+                                              int32_t* __restrict__ sync, int32_t epoch) {
   if (st && st->done) return;
   __shared__ int tk_sh;
-  __shared__ double Dt[kTB][kTB + 1];
-  __shared__ double rhs[kTB];
-  __shared__ double rdiag[kTB];
-  __shared__ double xs[kBatch][kTB];
+  __shared__ double Dt[2][kTB][kTB + 1];  // solver: diagonal tiles of even and odd steps, [row][col], diagonal zeroed
+  __shared__ double dg[2][kTB];           // solver: their diagonals
+  __shared__ double xs[kBatch][kTB];    // helper: ready blocks of x
+  __shared__ double red[8][kTB];
+  __shared__ double xl[kLook][kTB];     // solver: the last kLook solved blocks (by step parity)
+  __shared__ double pzs[2][kTB];        // solver: helper partials of this and the next step
+  __shared__ double red2[2][kTB];       // solver: product with the block two steps back
   __shared__ int nready_sh;
-  __shared__ double red[4][kTB];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   if (tid == 0) {
     const int t = __hip_atomic_fetch_add(&sync[kTicket], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (t == nbk - 1) __hip_atomic_store(&sync[kTicket], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == nbk) __hip_atomic_store(&sync[kTicket], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     tk_sh = t;
   }
   __syncthreads();
   const int ticket = tk_sh;
-  const int i = MODE == 0 ? nbk - 1 - ticket : ticket;
-  double ysc = 1.0, coef = 0.0;
-  if (st) {
-    ysc = yscale_sel == 1 ? st->inv_alpha : 1.0;
-    coef = sub_sel == 1 ? st->beta * st->inv_alpha : 0.0;
+  constexpr int d = MODE == 0 ? 1 : -1;  // step from a block to the one solved just before it
+  auto blk = [&](int step) { return MODE == 0 ? nbk - 1 - step : step; };
+  int32_t* xflag = sync + kXFlags;
+  int32_t* pflag = sync + kXFlags + nbk;
+
+  if (ticket == 0) {
+    // ------------------------------------------------------------------ solver
+    double ysc = 1.0, coef = 0.0;
+    if (st) {
+      ysc = yscale_sel == 1 ? st->inv_alpha : 1.0;
+      coef = sub_sel == 1 ? st->beta * st->inv_alpha : 0.0;
+    }
+    // wavefronts 1-3 (even steps) and 4-6 (odd steps): role 0 the tile next to the diagonal, 1 the
+    // one after, 2 the diagonal tile; lane l holds row l of the tile as the solve sees it (R, or R^T
+    // in mode 1).  Wavefront 0 keeps row (mode 0) or column (mode 1) `lane` of the current diagonal
+    // tile in the same registers.
+    const int set = (wv - 1) / 3, role = (wv - 1) % 3;
+    const bool tile_wave = wv >= 1 && wv <= 6;
+    double tv[kTB];
+    auto load_tiles = [&](int step) {
+      const int i = blk(step);
+      if (role < 2) {
+        const int ij = i + (role == 0 ? d : 2 * d);
+        const bool has = ij >= 0 && ij < nbk;
+        if (MODE == 0) {
+          const double* T = tile_ptr(Rt, i, has ? ij : i);
+#pragma unroll
+          for (int c = 0; c < kTB; ++c) tv[c] = has ? T[c * kTB + lane] : 0.0;
+        } else {
+          const double* T = tile_ptr(Rt, has ? ij : i, i);
+#pragma unroll
+          for (int r = 0; r < kTB; ++r) tv[r] = has ? T[lane * kTB + r] : 0.0;
+        }
+      } else {
+        const double* T = tile_ptr(Rt, i, i);
+#pragma unroll
+        for (int c = 0; c < kTB; ++c) tv[c] = T[c * kTB + lane];
+      }
+    };
+    auto fetch_partial = [&](int step) {  // wavefront 7
+      const int i = blk(step);
+      wait_flag(&pflag[i], sync, epoch);
+      pzs[step & 1][lane] = ld_dev(&pz[(size_t)i * kTB + lane]);
+    };
+    // tile (registers) times a block of x (LDS, read by every lane): the block is read 16 values
+    // at a time into registers of their own so that the reads overlap
+    auto tile_times = [&](const double* xv) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+      for (int kb = 0; kb < kTB; kb += 16) {
+        double xr[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) xr[q] = xv[kb + q];
+#pragma unroll
+        for (int q = 0; q < 16; q += 4) {
+          a0 += tv[kb + q] * xr[q];
+          a1 += tv[kb + q + 1] * xr[q + 1];
+          a2 += tv[kb + q + 2] * xr[q + 2];
+          a3 += tv[kb + q + 3] * xr[q + 3];
+        }
+      }
+      return (a0 + a1) + (a2 + a3);
+    };
+    auto two_back = [&](int step) {  // role 1 of the set of `step`: its tile times the block of step - 2
+      red2[step & 1][lane] = tile_times(xl[step & 1]);
+    };
+    auto diag_to_lds = [&](int step) {  // role 2 of the set of `step`: tile without its diagonal, and the diagonal
+      double d = 0.0;
+#pragma unroll
+      for (int c = 0; c < kTB; ++c) {
+        Dt[step & 1][lane][c] = c == lane ? 0.0 : tv[c];
+        d = c == lane ? tv[c] : d;
+      }
+      dg[step & 1][lane] = d;
+    };
+    double yv = 0.0, sv = 0.0;
+    if (wv == 0) {
+      xl[0][lane] = 0.0;
+      xl[1][lane] = 0.0;
+      // y (and sub) of the first block; later blocks are prefetched one step ahead
+      const int row = blk(0) * kTB + lane;
+      yv = row < n ? y[row] : 0.0;
+      sv = (sub && row < n) ? sub[row] : 0.0;
+    } else if (tile_wave) {
+      if (set < nbk) load_tiles(set);
+    } else {
+      fetch_partial(0);
+    }
+    __syncthreads();
+    // step 0 has no earlier blocks: only its diagonal tile
+    if (tile_wave && set == 0 && role == 1) red2[0][lane] = 0.0;
+    if (tile_wave && set == 0 && role == 2) diag_to_lds(0);
+    __syncthreads();
+    for (int step = 0; step < nbk; ++step) {
+      const int i = blk(step);
+      const int cur = step & 1;
+      const bool in_set = tile_wave && set == cur;      // tiles of this step
+      const bool in_next = tile_wave && set != cur;     // tiles of the next step
+      double rd = 0.0;
+      if (wv == 0) {
+        // this lane's equation divided by its diagonal entry, the diagonal entry itself dropped:
+        // each unknown is then final when its turn comes, and one FMA per step updates every lane
+        // (lanes already solved, and the pivot lane, multiply a zero)
+#pragma unroll
+        for (int k = 0; k < kTB; ++k) tv[k] = MODE == 0 ? Dt[cur][lane][k] : Dt[cur][k][lane];
+        rd = 1.0 / dg[cur][lane];
+#pragma unroll
+        for (int k = 0; k < kTB; ++k) tv[k] *= rd;
+      } else if (in_set && role == 0) {
+        // the tile next to the diagonal times the block solved last
+        red[1][lane] = tile_times(xl[(step + 1) & 1]);
+      }
+      __syncthreads();
+      if (wv == 0) {
+        double r = (yv * ysc - pzs[cur][lane] - (red[1][lane] + red2[cur][lane])) * rd;
+        if (MODE == 0) {
+#pragma unroll
+          for (int k = kTB - 1; k >= 0; --k) r = fma(-tv[k], bcast(r, k), r);
+        } else {
+#pragma unroll
+          for (int k = 0; k < kTB; ++k) r = fma(-tv[k], bcast(r, k), r);
+        }
+        xl[cur][lane] = r;
+        const int row = i * kTB + lane;
+        st_dev(&z[row], r);  // padded length: nbk * 64
+        const double o = r - coef * sv;
+        if (row < n) out[row] = o;
+        if (partial) {
+          double q = row < n ? o * o : 0.0;
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
+          if (lane == 0) partial[i] = q;
+        }
+        stores_done();
+        if (lane == 0) __hip_atomic_store(&xflag[i], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (step + 1 < nbk) {
+          const int rn = blk(step + 1) * kTB + lane;
+          yv = rn < n ? y[rn] : 0.0;
+          sv = (sub && rn < n) ? sub[rn] : 0.0;
+        }
+      } else if (in_set) {
+        if (step + 2 < nbk) load_tiles(step + 2);
+      } else if (in_next) {
+        // next step: its tile two blocks from the diagonal times the block of step - 1, its diagonal tile to LDS
+        if (step + 1 < nbk) {
+          if (role == 1) two_back(step + 1);
+          else if (role == 2) diag_to_lds(step + 1);
+        }
+      } else if (wv == 7) {
+        if (step + 1 < nbk) fetch_partial(step + 1);
+      }
+      __syncthreads();
+    }
+    return;
   }
 
-  // diagonal tile to LDS first: it does not depend on any other block
-  {
-    const double* T = tile_ptr(Rt, i, i);
-    for (int e = tid; e < kTB * kTB; e += 256) Dt[e % kTB][e / kTB] = T[e];
-  }
-  __syncthreads();
-  if (tid < kTB) rdiag[tid] = 1.0 / Dt[tid][tid];
-
-  // off-diagonal contributions
-  double acc = 0.0;            // MODE 0: row lane of the block, columns quarter wv
-  double accT[16];             // MODE 1: columns wv*16 .. +15, rows lane
+  // -------------------------------------------------------------------- helper
+  // block i; its tiles against blocks j with |j - i| > kLook, in chain order
+  const int i = blk(ticket - 1);
+  const int jstop = i + (kLook + 1) * d;  // last block in chain order this helper needs
+  double acc = 0.0;            // MODE 0: row lane of the block, columns wv*8 .. +7
+  double accT[8];              // MODE 1: columns wv*8 .. +7, rows lane
 #pragma unroll
-  for (int q = 0; q < 16; ++q) accT[q] = 0.0;
-  // the tile multiplying the block this one waits for last sits on the critical
-  // path: load this thread's 16 values of it before any waiting
-  double tl[16];
+  for (int q = 0; q < 8; ++q) accT[q] = 0.0;
+  // the tile multiplying the block this one waits for last: load this thread's 8 values first
+  double tl[8];
   {
-    const int jl = MODE == 0 ? i + 1 : i - 1;
-    const bool has = MODE == 0 ? jl < nbk : jl >= 0;
-    const double* T = has ? (MODE == 0 ? tile_ptr(Rt, i, jl) : tile_ptr(Rt, jl, i)) : nullptr;
+    const bool has = jstop >= 0 && jstop < nbk;
+    const double* T = MODE == 0 ? tile_ptr(Rt, i, has ? jstop : i) : tile_ptr(Rt, has ? jstop : i, i);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) tl[q] = has ? T[(wv * 16 + q) * kTB + lane] : 0.0;
+    for (int q = 0; q < 8; ++q) tl[q] = has ? T[(wv * 8 + q) * kTB + lane] : 0.0;
   }
-  // Blocks of x become ready in chain order.  Per step, wavefront 0 polls the
+  // Blocks of x become ready in chain order.  Per round, wavefront 0 polls the
   // flags of up to kBatch upcoming blocks in one round trip, loads every ready
-  // block once into LDS, and all four wavefronts then stream those tiles.
-  if (MODE == 0) {
-    int j = nbk - 1;
-    while (j > i) {
-      if (wv == 0) {
-        const int cnt = min(kBatch, j - i);
-        int ready = 0;
-        int spins = 0;
-        while (true) {
-          int ok = 0;  // lanes past cnt count as not ready, so ~bal has a set bit at or below cnt
-          if (lane < cnt) ok = __hip_atomic_load(&sync[kFlags + j - lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
-          const unsigned long long bal = __ballot(ok);
-          ready = __builtin_ctzll(~bal);  // leading run of ready blocks j, j-1, ...
-          if (ready > cnt) ready = cnt;
-          if (ready > 0) break;
-          __builtin_amdgcn_s_sleep(1);
-          if ((++spins & 1023) == 0 && __hip_atomic_load(&sync[kTrsvErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            ready = cnt;
-            break;
-          }
-          if (spins > kSpinLimit) {
-            __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ready = cnt;
-            break;
-          }
+  // block once into LDS, and all eight wavefronts then stream those tiles.
+  int j = MODE == 0 ? nbk - 1 : 0;
+  while (MODE == 0 ? j >= jstop : j <= jstop) {
+    if (wv == 0) {
+      const int cnt = min(kBatch, MODE == 0 ? j - jstop + 1 : jstop - j + 1);
+      int ready = 0;
+      int spins = 0;
+      while (true) {
+        int ok = 0;  // lanes past cnt count as not ready, so ~bal has a set bit at or below cnt
+        if (lane < cnt) ok = ld_flag(&xflag[j + d * -lane]) == epoch;
+        const unsigned long long bal = __ballot(ok);
+        ready = __builtin_ctzll(~bal);  // leading run of ready blocks in chain order
+        if (ready > cnt) ready = cnt;
+        if (ready > 0) break;
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 1023) == 0 && ld_flag(&sync[kTrsvErr]) != 0) {
+          ready = cnt;
+          break;
         }
-        double xv[kBatch];
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) xv[b] = b < ready ? ld_dev(&z[(size_t)(j - b) * kTB + lane]) : 0.0;
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) xs[b][lane] = xv[b];
-        if (lane == 0) nready_sh = ready;
-      }
-      __syncthreads();
-      const int ready = nready_sh;
-      for (int b = 0; b < ready; ++b) {
-        if (j - b == i + 1) {
-#pragma unroll
-          for (int q = 0; q < 16; ++q) acc += tl[q] * xs[b][wv * 16 + q];
-        } else {
-          const double* T = tile_ptr(Rt, i, j - b);
-#pragma unroll
-          for (int c = wv * 16; c < wv * 16 + 16; ++c) acc += T[c * kTB + lane] * xs[b][c];
+        if (spins > kSpinLimit) {
+          __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ready = cnt;
+          break;
         }
       }
-      __syncthreads();
-      j -= ready;
+      double xv[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) xv[b] = b < ready ? ld_dev(&z[(size_t)(j - d * b) * kTB + lane]) : 0.0;
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) xs[b][lane] = xv[b];
+      if (lane == 0) nready_sh = ready;
     }
-  } else {
-    int j = 0;
-    while (j < i) {
-      if (wv == 0) {
-        const int cnt = min(kBatch, i - j);
-        int ready = 0;
-        int spins = 0;
-        while (true) {
-          int ok = 0;  // lanes past cnt count as not ready, so ~bal has a set bit at or below cnt
-          if (lane < cnt) ok = __hip_atomic_load(&sync[kFlags + j + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
-          const unsigned long long bal = __ballot(ok);
-          ready = __builtin_ctzll(~bal);
-          if (ready > cnt) ready = cnt;
-          if (ready > 0) break;
-          __builtin_amdgcn_s_sleep(1);
-          if ((++spins & 1023) == 0 && __hip_atomic_load(&sync[kTrsvErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            ready = cnt;
-            break;
-          }
-          if (spins > kSpinLimit) {
-            __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ready = cnt;
-            break;
-          }
+    __syncthreads();
+    const int ready = nready_sh;
+    for (int b = 0; b < ready; ++b) {
+      const int jb = j - d * b;
+      if (MODE == 0) {
+        if (jb == jstop) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc += tl[q] * xs[b][wv * 8 + q];
+        } else {
+          const double* T = tile_ptr(Rt, i, jb);
+#pragma unroll
+          for (int c = wv * 8; c < wv * 8 + 8; ++c) acc += T[c * kTB + lane] * xs[b][c];
         }
-        double xv[kBatch];
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) xv[b] = b < ready ? ld_dev(&z[(size_t)(j + b) * kTB + lane]) : 0.0;
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) xs[b][lane] = xv[b];
-        if (lane == 0) nready_sh = ready;
-      }
-      __syncthreads();
-      const int ready = nready_sh;
-      for (int b = 0; b < ready; ++b) {
+      } else {
         const double zl = xs[b][lane];
-        if (j + b == i - 1) {
+        if (jb == jstop) {
 #pragma unroll
-          for (int q = 0; q < 16; ++q) accT[q] += tl[q] * zl;
+          for (int q = 0; q < 8; ++q) accT[q] += tl[q] * zl;
         } else {
-          const double* T = tile_ptr(Rt, j + b, i);
+          const double* T = tile_ptr(Rt, jb, i);
 #pragma unroll
-          for (int q = 0; q < 16; ++q) accT[q] += T[(wv * 16 + q) * kTB + lane] * zl;
+          for (int q = 0; q < 8; ++q) accT[q] += T[(wv * 8 + q) * kTB + lane] * zl;
         }
       }
-      __syncthreads();
-      j += ready;
     }
+    __syncthreads();
+    j -= d * ready;
   }
-  // combine: red[wv][row]
+  // combine: red[wv][row] (mode 0) or red[0][column] (mode 1)
   if (MODE == 0) {
     red[wv][lane] = acc;
   } else {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < 8; ++q) {
       double v = accT[q];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == q) red[0][wv * 16 + q] = v;
+      if (lane == q) red[0][wv * 8 + q] = v;
     }
   }
   __syncthreads();
-  if (tid < kTB) {
-    const int row = i * kTB + tid;
-    const double yv = row < n ? y[row] * ysc : 0.0;
-    const double s = MODE == 0 ? (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]) : red[0][tid];
-    rhs[tid] = yv - s;
-  }
-  __syncthreads();
-  // substitution inside the diagonal tile, one wavefront
   if (wv == 0) {
-    double r = rhs[lane];
-    if (MODE == 0) {
-#pragma unroll
-      for (int k = kTB - 1; k >= 0; --k) {
-        const double xk = bcast(r, k) * rdiag[k];
-        if (lane == k) r = xk;
-        else if (lane < k) r -= Dt[lane][k] * xk;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < kTB; ++k) {
-        const double xk = bcast(r, k) * rdiag[k];
-        if (lane == k) r = xk;
-        else if (lane > k) r -= Dt[k][lane] * xk;
-      }
-    }
-    const int row = i * kTB + lane;
-    st_dev(&z[row], r);  // padded length: nbk * 64
-    double o = r;
-    if (sub && row < n) o = r - coef * sub[row];
-    if (row < n) out[row] = o;
-    if (partial) {
-      double q = row < n ? o * o : 0.0;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
-      if (lane == 0) partial[i] = q;
-    }
-  }
-  if (wv == 0) {
+    double v = red[0][lane];
+    if (MODE == 0)
+      v = ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) +
+          ((red[4][lane] + red[5][lane]) + (red[6][lane] + red[7][lane]));
+    st_dev(&pz[(size_t)i * kTB + lane], v);
     stores_done();
-    if (lane == 0) __hip_atomic_store(&sync[kFlags + i], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) __hip_atomic_store(&pflag[i], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -281,19 +394,21 @@ void check_trsv_error(Problem& P) {
 void launch_trsv(Problem& P, const double* y, double* x, bool transpose, const double* sub_vec,
                  const LsqrState* st, int yscale_sel, int sub_sel, double* red_partials) {
   const int nbk = (int)((P.n + kTB - 1) / kTB);
-  RFM_CHECK(kFlags + nbk <= (int)P.d_sync.n, RFM_EINVAL, "triangular solve: too many blocks");
-  double* z = P.d_vec.p + 4 * std::max(P.m, P.n);  // padded solution (nbk * 64 <= n + 63)
-  RFM_CHECK(4 * std::max(P.m, P.n) + (int64_t)nbk * kTB <= (int64_t)P.d_vec.n, RFM_EINVAL, "scratch too small");
+  RFM_CHECK((int64_t)kXFlags + 2 * (int64_t)nbk <= (int64_t)P.d_sync.n, RFM_EINVAL,
+            "triangular solve: too many blocks");
+  P.d_trsv.resize((size_t)2 * nbk * kTB);
+  double* z = P.d_trsv.p;                     // published blocks of x, nbk * 64
+  double* pz = P.d_trsv.p + (size_t)nbk * kTB;  // helper partials, nbk * 64
   const double nn = (double)P.n;
   ProfScope ps(P.prof, P.stream, "trsv", nn * nn, 8.0 * (nn * (nn + 1) / 2 + 3 * nn));
   int32_t epoch = (int32_t)(++P.trsv_epoch & 0x7fffffff);
   if (epoch == 0) epoch = (int32_t)(++P.trsv_epoch & 0x7fffffff);
   if (transpose)
-    hipLaunchKernelGGL(k_trsv<1>, dim3(nbk), dim3(256), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, x, sub_vec, st,
-                       yscale_sel, sub_sel, red_partials, P.d_sync.p, epoch);
+    hipLaunchKernelGGL(k_trsv<1>, dim3(nbk + 1), dim3(512), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, pz, x,
+                       sub_vec, st, yscale_sel, sub_sel, red_partials, P.d_sync.p, epoch);
   else
-    hipLaunchKernelGGL(k_trsv<0>, dim3(nbk), dim3(256), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, x, sub_vec, st,
-                       yscale_sel, sub_sel, red_partials, P.d_sync.p, epoch);
+    hipLaunchKernelGGL(k_trsv<0>, dim3(nbk + 1), dim3(512), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, pz, x,
+                       sub_vec, st, yscale_sel, sub_sel, red_partials, P.d_sync.p, epoch);
   RFM_HIP(hipGetLastError());
 }
 

@@ -258,6 +258,7 @@ struct Problem {
   DBuf<double> d_B;       // s x n column-major (becomes Q's reflectors and R)
   DBuf<double> d_tau;     // Householder scalars
   DBuf<double> d_R;       // R in tiled upper storage for the triangular solves
+  DBuf<double> d_trsv;    // triangular solves: published blocks of x, then the helpers' partial sums
   DBuf<double> d_ws;      // QR workspace
   DBuf<int32_t> d_sync;   // grid-barrier / ticket / flag words
   int64_t ws_elems = 0;
