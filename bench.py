@@ -108,6 +108,9 @@ def main() -> None:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["gray-scott", "allen-cahn-hole"], default="gray-scott",
+                    help="allen-cahn-hole: space-time Allen-Cahn around a moving disc, 4 x 4 x 8 boxes, "
+                         "J = 400, q = 12 (n = 51,200); no warm-start study or CPU baseline")
     ap.add_argument("--method", choices=["ipn", "amipn"], default="ipn")
     ap.add_argument("--sketch-prec", choices=["bf16", "fp8", "f64"], default="bf16")
     ap.add_argument("--sketch-kind", choices=["gaussian", "count"], default="gaussian",
@@ -136,8 +139,17 @@ def main() -> None:
     import paper_2510_04170_amd as R
 
     rank = int(os.environ.get("RANK", "0"))
-    prob = W.config2()
+    if a.workload == "allen-cahn-hole":
+        a.no_warm_start_study = True
+        a.no_cpu_baseline = True
+        prob = W.config4()
+        workload = "allen_cahn_space_time_moving_hole_4x4x8_J400_q12"
+    else:
+        prob = W.config2()
+        workload = "gray_scott_3d_4x4x4_J300_q10"
+    t_setup = time.perf_counter()
     lp = R.from_description(prob)
+    print(f"[bench] problem uploaded in {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
     n, m = lp.n, lp.m
     method = R.RFM_AMIPN if a.method == "amipn" else R.RFM_IPN
     if a.sketch_kind == "count":
@@ -254,7 +266,7 @@ def main() -> None:
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": "gray_scott_3d_4x4x4_J300_q10", "n": n, "m": m, "s": 2 * n, "method": a.method,
+        "config": {"workload": workload, "n": n, "m": m, "s": 2 * n, "method": a.method,
                    "sketch": ("count_sketch_philox4x64_f64" if a.sketch_kind == "count" else
                               "gaussian_philox4x64_f64" if a.sketch_prec == "f64" else
                               f"philox4x64_code_table_{a.sketch_prec}_exact_pieces"),

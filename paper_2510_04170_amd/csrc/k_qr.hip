@@ -13,13 +13,16 @@
 //     beta = -sign(alpha) ||(alpha, x)||.
 //  2. The Gram V^T V (k_gemm_tn) and the compact-WY factor T (k_build_t), with
 //     H_1 ... H_ib = I - V T V^T (Schreiber and Van Loan, 1989).
-//  3. Inside a 256-column outer panel, each 64-column block updates the rest of
-//     the outer panel: W = V^T C (k_gemm_tn, split over rows with a fixed-order
+//  3. Inside a 256-column block, each 64-column block updates the rest of the
+//     256 columns: W = V^T C (k_gemm_tn, split over rows with a fixed-order
 //     reduction), W2 = -T^T W (k_reduce_w) and C += V W2 (k_gemm_nn), on
-//     v_mfma_f64_16x16x4.  The four blocks' T factors are merged into the T of
-//     the outer panel (k_combine_t, then the 256-wide assembly), and the
-//     trailing matrix gets one update with K = 256 (k_gemm_tn128, k_reduce_w256,
-//     k_gemm_nn128) on v_mfma_f64_4x4x4_4b.
+//     v_mfma_f64_16x16x4; the four T factors are merged into the block's T
+//     (k_combine_t, then the 256-wide merge).
+//  4. Outer panels are 512 columns: the first 256 are factored and applied to
+//     the second 256 (K = 256), the second 256 are factored, the two T are
+//     merged (T = [[Ta, -Ta Va^T Vb Tb], [0, Tb]]), and the trailing matrix is
+//     updated once with K = 512 (k_gemm_tn128, k_reduce_wide, k_gemm_nn128 on
+//     v_mfma_f64_4x4x4_4b), which halves the passes over it against K = 256.
 // Finally k_extract_r copies R (rows flipped to a positive diagonal) into the
 // tiled upper storage used by the triangular solves and flags a zero or
 // non-finite diagonal entry.
@@ -671,10 +674,12 @@ __global__ void k_zero_top(double* __restrict__ V, int64_t ldv) {
 }
 
 // ---------------------------------------------------------------------------
-// 256-column outer panels: T of four 64-column reflector blocks, and the
-// -T^T W reduction for 256 reflectors
+// Outer panels: 256-column blocks (four 64-column reflector blocks) and the
+// 512-column trailing-update width (two 256-column blocks); T of the merged
+// blocks and the -T^T W reduction
 // ---------------------------------------------------------------------------
 constexpr int kOuter = 256;
+constexpr int kWide = 512;
 
 // zero rows [0, nrows) of columns [c0, c0 + ncols) of V (leading dimension ldv)
 __global__ void k_zero_block(double* __restrict__ V, int64_t ldv, int c0, int ncols, int nrows) {
@@ -697,63 +702,65 @@ __global__ void k_gsum64(const double* __restrict__ part, int nsplit, int nb, do
   G[e] = g;
 }
 
-// G[a][b] (row-major 128 x 128) = sum over splits of part[split][b][a] (pstride 128)
-__global__ void k_gsum128(const double* __restrict__ part, int nsplit, double* __restrict__ G) {
+// G[a][b] (row-major w x w) = sum over splits of part[split][b][a] (pstride w), splits in order
+__global__ void k_gsum(const double* __restrict__ part, int nsplit, int w, double* __restrict__ G) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kBig * kBig) return;
-  const int a = e / kBig, b = e % kBig;
+  if (e >= w * w) return;
+  const int a = e / w, b = e % w;
   double g = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) g += part[((size_t)sp * kBig + b) * kBig + a];
+  for (int sp = 0; sp < nsplit; ++sp) g += part[((size_t)sp * w + b) * w + a];
   G[e] = g;
 }
 
-// C = alpha * A B for row-major 128 x 128 matrices, one thread per entry
-__global__ void k_sq_gemm128(const double* __restrict__ A, const double* __restrict__ B, double alpha,
-                             double* __restrict__ C) {
+// C = alpha * A B for row-major w x w matrices, one thread per entry
+__global__ void k_sq_gemm(const double* __restrict__ A, const double* __restrict__ B, double alpha, int w,
+                          double* __restrict__ C) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kBig * kBig) return;
-  const int i = e / kBig, j = e % kBig;
+  if (e >= w * w) return;
+  const int i = e / w, j = e % w;
   double v = 0.0;
-  for (int k = 0; k < kBig; ++k) v += A[i * kBig + k] * B[k * kBig + j];
+  for (int k = 0; k < w; ++k) v += A[i * w + k] * B[k * w + j];
   C[e] = alpha * v;
 }
 
-// T (256 x 256, row-major) = [[T1, Y], [0, T2]] from 128 x 128 blocks
-__global__ void k_assemble_t256(const double* __restrict__ T1, const double* __restrict__ T2,
-                                const double* __restrict__ Y, double* __restrict__ T) {
+// T (2w x 2w, row-major) = [[T1, Y], [0, T2]] from w x w blocks
+__global__ void k_assemble_t(const double* __restrict__ T1, const double* __restrict__ T2,
+                             const double* __restrict__ Y, int w, double* __restrict__ T) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kOuter * kOuter) return;
-  const int qq = e / kOuter, p = e % kOuter;
+  if (e >= 4 * w * w) return;
+  const int qq = e / (2 * w), p = e % (2 * w);
   double v = 0.0;
-  if (qq < kBig && p < kBig) v = T1[qq * kBig + p];
-  else if (qq >= kBig && p >= kBig) v = T2[(qq - kBig) * kBig + (p - kBig)];
-  else if (qq < kBig && p >= kBig) v = Y[qq * kBig + (p - kBig)];
+  if (qq < w && p < w) v = T1[qq * w + p];
+  else if (qq >= w && p >= w) v = T2[(qq - w) * w + (p - w)];
+  else if (qq < w && p >= w) v = Y[qq * w + (p - w)];
   T[e] = v;
 }
 
-// W2[n][p] = -sum_{q <= p} T[q][p] W[n][q], W = sum over splits (pstride 256), 8 columns per block
-__global__ void __launch_bounds__(256) k_reduce_w256(const double* __restrict__ part, int nsplit, int N,
+// W2[n][p] = -sum_{q <= p} T[q][p] W[n][q] for WID (256 or 512) reflectors, W = sum over splits
+// (pstride WID); one thread per p, 8 columns per block
+template <int WID>
+__global__ void __launch_bounds__(WID) k_reduce_wide(const double* __restrict__ part, int nsplit, int N,
                                                      const double* __restrict__ T, double* __restrict__ W2) {
-  __shared__ double Wsh[8][kOuter];
+  __shared__ double Wsh[8][WID];
   const int p = threadIdx.x;
   const int n0 = blockIdx.x * 8;
   for (int c = 0; c < 8; ++c) {
     const int n = n0 + c;
     double w = 0.0;
     if (n < N)
-      for (int sp = 0; sp < nsplit; ++sp) w += part[((size_t)sp * N + n) * kOuter + p];
+      for (int sp = 0; sp < nsplit; ++sp) w += part[((size_t)sp * N + n) * WID + p];
     Wsh[c][p] = w;
   }
   __syncthreads();
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int qq = 0; qq <= p; ++qq) {
-    const double t = T[qq * kOuter + p];
+    const double t = T[qq * WID + p];
 #pragma unroll
     for (int c = 0; c < 8; ++c) v[c] += t * Wsh[c][qq];
   }
 #pragma unroll
   for (int c = 0; c < 8; ++c)
-    if (n0 + c < N) W2[(int64_t)(n0 + c) * kOuter + p] = -v[c];
+    if (n0 + c < N) W2[(int64_t)(n0 + c) * WID + p] = -v[c];
 }
 
 // R (upper n x n of B) into tiled storage: tile (bi, bj), bi <= bj, at
@@ -858,19 +865,23 @@ void qr_factor(Problem& P) {
   const int ncu = num_cus(P.device);
   const int max_split = 16;
   // workspace
-  const size_t vb = (size_t)(s + 1) * kOuter;  // V of an outer panel, leading dimension M rounded up to even
-  const size_t tn = (size_t)max_split * std::max<int64_t>(n, kOuter) * kOuter;
-  const size_t small = 5 * kPanel * kPanel + 5 * kBig * kBig + kOuter * kOuter;
-  const size_t need = vb + small + 2 * (size_t)ncu * kPanel + 4 * kPanel + tn + (size_t)n * kOuter + 256;
+  const size_t vb = (size_t)(s + 1) * kWide;  // V of a 512-column outer panel, leading dimension M rounded up to even
+  const size_t tn = (size_t)max_split * std::max<int64_t>(n, kWide) * kWide;
+  const size_t small = 5 * kPanel * kPanel + 5 * kBig * kBig + 5 * kOuter * kOuter + kWide * kWide;
+  const size_t need = vb + small + 2 * (size_t)ncu * kPanel + 4 * kPanel + tn + (size_t)n * kWide + 256;
   P.d_ws.resize(need);
-  double* Vb = P.d_ws.p;
-  double* T64 = Vb + vb;                    // 4 blocks of 64 x 64
-  double* T128 = T64 + 4 * kPanel * kPanel; // 2 blocks of 128 x 128
+  double* Vw = P.d_ws.p;
+  double* T64 = Vw + vb;                     // 4 blocks of 64 x 64
+  double* T128 = T64 + 4 * kPanel * kPanel;  // 2 blocks of 128 x 128
   double* G128 = T128 + 2 * kBig * kBig;
   double* X128 = G128 + kBig * kBig;
   double* Y128 = X128 + kBig * kBig;
-  double* T256 = Y128 + kBig * kBig;
-  double* G64 = T256 + kOuter * kOuter;    // summed 64-wide Gram blocks
+  double* T256 = Y128 + kBig * kBig;         // 2 blocks of 256 x 256: the two halves of an outer panel
+  double* G256 = T256 + 2 * kOuter * kOuter;
+  double* X256 = G256 + kOuter * kOuter;
+  double* Y256 = X256 + kOuter * kOuter;
+  double* T512 = Y256 + kOuter * kOuter;
+  double* G64 = T512 + kWide * kWide;        // summed 64-wide Gram blocks
   double* Pp = G64 + kPanel * kPanel;
   double* DR = Pp + 2 * (size_t)ncu * kPanel;
   double* part = DR + 4 * kPanel;
@@ -887,6 +898,23 @@ void qr_factor(Problem& P) {
   auto fill = [&](double* p, int64_t cnt) {
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, P.stream, p, cnt, 0.0);
   };
+  // merged T of two reflector blocks of width w: [[Ta, -Ta G Tb], [0, Tb]] with G = Va^T Vb
+  auto merge_t = [&](const double* G, const double* Ta, const double* Tb, double* X, double* Y, int w, double* Tout) {
+    const unsigned g1 = (unsigned)((w * w + 255) / 256), g4 = (unsigned)((4 * w * w + 255) / 256);
+    hipLaunchKernelGGL(k_sq_gemm, dim3(g1), dim3(256), 0, P.stream, G, Tb, 1.0, w, X);
+    hipLaunchKernelGGL(k_sq_gemm, dim3(g1), dim3(256), 0, P.stream, Ta, X, -1.0, w, Y);
+    hipLaunchKernelGGL(k_assemble_t, dim3(g4), dim3(256), 0, P.stream, Ta, Tb, Y, w, Tout);
+  };
+  // split-row Gram V_a^T V_b of two w-wide (128 or 256) column blocks over K rows into G (w x w)
+  auto gram_wide = [&](const double* Va, const double* Vbk, int64_t ldv, int K, int w, double* G) {
+    int nsplit, krange;
+    tn_split(K, (w / kBig) * (w / kBig), ncu, max_split, &nsplit, &krange);
+    krange = (krange + kKC - 1) / kKC * kKC;
+    nsplit = (K + krange - 1) / krange;
+    hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(w / kBig, w / kBig, nsplit), dim3(256), 0, P.stream, Va, ldv, Vbk,
+                       ldv, K, w, krange, part, w);
+    hipLaunchKernelGGL(k_gsum, dim3((unsigned)((w * w + 255) / 256)), dim3(256), 0, P.stream, part, nsplit, w, G);
+  };
 
   double* B = P.d_B.p;
   auto gram_t = [&](const double* V, int64_t ldv, int K, int nb, const double* tau, double* Tout) {
@@ -897,103 +925,114 @@ void qr_factor(Problem& P) {
                        nb, G64);
     hipLaunchKernelGGL(k_build_t, dim3(1), dim3(256), 0, P.stream, G64, 1, nb, tau, Tout);
   };
-  for (int64_t col0 = 0; col0 < n; col0 += kOuter) {
-    const int nbo = (int)std::min<int64_t>(kOuter, n - col0);
-    const int nsp = (nbo + kPanel - 1) / kPanel;
-    const int M = (int)(s - col0);
-    const int Mv = (M + 1) & ~1;  // leading dimension of V: even, so that row pairs load as 16 bytes
-    // V columns of sub-panels beyond the last one stay zero
-    if (nsp < 4) zero_block(Vb, Mv, nsp * kPanel, (4 - nsp) * kPanel, M);
+  // C (M x N at Cp, leading dimension s) <- (I - V T^T V^T) C for the K = 256 or 512 reflectors in
+  // V (leading dimension Mv): W = V^T C, W2 = -T^T W, C += V W2^T
+  auto trailing = [&](const double* V, int64_t Mv, int K, const double* T, double* Cp, int M, int64_t N) {
+    const int ntile = (int)((N + kBig - 1) / kBig);
+    const int halves = K / kBig;
+    int nsplit, krange;
+    tn_split(M, halves * ntile, ncu, max_split, &nsplit, &krange);
+    krange = (krange + kKC - 1) / kKC * kKC;
+    nsplit = (M + krange - 1) / krange;
+    {
+      ProfScope ps(P.prof, P.stream, "qr_gemm_tn", 2.0 * M * (double)N * K,
+                   8.0 * (2.0 * M * N + (double)M * K + (double)nsplit * N * K));
+      // 16-byte loads of C need an even leading dimension and an aligned first column
+      const bool vec = (s % 2 == 0) && (reinterpret_cast<uintptr_t>(Cp) % 16 == 0);
+      if (vec)
+        hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(halves, ntile, nsplit), dim3(256), 0, P.stream, V, Mv, Cp, s, M,
+                           (int)N, krange, part, K);
+      else
+        hipLaunchKernelGGL(k_gemm_tn128<false>, dim3(halves, ntile, nsplit), dim3(256), 0, P.stream, V, Mv, Cp, s, M,
+                           (int)N, krange, part, K);
+    }
+    if (K == kWide)
+      hipLaunchKernelGGL(k_reduce_wide<kWide>, dim3((unsigned)((N + 7) / 8)), dim3(kWide), 0, P.stream, part, nsplit,
+                         (int)N, T, W2);
+    else
+      hipLaunchKernelGGL(k_reduce_wide<kOuter>, dim3((unsigned)((N + 7) / 8)), dim3(kOuter), 0, P.stream, part,
+                         nsplit, (int)N, T, W2);
+    {
+      ProfScope ps(P.prof, P.stream, "qr_gemm_nn", 2.0 * M * (double)N * K,
+                   8.0 * (2.0 * M * N + (double)M * K + (double)N * K));
+      hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)ntile), dim3(256), 0,
+                         P.stream, Cp, s, V, Mv, W2, (int64_t)K, M, (int)N, K);
+    }
+  };
+  // Factor columns c0 .. c0 + nbh - 1 (nbh <= 256) of the current trailing matrix in four 64-column
+  // blocks; their reflectors go to Vh (row 0 = row c0 of B, leading dimension Mv) and the T of all
+  // of them to Tout.
+  auto factor256 = [&](int64_t c0, int nbh, double* Vh, int64_t Mv, double* Tout) {
+    const int Mh = (int)(s - c0);
+    const int nsp = (nbh + kPanel - 1) / kPanel;
+    // V columns of blocks beyond the last one stay zero
+    if (nsp < 4) zero_block(Vh, Mv, nsp * kPanel, (4 - nsp) * kPanel, Mh);
     if (nsp < 4) fill(T64 + (size_t)nsp * kPanel * kPanel, (int64_t)(4 - nsp) * kPanel * kPanel);
     int nbs[4] = {0, 0, 0, 0};
     for (int sp = 0; sp < nsp; ++sp) {
-      const int64_t c_sp = col0 + (int64_t)sp * kPanel;
-      const int Msp = M - sp * kPanel;
-      const int nbsp = std::min(kPanel, nbo - sp * kPanel);
+      const int64_t c_sp = c0 + (int64_t)sp * kPanel;
+      const int Msp = Mh - sp * kPanel;
+      const int nbsp = std::min(kPanel, nbh - sp * kPanel);
       nbs[sp] = nbsp;
-      double* Vsp = Vb + (int64_t)sp * kPanel * Mv + sp * kPanel;
-      if (sp > 0) zero_block(Vb, Mv, sp * kPanel, kPanel, sp * kPanel);
+      double* Vsp = Vh + (int64_t)sp * kPanel * Mv + sp * kPanel;
+      if (sp > 0) zero_block(Vh, Mv, sp * kPanel, kPanel, sp * kPanel);
       launch_panel(P, B + c_sp * s + c_sp, s, Msp, nbsp, P.d_tau.p + c_sp, Pp, DR, Vsp, Mv);
       gram_t(Vsp, Mv, Msp, nbsp, P.d_tau.p + c_sp, T64 + (size_t)sp * kPanel * kPanel);
-      const int Nr = nbo - (sp + 1) * kPanel;
+      const int Nr = nbh - (sp + 1) * kPanel;
       if (Nr > 0) {
-        // apply this sub-panel's reflectors to the rest of the outer panel
+        // apply this block's reflectors to the rest of the 256 columns
         double* Cr = B + (c_sp + kPanel) * s + c_sp;
         int nsplit, krange;
         tn_split(Msp, (Nr + 63) / 64, ncu, 64, &nsplit, &krange);
-        hipLaunchKernelGGL(k_gemm_tn, dim3((unsigned)((Nr + 63) / 64), nsplit), dim3(256), 0, P.stream, Vsp,
-                           (int64_t)Mv, Cr, s, Msp, Nr, krange, part);
+        hipLaunchKernelGGL(k_gemm_tn, dim3((unsigned)((Nr + 63) / 64), nsplit), dim3(256), 0, P.stream, Vsp, Mv, Cr,
+                           s, Msp, Nr, krange, part);
         hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((Nr + 3) / 4)), dim3(256), 0, P.stream, part, nsplit, Nr,
                            T64 + (size_t)sp * kPanel * kPanel, W2);
         hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((Msp + 63) / 64), (unsigned)((Nr + 63) / 64)), dim3(256), 0,
-                           P.stream, Cr, s, Vsp, (int64_t)Mv, W2, Msp, Nr, kPanel);
+                           P.stream, Cr, s, Vsp, Mv, W2, Msp, Nr, kPanel);
       }
     }
     // T of the 256 reflectors: pairs of 64-blocks into 128-blocks, then the two 128-blocks
     for (int pr = 0; pr < 2; ++pr) {
       const int a = 2 * pr, b = 2 * pr + 1;
       int nsplit_ab = 1, krange;
-      const int Kab = M - b * kPanel;
+      const int Kab = Mh - b * kPanel;
       if (nbs[b] > 0) {
         tn_split(Kab, 1, ncu, 64, &nsplit_ab, &krange);
-        hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit_ab), dim3(256), 0, P.stream,
-                           Vb + (int64_t)a * kPanel * Mv + b * kPanel, (int64_t)Mv,
-                           Vb + (int64_t)b * kPanel * Mv + b * kPanel, (int64_t)Mv, Kab, nbs[b], krange, part);
+        hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit_ab), dim3(256), 0, P.stream, Vh + (int64_t)a * kPanel * Mv + b * kPanel,
+                           Mv, Vh + (int64_t)b * kPanel * Mv + b * kPanel, Mv, Kab, nbs[b], krange, part);
         hipLaunchKernelGGL(k_gsum64, dim3((unsigned)((nbs[b] * kPanel + 255) / 256)), dim3(256), 0, P.stream, part,
                            nsplit_ab, nbs[b], G64);
       }
       hipLaunchKernelGGL(k_combine_t, dim3(1), dim3(256), 0, P.stream, T64 + (size_t)a * kPanel * kPanel,
                          T64 + (size_t)b * kPanel * kPanel, G64, 1, nbs[b], T128 + (size_t)pr * kBig * kBig);
     }
-    {
-      // G = V01^T V23 over rows 128..M-1 (V23 is zero above row 128)
-      const int K2 = M - kBig;
-      if (nsp > 2 && K2 > 0) {
-        int nsplit, krange;
-        tn_split(K2, 1, ncu, max_split, &nsplit, &krange);
-        krange = (krange + kKC - 1) / kKC * kKC;
-        nsplit = (K2 + krange - 1) / krange;
-        hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(1, 1, nsplit), dim3(256), 0, P.stream, Vb + kBig, (int64_t)Mv,
-                           Vb + (int64_t)kBig * Mv + kBig, (int64_t)Mv, K2, kBig, krange, part, kBig);
-        hipLaunchKernelGGL(k_gsum128, dim3(kBig * kBig / 256), dim3(256), 0, P.stream, part, nsplit, G128);
-      } else {
-        fill(G128, (int64_t)kBig * kBig);  // no reflectors past column 128 in this block
-      }
-      hipLaunchKernelGGL(k_sq_gemm128, dim3(kBig * kBig / 256), dim3(256), 0, P.stream, G128, T128 + kBig * kBig,
-                         1.0, X128);
-      hipLaunchKernelGGL(k_sq_gemm128, dim3(kBig * kBig / 256), dim3(256), 0, P.stream, T128, X128, -1.0, Y128);
-      hipLaunchKernelGGL(k_assemble_t256, dim3(kOuter * kOuter / 256), dim3(256), 0, P.stream, T128,
-                         T128 + kBig * kBig, Y128, T256);
-    }
+    // G = V01^T V23 over rows 128..Mh-1 (V23 is zero above row 128)
+    if (nsp > 2 && Mh > kBig) gram_wide(Vh + kBig, Vh + (int64_t)kBig * Mv + kBig, Mv, Mh - kBig, kBig, G128);
+    else fill(G128, (int64_t)kBig * kBig);  // no reflectors past column 128 in this block
+    merge_t(G128, T128, T128 + kBig * kBig, X128, Y128, kBig, Tout);
     RFM_HIP(hipGetLastError());
-    const int64_t N = n - col0 - nbo;
+  };
+
+  // 512-column outer panels: the first 256 columns are factored, applied to the second 256 (K = 256),
+  // the second 256 factored, the two T merged, and the trailing matrix updated once with K = 512
+  for (int64_t col0 = 0; col0 < n; col0 += kWide) {
+    const int nbw = (int)std::min<int64_t>(kWide, n - col0);
+    const int nb0 = std::min(kOuter, nbw), nb1 = nbw - nb0;
+    const int M = (int)(s - col0);
+    const int64_t Mv = (M + 1) & ~1;  // leading dimension of V: even, so that row pairs load as 16 bytes
+    factor256(col0, nb0, Vw, Mv, T256);
+    if (nb1 > 0) {
+      trailing(Vw, Mv, kOuter, T256, B + (col0 + kOuter) * s + col0, M, nb1);
+      zero_block(Vw, Mv, kOuter, kOuter, kOuter);  // the second half's reflectors start at row 256
+      factor256(col0 + kOuter, nb1, Vw + (int64_t)kOuter * Mv + kOuter, Mv, T256 + kOuter * kOuter);
+    }
+    const int64_t N = n - col0 - nbw;
     if (N > 0) {
-      double* C = B + (col0 + nbo) * s + col0;
-      const int ntile = (int)((N + kBig - 1) / kBig);
-      int nsplit, krange;
-      tn_split(M, 2 * ntile, ncu, max_split, &nsplit, &krange);
-      krange = (krange + kKC - 1) / kKC * kKC;
-      nsplit = (M + krange - 1) / krange;
-      {
-        ProfScope ps(P.prof, P.stream, "qr_gemm_tn", 2.0 * M * (double)N * kOuter,
-                     8.0 * (2.0 * M * N + (double)M * kOuter + (double)nsplit * N * kOuter));
-        // 16-byte loads of C need an even leading dimension and an aligned first column
-        const bool vec = (s % 2 == 0) && (reinterpret_cast<uintptr_t>(C) % 16 == 0);
-        if (vec)
-          hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(2, ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)Mv, C, s,
-                             M, (int)N, krange, part, kOuter);
-        else
-          hipLaunchKernelGGL(k_gemm_tn128<false>, dim3(2, ntile, nsplit), dim3(256), 0, P.stream, Vb, (int64_t)Mv, C,
-                             s, M, (int)N, krange, part, kOuter);
-      }
-      hipLaunchKernelGGL(k_reduce_w256, dim3((unsigned)((N + 7) / 8)), dim3(256), 0, P.stream, part, nsplit, (int)N,
-                         T256, W2);
-      {
-        ProfScope ps(P.prof, P.stream, "qr_gemm_nn", 2.0 * M * (double)N * kOuter,
-                     8.0 * (2.0 * M * N + (double)M * kOuter + (double)N * kOuter));
-        hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)ntile), dim3(256), 0,
-                           P.stream, C, s, Vb, (int64_t)Mv, W2, (int64_t)kOuter, M, (int)N, kOuter);
-      }
+      // nbw = 512 here; G = V_a^T V_b over rows 256..M-1 (V_b is zero above row 256)
+      gram_wide(Vw + kOuter, Vw + (int64_t)kOuter * Mv + kOuter, Mv, M - kOuter, kOuter, G256);
+      merge_t(G256, T256, T256 + kOuter * kOuter, X256, Y256, kOuter, T512);
+      trailing(Vw, Mv, kWide, T512, B + (col0 + kWide) * s + col0, M, N);
     }
     RFM_HIP(hipGetLastError());
   }

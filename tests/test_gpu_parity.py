@@ -376,3 +376,35 @@ def test_full_solve_count_sketch(name):
           f"oracle {_relerr(fg, fo):.2e}; relL2 vs u* {_relerr(fg, ex):.3e}")
     assert _relerr(fg, fo) < 1e-8
     lp.close()
+
+
+@pytest.mark.parametrize("extra_row", [False, True])
+def test_qr_across_512_column_outer_panels(extra_row):
+    """n = 1,320: three 512-column outer panels (the last one 296 wide: a full first half and a
+    40-column second half), K = 512 trailing updates between them; with extra_row, s = 2n + 1."""
+    prob = W.config1(J=330)
+    lp = R.from_description(prob)
+    assert lp.n == 1320
+    gamma = (2 * lp.n + 0.5) / lp.n if extra_row else 2.0
+    F, J = O.assemble(prob, np.zeros(prob.n))
+    DJ = O.row_scale(J)[:, None] * J
+    lp.stage_assemble(np.zeros(prob.n), 100.0)
+    lp.stage_sketch(gamma, 1, 0, R.RFM_PREC_F64)
+    assert lp.s == O.sketch_rows(lp.n, gamma)
+    B = lp.get_sketch_cols(0, lp.n)
+    assert _relerr(B, O.sketch(DJ, lp.s, 1, 0)) < 1e-12
+    lp.stage_qr()
+    Rg = lp.get_r_cols(0, lp.n)
+    assert np.array_equal(np.tril(Rg, -1), np.zeros_like(Rg))
+    assert np.all(np.diag(Rg) > 0)
+    G = B.T @ B
+    assert np.abs(Rg.T @ Rg - G).max() < 1e-12 * np.abs(G).max()
+    Ro = O.qr_r(B)
+    assert _relerr(Rg, Ro) < max(1e-12, 1e-15 * np.linalg.cond(B))
+    # with 330 features per box this D J is numerically rank-deficient, so kappa(D J R^-1) is set by
+    # rounding rather than by the sketch: the GPU's R has to precondition as well as LAPACK's R
+    kg = np.linalg.cond(DJ @ np.linalg.inv(Rg))
+    ko = np.linalg.cond(DJ @ np.linalg.inv(Ro))
+    print(f"kappa(D J R^-1): GPU R {kg:.3g}, LAPACK R {ko:.3g}")
+    assert kg < 1.5 * ko + 1.0
+    lp.close()
