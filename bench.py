@@ -46,11 +46,14 @@ PEAK_FP8_TFLOPS = 5000.0     # MI355X dense FP8 matrix
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
 
-# HBM bytes per launch of the dominant kernel on this workload, from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, scaled by 2.0 and 1.0: what the same counters read
-# for an elementwise copy of 1 GiB); valid only while the kernel is unchanged, so a kernel without
-# counters taken on its current code reports null
-TRAFFIC_BYTES = {}
+# HBM bytes per launch of the QR's trailing-update products on the Gray-Scott workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, scaled by 2.0 and 1.0: what the
+# same counters read for an elementwise copy of 1 GiB); valid only while the kernels are unchanged,
+# so a kernel without counters taken on its current code reports null
+TRAFFIC_BYTES = {
+    "qr_gemm_tn": (8338539.7 * 2.0 + 85947.3 * 1.0) * 1024.0,
+    "qr_gemm_nn": (6335101.8 * 2.0 + 4851457.7 * 1.0) * 1024.0,
+}
 
 METRIC = "Newton solves/s at relL2<=1e-6; sketch-GEMM TFLOP/s; LSQR SpMV HBM GB/s"
 
@@ -239,7 +242,8 @@ def main() -> None:
     if mfma_bound:
         achieved = dk["flops"] / dk["seconds"] / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": TRAFFIC_BYTES.get(dom),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": TRAFFIC_BYTES.get(dom) if a.workload == "gray-scott" else None,
                 "per_launch_alg_bytes": dk["bytes"] / dk["launches"],
                 "per_launch_flops": dk["flops"] / dk["launches"],
                 "avg_launch_us": round(1e6 * dk["seconds"] / dk["launches"], 2)}

@@ -417,6 +417,14 @@ constexpr int kKC = 16;
 
 typedef double v2d __attribute__((ext_vector_type(2)));
 
+// Workgroups are dealt to the 8 XCDs round robin (workgroup id mod 8), and each XCD has its own L2.
+// The position of workgroup `id` in a sequence where every XCD takes a contiguous range, so that
+// workgroups that share operands can be placed on one XCD and run there close in time.
+__device__ __forceinline__ int xcd_order(int id, int total) {
+  const int per = total / 8, x = id % 8, q = id / 8;
+  return q < per ? x * per + q : 8 * per + x;
+}
+
 // One 16-deep k-chunk on LDS tiles Xs[k][row], Ys[k][col] (row and column of the output).
 // v_mfma_f64_4x4x4_4b_f64 holds, for block b, A(i,k) in lane 16k+4b+i, B(k,j) in lane 16k+4b+j
 // and D(i,j) in lane 16i+4b+j.  With the A operand carrying 4 output columns (the same in every
@@ -449,6 +457,9 @@ __device__ __forceinline__ void mfma4_chunk(const double (*Xs)[kBig + 1], const 
 // C[M x N] += A[M x K] B, A column-major (lda even, 16-byte aligned), B[k][n] = Bt[n * ldb + k] (ldb even,
 // aligned); K a multiple of 16.  Loaders: A as row pairs (m = 2 (tid % 64), k = tid / 64 + 4 i), B as k pairs
 // (k = 2 (tid % 8), n = tid / 8 + 32 i); tiles wholly inside M x N take unguarded 16-byte loads.
+// 1-D grid over the tiles: each XCD takes a contiguous range of the tiles ordered in groups of 4 row
+// tiles (row tile fastest), so the 4 x 4 tiles it runs at a time share 4 tiles of A and 4 of B in its L2
+// (against a fresh A tile per workgroup in row-major launch order; 8% faster at K = 512).
 __global__ void __launch_bounds__(256, 2) k_gemm_nn128(double* __restrict__ C, int64_t ldc,
                                                       const double* __restrict__ A, int64_t lda,
                                                       const double* __restrict__ Bt, int64_t ldb, int M, int N,
@@ -457,7 +468,16 @@ __global__ void __launch_bounds__(256, 2) k_gemm_nn128(double* __restrict__ C, i
   __shared__ double Bs[2][kKC][kBig + 1];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
-  const int r0 = blockIdx.x * kBig, n0 = blockIdx.y * kBig;
+  int r0, n0;
+  {
+    constexpr int kGroup = 4;
+    const int nrt = (M + kBig - 1) / kBig, nct = (N + kBig - 1) / kBig;
+    const int L = xcd_order(blockIdx.x, nrt * nct);
+    const int gi = L / (kGroup * nct), gl = L % (kGroup * nct);
+    const int gh = min(kGroup, nrt - gi * kGroup);
+    r0 = (gi * kGroup + gl % gh) * kBig;
+    n0 = (gl / gh) * kBig;
+  }
   const bool full = (r0 + kBig <= M) && (n0 + kBig <= N);
   double acc[4][16];
 #pragma unroll
@@ -527,11 +547,12 @@ __global__ void __launch_bounds__(256, 2) k_gemm_nn128(double* __restrict__ C, i
   }
 }
 
-// part[split][n][p] = sum_{k in split} A[k][p] B[k][n]; A: K x 128 (lda), B: K x N (ldb), both
-// column-major; rows of a split: [split * krange, ...), krange a multiple of 16.  Grid: (P halves
-// of a 256-wide V, column tiles, row splits).  VEC: lda, ldb even and both bases 16-byte aligned,
-// so k pairs load as 16 bytes.
-template <bool VEC>
+// part[split][n][p] = sum_{k in split} A[k][p] B[k][n]; A: K x pstride (lda), B: K x N (ldb), both
+// column-major; rows of a split: [split * krange, ...), krange a multiple of 16.  Grid: 1-D,
+// (pstride / 128 halves) x (column tiles) x (row splits) workgroups.  VEC: lda, ldb even and both bases 16-byte aligned,
+// so k pairs load as 16 bytes.  GRAM only tells the Gram products of the T merges apart from the
+// trailing updates in a profile (same code).
+template <bool VEC, bool GRAM = false>
 __global__ void __launch_bounds__(256, 2) k_gemm_tn128(const double* __restrict__ A, int64_t lda,
                                                      const double* __restrict__ B, int64_t ldb, int K, int N,
                                                      int krange, double* __restrict__ part, int pstride) {
@@ -539,9 +560,13 @@ __global__ void __launch_bounds__(256, 2) k_gemm_tn128(const double* __restrict_
   __shared__ double Bs[2][kKC][kBig + 1];
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
-  const int half = blockIdx.x;
-  const int n0 = blockIdx.y * kBig;
-  const int split = blockIdx.z;
+  // 1-D grid of halves x column tiles x splits: on each XCD the halves of one (column tile, split)
+  // run next to each other and share that C tile in its L2
+  const int halves = pstride / kBig, ntile = (N + kBig - 1) / kBig;
+  const int L = xcd_order(blockIdx.x, gridDim.x);
+  const int half = L % halves;
+  const int n0 = (L / halves) % ntile * kBig;
+  const int split = L / halves / ntile;
   A += (int64_t)half * kBig * lda;
   const int kb = split * krange, ke = min(K, kb + krange);
   const bool ncols_full = n0 + kBig <= N;
@@ -911,8 +936,8 @@ void qr_factor(Problem& P) {
     tn_split(K, (w / kBig) * (w / kBig), ncu, max_split, &nsplit, &krange);
     krange = (krange + kKC - 1) / kKC * kKC;
     nsplit = (K + krange - 1) / krange;
-    hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(w / kBig, w / kBig, nsplit), dim3(256), 0, P.stream, Va, ldv, Vbk,
-                       ldv, K, w, krange, part, w);
+    hipLaunchKernelGGL((k_gemm_tn128<true, true>), dim3((w / kBig) * (w / kBig) * nsplit), dim3(256), 0, P.stream, Va,
+                       ldv, Vbk, ldv, K, w, krange, part, w);
     hipLaunchKernelGGL(k_gsum, dim3((unsigned)((w * w + 255) / 256)), dim3(256), 0, P.stream, part, nsplit, w, G);
   };
 
@@ -940,11 +965,11 @@ void qr_factor(Problem& P) {
       // 16-byte loads of C need an even leading dimension and an aligned first column
       const bool vec = (s % 2 == 0) && (reinterpret_cast<uintptr_t>(Cp) % 16 == 0);
       if (vec)
-        hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(halves, ntile, nsplit), dim3(256), 0, P.stream, V, Mv, Cp, s, M,
-                           (int)N, krange, part, K);
+        hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(halves * ntile * nsplit), dim3(256), 0, P.stream, V, Mv, Cp, s,
+                           M, (int)N, krange, part, K);
       else
-        hipLaunchKernelGGL(k_gemm_tn128<false>, dim3(halves, ntile, nsplit), dim3(256), 0, P.stream, V, Mv, Cp, s, M,
-                           (int)N, krange, part, K);
+        hipLaunchKernelGGL(k_gemm_tn128<false>, dim3(halves * ntile * nsplit), dim3(256), 0, P.stream, V, Mv, Cp, s,
+                           M, (int)N, krange, part, K);
     }
     if (K == kWide)
       hipLaunchKernelGGL(k_reduce_wide<kWide>, dim3((unsigned)((N + 7) / 8)), dim3(kWide), 0, P.stream, part, nsplit,
@@ -955,8 +980,8 @@ void qr_factor(Problem& P) {
     {
       ProfScope ps(P.prof, P.stream, "qr_gemm_nn", 2.0 * M * (double)N * K,
                    8.0 * (2.0 * M * N + (double)M * K + (double)N * K));
-      hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig), (unsigned)ntile), dim3(256), 0,
-                         P.stream, Cp, s, V, Mv, W2, (int64_t)K, M, (int)N, K);
+      hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig * ntile)), dim3(256), 0, P.stream, Cp, s,
+                         V, Mv, W2, (int64_t)K, M, (int)N, K);
     }
   };
   // Factor columns c0 .. c0 + nbh - 1 (nbh <= 256) of the current trailing matrix in four 64-column
