@@ -111,9 +111,13 @@ def main() -> None:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["gray-scott", "allen-cahn-hole"], default="gray-scott",
+    ap.add_argument("--workload", choices=["gray-scott", "allen-cahn-hole", "helmholtz-cosh"], default="gray-scott",
                     help="allen-cahn-hole: space-time Allen-Cahn around a moving disc, 4 x 4 x 8 boxes, "
-                         "J = 400, q = 12 (n = 51,200); no warm-start study or CPU baseline")
+                         "J = 400, q = 12 (n = 51,200); helmholtz-cosh: Lap u - 100 u + 10 cosh(u) = f on the "
+                         "unit cube, 2 x 2 x 2 boxes, --features J, --points q; neither runs the warm-start "
+                         "study or the CPU baseline")
+    ap.add_argument("--features", type=int, default=400, help="helmholtz-cosh: J per box")
+    ap.add_argument("--points", type=int, default=20, help="helmholtz-cosh: q (q^3 points per box)")
     ap.add_argument("--method", choices=["ipn", "amipn"], default="ipn")
     ap.add_argument("--sketch-prec", choices=["bf16", "fp8", "f64"], default="bf16")
     ap.add_argument("--sketch-kind", choices=["gaussian", "count"], default="gaussian",
@@ -147,6 +151,11 @@ def main() -> None:
         a.no_cpu_baseline = True
         prob = W.config4()
         workload = "allen_cahn_space_time_moving_hole_4x4x8_J400_q12"
+    elif a.workload == "helmholtz-cosh":
+        a.no_warm_start_study = True
+        a.no_cpu_baseline = True
+        prob = W.helmholtz_cosh(nsub=(2, 2, 2), J=a.features, q=a.points)
+        workload = f"helmholtz_cosh_3d_2x2x2_J{a.features}_q{a.points}"
     else:
         prob = W.config2()
         workload = "gray_scott_3d_4x4x4_J300_q10"

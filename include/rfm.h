@@ -68,6 +68,13 @@ typedef struct { int32_t eq, comp; double coeff; int32_t deriv; } rfm_lin_term;
  * restricted to polynomials of the field values.  At most 4 components. */
 typedef struct { int32_t eq; double coeff; int32_t pow[4]; } rfm_poly_term;
 
+/* One term coeff * f(u_comp) of equation eq with f one of the functions below:
+ * the nonlinear part mu*N(u) for pointwise transcendental nonlinearities (the
+ * cosh term of the 3-D Helmholtz problem of Sec. 5, e^u of the diffusion-reaction
+ * problems).  Its Jacobian contribution is coeff * f'(u_comp) phi. */
+typedef struct { int32_t eq, comp; double coeff; int32_t fn; } rfm_fn_term;
+enum { RFM_FN_COSH = 0, RFM_FN_SINH = 1, RFM_FN_EXP = 2 };
+
 /* Create an empty problem on HIP device `device`.  dim: 1..4 coordinates
  * (time, if any, is the last one, Sec. 2.1); ncomp: 1..4 solution components,
  * with one equation per component.  hip_stream: a hipStream_t, or NULL for the
@@ -94,7 +101,7 @@ rfm_status rfm_set_features(rfm_problem* p, int32_t J, const double* W, const do
  * box `neighbor` across the interface.  Rows are appended in the order
  * (equation or component, continuity order, point):
  *  RFM_PDE:        one row per equation (comp = -1) or for equation comp;
- *                  residual  sum lin + sum poly - data[p][q]  (Alg. 3 step 1);
+ *                  residual  sum lin + sum poly + sum fn - data[p][q]  (Alg. 3 step 1);
  *                  data: [npts][neq_sel]
  *  RFM_DIRICHLET:  u_c(x) - data[p][k]            (Alg. 3 step 3), data [npts][ncomp_sel]
  *  RFM_NEUMANN:    normal . grad u_c(x) - data[p][k],               data [npts][ncomp_sel]
@@ -108,9 +115,17 @@ rfm_status rfm_add_points(rfm_problem* p, int32_t kind, int64_t npts, const doub
                           int32_t neighbor, const double* normal, int32_t comp, int32_t cont_order,
                           const double* data);
 
-/* Operator P(u) = sum of linear terms + sum of polynomial terms (Sec. 2.1). */
+/* Operator P(u) = sum of linear terms + sum of polynomial terms (Sec. 2.1)
+ * (+ the pointwise terms of rfm_set_fn_terms, which this call leaves in place).
+ * At most 16 linear and 8 polynomial terms. */
 rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nlin,
                             const rfm_poly_term* nl, int32_t nnl);
+
+/* Pointwise terms coeff * f(u_comp) added to the operator (Sec. 2.1, Sec. 5):
+ * replaces any earlier ones; at most 8 (n = 0 removes them).  eq and comp in
+ * [0, ncomp), fn one of RFM_FN_*, finite coeff, else RFM_EINVAL / RFM_ENUMERIC.
+ * Like rfm_set_operator it may be called again after rfm_finalize. */
+rfm_status rfm_set_fn_terms(rfm_problem* p, const rfm_fn_term* terms, int32_t n);
 
 /* Replaces the data of point group `group` (numbered in rfm_add_points order;
  * not a continuity group): data [npts][ncomp] for comp = -1, else [npts].

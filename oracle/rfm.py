@@ -99,6 +99,10 @@ def col_slice(prob: Problem, e: int, c: int) -> slice:
 # ---------------------------------------------------------------------------
 
 
+# f and f' of the pointwise terms coeff * f(u_c) (the paper's cosh nonlinearity, Sec. 5)
+_FN = {"cosh": (np.cosh, np.sinh), "sinh": (np.sinh, np.cosh), "exp": (np.exp, np.exp)}
+
+
 def _comps(prob: Problem, g) -> List[int]:
     return list(range(prob.ncomp)) if g.comp < 0 else [g.comp]
 
@@ -140,6 +144,14 @@ def group_F_J(prob: Problem, g, u: np.ndarray, with_J: bool = True):
                             if c2 != c:
                                 dprod = dprod * val[c2] ** p2
                         Jq[:, col_slice(prob, e, c)] += (coeff * dprod)[:, None] * jets[c][0]
+            # pointwise functions of one component: coeff f(u_c), derivative coeff f'(u_c) phi
+            for (eq, c, coeff, fn) in getattr(prob, "fn_terms", ()):
+                if eq != q:
+                    continue
+                f, df = _FN[fn]
+                Fq += coeff * f(val[c])
+                if with_J:
+                    Jq[:, col_slice(prob, e, c)] += (coeff * df(val[c]))[:, None] * jets[c][0]
             Fs.append(Fq)
             Js.append(Jq)
     elif g.kind in (KIND_DIRICHLET, KIND_NEUMANN):

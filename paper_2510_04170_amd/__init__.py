@@ -23,6 +23,8 @@ RFM_PDE, RFM_DIRICHLET, RFM_NEUMANN, RFM_CONTINUITY = 0, 1, 2, 3
 RFM_IPN, RFM_AMIPN = 0, 1
 RFM_PREC_F64, RFM_PREC_F32, RFM_PREC_BF16, RFM_PREC_FP8 = 0, 1, 2, 3
 RFM_SKETCH_GAUSSIAN, RFM_SKETCH_COUNT = 0, 1
+RFM_FN_COSH, RFM_FN_SINH, RFM_FN_EXP = 0, 1, 2
+_FN_CODE = {"cosh": RFM_FN_COSH, "sinh": RFM_FN_SINH, "exp": RFM_FN_EXP}
 RFM_MAX_STEPS = 64
 
 
@@ -32,6 +34,10 @@ class rfm_lin_term(C.Structure):
 
 class rfm_poly_term(C.Structure):
     _fields_ = [("eq", C.c_int32), ("coeff", C.c_double), ("pow", C.c_int32 * 4)]
+
+
+class rfm_fn_term(C.Structure):
+    _fields_ = [("eq", C.c_int32), ("comp", C.c_int32), ("coeff", C.c_double), ("fn", C.c_int32)]
 
 
 class rfm_solve_opts(C.Structure):
@@ -89,6 +95,7 @@ _SIGS = {
     "rfm_set_features": (C.c_int, [_P, C.c_int32, _D, _D]),
     "rfm_add_points": (C.c_int, [_P, C.c_int32, C.c_int64, _D, C.c_int32, C.c_int32, _D, C.c_int32, C.c_int32, _D]),
     "rfm_set_operator": (C.c_int, [_P, C.POINTER(rfm_lin_term), C.c_int32, C.POINTER(rfm_poly_term), C.c_int32]),
+    "rfm_set_fn_terms": (C.c_int, [_P, C.POINTER(rfm_fn_term), C.c_int32]),
     "rfm_finalize": (C.c_int, [_P]),
     "rfm_set_group_data": (C.c_int, [_P, C.c_int32, _D]),
     "rfm_num_unknowns": (C.c_int64, [_P]),
@@ -313,6 +320,13 @@ class RfmProblem:
             Pt[i] = rfm_poly_term(eq, coeff, p4)
         _check(lib().rfm_set_operator(self.h, L, len(lin_terms), Pt, len(poly_terms)))
 
+    def set_fn_terms(self, fn_terms):
+        """Pointwise terms (eq, comp, coeff, 'cosh' | 'sinh' | 'exp' or an RFM_FN_* code)."""
+        T = (rfm_fn_term * max(1, len(fn_terms)))()
+        for i, (eq, comp, coeff, fn) in enumerate(fn_terms):
+            T[i] = rfm_fn_term(eq, comp, coeff, _FN_CODE[fn] if isinstance(fn, str) else int(fn))
+        _check(lib().rfm_set_fn_terms(self.h, T, len(fn_terms)))
+
     def finalize(self):
         _check(lib().rfm_finalize(self.h))
 
@@ -324,6 +338,7 @@ class RfmProblem:
         """Take the operator and point data of another description with the same
         partition, features and points (a member of the same parameter family)."""
         self.set_operator(desc.lin_terms, desc.poly_terms)
+        self.set_fn_terms(getattr(desc, "fn_terms", []))
         for i, g in enumerate(desc.groups):
             if g.data is not None and len(g.x):
                 self.set_group_data(i, g.data)
@@ -503,5 +518,7 @@ def from_description(desc, device: int = 0, stream: Optional[int] = None) -> Rfm
     for g in desc.groups:
         p.add_points(g.kind, g.x, g.owner, g.neighbor, g.normal, g.comp, g.cont_order, g.data)
     p.set_operator(desc.lin_terms, desc.poly_terms)
+    if getattr(desc, "fn_terms", None):
+        p.set_fn_terms(desc.fn_terms)
     p.finalize()
     return p

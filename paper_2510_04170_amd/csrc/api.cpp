@@ -514,7 +514,9 @@ rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nli
     RFM_CHECK(nlin >= 0 && nlin <= kMaxLin && nnl >= 0 && nnl <= kMaxPoly, RFM_EINVAL,
               "rfm_set_operator: at most 16 linear and 8 polynomial terms");
     RFM_CHECK((nlin == 0 || lin) && (nnl == 0 || nl), RFM_EINVAL, "rfm_set_operator: NULL terms");
-    OpDesc op{};
+    OpDesc op = P.op;  // keeps the pointwise terms
+    op.nlin = 0;
+    op.npoly = 0;
     op.nlin = nlin;
     for (int i = 0; i < nlin; ++i) {
       const auto& t = lin[i];
@@ -544,6 +546,29 @@ rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nli
     }
     P.op = op;
     P.have_operator = true;
+  });
+}
+
+rfm_status rfm_set_fn_terms(rfm_problem* p, const rfm_fn_term* terms, int32_t n) {
+  return guarded([&] {
+    Problem& P = get(p);
+    RFM_CHECK(n >= 0 && n <= kMaxFn, RFM_EINVAL, "rfm_set_fn_terms: at most 8 terms");
+    RFM_CHECK(n == 0 || terms, RFM_EINVAL, "rfm_set_fn_terms: NULL terms");
+    OpDesc op = P.op;
+    op.nfn = n;
+    for (int i = 0; i < n; ++i) {
+      const auto& t = terms[i];
+      RFM_CHECK(t.eq >= 0 && t.eq < P.ncomp && t.comp >= 0 && t.comp < P.ncomp, RFM_EINVAL,
+                "rfm_set_fn_terms: term index out of range");
+      RFM_CHECK(t.fn == RFM_FN_COSH || t.fn == RFM_FN_SINH || t.fn == RFM_FN_EXP, RFM_EINVAL,
+                "rfm_set_fn_terms: unknown function");
+      RFM_CHECK(std::isfinite(t.coeff), RFM_ENUMERIC, "rfm_set_fn_terms: non-finite coefficient");
+      op.fn_eq[i] = t.eq;
+      op.fn_comp[i] = t.comp;
+      op.fn_kind[i] = t.fn;
+      op.fn_coeff[i] = t.coeff;
+    }
+    P.op = op;
   });
 }
 

@@ -153,6 +153,14 @@ __device__ void row_values(const RowsCtx& C, int64_t r, const double* __restrict
         dp[c] += d;
       }
     }
+    for (int i = 0; i < C.op.nfn; ++i) {
+      if (C.op.fn_eq[i] != q) continue;
+      const int c = C.op.fn_comp[i];
+      double f, df;
+      fn_eval(C.op.fn_kind[i], val[c], &f, &df);
+      Fp += C.op.fn_coeff[i] * f;
+      dp[c] += C.op.fn_coeff[i] * df;
+    }
 #pragma unroll
     for (int c = 0; c < kMaxComp; ++c) {
       if (c >= K) break;
@@ -248,6 +256,7 @@ __global__ void __launch_bounds__(256) k_assemble(RowsCtx C, const TileDesc* __r
 // Linear part and field values along u and du for the line search:
 //   ab[r] = {a_r, b_r, vu_0..vu_{K-1}, vd_0..vd_{K-1}}
 //   F_r(alpha) = a_r + alpha b_r + sum_poly coeff prod_c (vu_c + alpha vd_c)^p_c
+//                + sum_fn coeff f(vu_c + alpha vd_c)
 template <int KPER>
 __global__ void __launch_bounds__(256) k_row_eval(RowsCtx C, int64_t m, const double* __restrict__ u,
                                                   const double* __restrict__ du, double* __restrict__ ab) {
@@ -348,6 +357,13 @@ __global__ void __launch_bounds__(kRedBlock) k_phi(RowsCtx C, int64_t m, const d
         double prod = C.op.poly_coeff[i];
         for (int c = 0; c < K; ++c) prod *= ipow(o[2 + c] + alpha * o[2 + K + c], C.op.poly_pow[i][c]);
         F += prod;
+      }
+      for (int i = 0; i < C.op.nfn; ++i) {
+        if (C.op.fn_eq[i] != rd.sel) continue;
+        const int c = C.op.fn_comp[i];
+        double f, df;
+        fn_eval(C.op.fn_kind[i], o[2 + c] + alpha * o[2 + K + c], &f, &df);
+        F += C.op.fn_coeff[i] * f;
       }
     }
     if (Fout) Fout[r] = F;

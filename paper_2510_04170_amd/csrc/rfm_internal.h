@@ -90,6 +90,7 @@ constexpr int kMaxDim = 4;
 constexpr int kMaxComp = 4;
 constexpr int kMaxLin = 16;
 constexpr int kMaxPoly = 8;
+constexpr int kMaxFn = 8;
 constexpr int kMaxRowWidth = 1024;  // widest Jacobian row (16 values per lane of a wave)
 constexpr int kTileRows = 64;       // rows per Jacobian tile
 constexpr int kMaxPieces = 16;      // pieces of D J in a low-precision sketch
@@ -102,7 +103,23 @@ struct OpDesc {
   int poly_eq[kMaxPoly];
   int poly_pow[kMaxPoly][kMaxComp];
   double poly_coeff[kMaxPoly];
+  int nfn;
+  int fn_eq[kMaxFn], fn_comp[kMaxFn], fn_kind[kMaxFn];  // kind: RFM_FN_*
+  double fn_coeff[kMaxFn];
 };
+
+// f(v) and f'(v) of a pointwise term
+__host__ __device__ inline void fn_eval(int kind, double v, double* f, double* df) {
+  if (kind == RFM_FN_EXP) {
+    const double e = exp(v);
+    *f = e;
+    *df = e;
+  } else {
+    const double c = cosh(v), s = sinh(v);
+    *f = kind == RFM_FN_COSH ? c : s;
+    *df = kind == RFM_FN_COSH ? s : c;
+  }
+}
 
 struct GeomDesc {
   int dim, ncomp, J, nbox;

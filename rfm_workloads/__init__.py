@@ -40,6 +40,11 @@ D_X0, D_X1, D_X2, D_X3 = 1, 2, 3, 4   # first derivative along axis k is 1 + k
 D_LAPLACE = 8            # sum of second derivatives over all axes
 D_LAPLACE_SPACE = 9      # sum of second derivatives over all axes but the last (time)
 
+# pointwise functions of one field component in a nonlinear term (coeff * f(u_c))
+FN_COSH, FN_SINH, FN_EXP = "cosh", "sinh", "exp"
+FN_CODES = {FN_COSH: 0, FN_SINH: 1, FN_EXP: 2}
+_FN_VALUE = {FN_COSH: np.cosh, FN_SINH: np.sinh, FN_EXP: np.exp}
+
 
 @dataclass
 class PointGroup:
@@ -75,6 +80,7 @@ class Problem:
     test_x: np.ndarray                 # [ntest, dim] points for the relative L2 error
     test_owner: np.ndarray             # [ntest] int32
     params: dict = field(default_factory=dict)
+    fn_terms: List[Tuple[int, int, float, str]] = field(default_factory=list)  # (eq, comp, coeff, function)
 
     @property
     def nbox(self) -> int:
@@ -229,7 +235,7 @@ def jet_config4(x: np.ndarray) -> Jet:
     return val[:, None], np.stack([gx, gy, gt], 1)[:, None, :], lap[:, None], lap_space[:, None]
 
 
-def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int) -> np.ndarray:
+def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int, fn_terms=()) -> np.ndarray:
     """Right-hand side f = P(u*) at the points, one column per equation."""
     val, grad, lap, lap_space = jet
     n = val.shape[0]
@@ -252,6 +258,8 @@ def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int) -> np.ndarr
             if p:
                 term = term * val[:, c] ** p
         f[:, q] += coeff * term
+    for (q, c, coeff, fn) in fn_terms:
+        f[:, q] += coeff * _FN_VALUE[fn](val[:, c])
     return f
 
 
@@ -261,7 +269,7 @@ def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int) -> np.ndarr
 
 def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_terms, poly_terms,
            seed=0, dirichlet_faces=None, test_per_dim=None, inside=None, extra_groups=None,
-           params=None):
+           params=None, fn_terms=()):
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
     nsub = np.asarray(nsub, np.int64)
@@ -278,7 +286,7 @@ def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_term
         pts = pts[keep(pts)]
         if pts.shape[0] == 0:
             continue
-        f = apply_operator_to_jet(jet_fn(pts), lin_terms, poly_terms, ncomp)
+        f = apply_operator_to_jet(jet_fn(pts), lin_terms, poly_terms, ncomp, fn_terms)
         groups.append(PointGroup(KIND_PDE, pts, e, data=f))
 
     # continuity groups: direction, plane, transverse box (axis 0 fastest)
@@ -331,7 +339,8 @@ def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_term
     return Problem(name=name, dim=dim, ncomp=ncomp, lo=lo, hi=hi, nsub=nsub, J=J, W=W, b=b,
                    groups=groups, lin_terms=list(lin_terms), poly_terms=list(poly_terms),
                    exact=exact, test_x=np.concatenate(tx), test_owner=np.concatenate(to),
-                   params=dict(params or {}, seed=seed, R=R, q_int=q_int, q_face=q_face))
+                   params=dict(params or {}, seed=seed, R=R, q_int=q_int, q_face=q_face),
+                   fn_terms=list(fn_terms))
 
 
 # ----------------------------------------------------------------------------
@@ -539,9 +548,35 @@ def make_config(i: int, **kw) -> Problem:
     return [config1, config2, config3_nohole, config4_nohole][i](**kw)
 
 
+def jet_helmholtz_cosh(x: np.ndarray) -> Jet:
+    """u* = (2 + |x|^2) sin(pi x) sin(pi y) sin(pi z), its gradient and Laplacian."""
+    pi = math.pi
+    s = [np.sin(pi * x[:, a]) for a in range(3)]
+    c = [np.cos(pi * x[:, a]) for a in range(3)]
+    S = s[0] * s[1] * s[2]
+    dS = np.stack([pi * c[0] * s[1] * s[2], pi * s[0] * c[1] * s[2], pi * s[0] * s[1] * c[2]], 1)
+    p = 2.0 + (x[:, :3] ** 2).sum(1)
+    val = p * S
+    grad = 2.0 * x[:, :3] * S[:, None] + p[:, None] * dS
+    lap = 6.0 * S + 4.0 * (x[:, :3] * dS).sum(1) - 3.0 * pi * pi * p * S
+    return val[:, None], grad[:, None, :], lap[:, None], lap[:, None]
+
+
+def helmholtz_cosh(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, test_per_dim=None) -> Problem:
+    """3-D nonlinear Helmholtz with a cosh term on the unit cube (the paper's IPN / AMIPN comparison,
+    Sec. 5): Lap u - 100 u + 10 cosh(u) = f, u* = (2 + |x|^2) sin(pi x) sin(pi y) sin(pi z),
+    Dirichlet u* on the boundary; q^3 collocation points per box, q x q face and interface grids."""
+    lin = [(0, 0, 1.0, D_LAPLACE), (0, 0, -100.0, D_ID)]
+    fn = [(0, 0, 10.0, FN_COSH)]
+    return _build("helmholtz_cosh_3d", 3, 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), nsub, J, R, q, q,
+                  jet_helmholtz_cosh, lin, [], seed=seed, test_per_dim=test_per_dim, fn_terms=fn)
+
+
 def jet_of(problem: Problem):
     """Closed-form jet of the problem's manufactured solution."""
     name = problem.name
+    if name == "helmholtz_cosh_3d":
+        return jet_helmholtz_cosh
     if name == "poisson_cubic_2d":
         return jet_config1
     if name == "gray_scott_3d":

@@ -526,3 +526,50 @@ def test_count_sketch_preconditions():
     assert sa[0] / sa[-1] < 100.0
     res = O.lsqr(lambda v: DJ @ O.r_solve(R, v), lambda w: O.rt_solve(R, DJ.T @ w), -D * F, prob.n, 1e-10, 1000)
     assert res.istop in (1, 2)
+
+
+# ---------------------------------------------------------------------------
+# pointwise transcendental terms: Lap u - 100 u + 10 cosh(u) = f (Sec. 5, IPN vs AMIPN)
+# ---------------------------------------------------------------------------
+
+def test_cosh_data_matches_finite_differences():
+    prob = W.helmholtz_cosh(nsub=(2, 2, 2), J=4, q=4)
+    g = prob.groups[1]
+    assert g.kind == W.KIND_PDE
+    val, grad, sec = _fd_jet(prob.exact, g.x)
+    f = sec[:, 0].sum(-1) - 100.0 * val[:, 0] + 10.0 * np.cosh(val[:, 0])
+    assert np.abs(f - g.data[:, 0]).max() < 2e-5 * max(1.0, np.abs(g.data).max())
+
+
+@pytest.mark.parametrize("fn", ["cosh", "sinh", "exp"])
+def test_pointwise_term_jacobian_matches_central_differences(fn):
+    prob = W.helmholtz_cosh(nsub=(2, 1, 2), J=4, q=3)
+    prob.fn_terms = [(0, 0, 10.0, fn)]
+    u = 0.3 * np.random.default_rng(4).normal(size=prob.n)
+    F, J = O.assemble(prob, u)
+    Jfd = np.zeros_like(J)
+    for j in range(prob.n):
+        h = 1e-6
+        up, um = u.copy(), u.copy()
+        up[j] += h
+        um[j] -= h
+        Jfd[:, j] = (O.residual(prob, up) - O.residual(prob, um)) / (2 * h)
+    assert np.abs(J - Jfd).max() / np.abs(J).max() < 1e-7
+    # the term enters F with its sign and coefficient: removing it changes F by exactly 10 f(u_n)
+    prob0 = W.helmholtz_cosh(nsub=(2, 1, 2), J=4, q=3)
+    prob0.fn_terms = []
+    F0 = O.residual(prob0, u)
+    un = np.concatenate([O.feature_jet(prob, g.owner, 0, g.x)[0] @ u[O.col_slice(prob, g.owner, 0)]
+                         for g in prob.groups if g.kind == W.KIND_PDE])
+    npde = un.size
+    ref = {"cosh": np.cosh, "sinh": np.sinh, "exp": np.exp}[fn]
+    assert np.allclose(F[:npde] - F0[:npde], 10.0 * ref(un), rtol=1e-12, atol=1e-12)
+    assert np.array_equal(F[npde:], F0[npde:])
+
+
+def test_cosh_problem_by_manufactured_solution():
+    """The exact-Newton iteration reaches u* of the cosh problem to the discretisation's accuracy."""
+    prob = W.helmholtz_cosh(nsub=(1, 1, 1), J=300, q=10, test_per_dim=4)
+    u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
+    assert st.status == "ok"
+    assert np.all(O.rel_l2(prob, u) < 2e-3)
