@@ -92,8 +92,10 @@ rfm_status rfm_set_partition(rfm_problem* p, const double* lo, const double* hi,
  *   phi_{e,c,j}(x) = tanh(sum_a W[e][c][j][a] (x_a - mu_{e,a}) / sigma_{e,a} + b[e][c][j]),
  * with mu, sigma the centre and half-width of box e.  W: [nbox][ncomp][J][dim],
  * b: [nbox][ncomp][J].  Unknowns are ordered [box][component][feature]:
- * n = nbox * ncomp * J.  J may be at most 512 (the widest Jacobian row is
- * ncomp*J for PDE rows and 2*J for continuity rows; both must be <= 1024). */
+ * n = nbox * ncomp * J.  J may be at most 8192 (the widest Jacobian row is
+ * ncomp*J for PDE rows and 2*J for continuity rows; both must be <= 16384).
+ * Rows of up to 1024 values are assembled from registers, wider rows by
+ * recomputing the features over three sweeps of the row. */
 rfm_status rfm_set_features(rfm_problem* p, int32_t J, const double* W, const double* b);
 
 /* Append one point group.  Every point of the group belongs to box `owner`

@@ -146,7 +146,7 @@ static void finalize(Problem& P) {
   RFM_CHECK(!P.groups.empty(), RFM_EINVAL, "rfm_finalize: no points");
   const int K = P.ncomp, J = P.J;
   for (const auto& g : P.groups)
-    RFM_CHECK(row_width_of_group(P, g) <= kMaxRowWidth, RFM_EINVAL, "row wider than 1024 values");
+    RFM_CHECK(row_width_of_group(P, g) <= kMaxRowWidth, RFM_EINVAL, "row wider than 16384 values");
 
   // rows
   std::vector<RowDesc> rows;
@@ -234,6 +234,22 @@ static void finalize(Problem& P) {
       P.cb_off_h.push_back(pr.second);
     }
     P.cb_ptr_h[bk + 1] = (int32_t)P.cb_tile_h.size();
+  }
+  // FP64 sketch: for each column block the rows touching it (tile order, which is ascending row order)
+  // with the d_J offset of each row's segment in the block
+  P.sk_ptr_h.assign(nblk + 1, 0);
+  P.sk_row_h.clear();
+  P.sk_off_h.clear();
+  for (int bk = 0; bk < nblk; ++bk) {
+    for (auto& pr : contrib[bk]) {
+      const TileDesc& td = P.tiles_h[pr.first];
+      const int w = td.wA + td.wB;
+      for (int rr = 0; rr < td.nrows; ++rr) {
+        P.sk_row_h.push_back(td.row0 + rr);
+        P.sk_off_h.push_back(td.val_off + (int64_t)rr * w + pr.second);
+      }
+    }
+    P.sk_ptr_h[bk + 1] = (int64_t)P.sk_row_h.size();
   }
   // low-precision sketch operand: for each column block the 32-row groups (rows 32 g .. 32 g + 31) that hold a
   // row touching it, ascending, padded with empty groups to a multiple of 4; per slot the d_J offset of each row's
@@ -337,6 +353,14 @@ static void finalize(Problem& P) {
   }
   P.d_rowtile.resize(P.m);
   RFM_HIP(hipMemcpy(P.d_rowtile.p, rowtile.data(), P.m * 4, hipMemcpyHostToDevice));
+  P.d_sk_ptr.resize(P.sk_ptr_h.size());
+  RFM_HIP(hipMemcpy(P.d_sk_ptr.p, P.sk_ptr_h.data(), P.sk_ptr_h.size() * 8, hipMemcpyHostToDevice));
+  P.d_sk_row.resize(std::max<size_t>(1, P.sk_row_h.size()));
+  P.d_sk_off.resize(std::max<size_t>(1, P.sk_off_h.size()));
+  if (!P.sk_row_h.empty()) {
+    RFM_HIP(hipMemcpy(P.d_sk_row.p, P.sk_row_h.data(), P.sk_row_h.size() * 4, hipMemcpyHostToDevice));
+    RFM_HIP(hipMemcpy(P.d_sk_off.p, P.sk_off_h.data(), P.sk_off_h.size() * 8, hipMemcpyHostToDevice));
+  }
 
   // working storage sized by m and n
   P.d_J.resize(P.nvals);
@@ -433,10 +457,11 @@ rfm_status rfm_set_features(rfm_problem* p, int32_t J, const double* W, const do
     Problem& P = get(p);
     RFM_CHECK(!P.finalized, RFM_EINVAL, "rfm_set_features: problem already finalized");
     RFM_CHECK(P.have_partition, RFM_EINVAL, "rfm_set_features: set the partition first");
-    RFM_CHECK(J >= 1 && J <= 512, RFM_EINVAL, "rfm_set_features: J must be 1..512");
-    RFM_CHECK((int64_t)P.ncomp * J <= kMaxRowWidth, RFM_EINVAL, "rfm_set_features: ncomp*J exceeds 1024");
+    RFM_CHECK(J >= 1 && J <= 8192, RFM_EINVAL, "rfm_set_features: J must be 1..8192");
+    RFM_CHECK((int64_t)P.ncomp * J <= kMaxRowWidth, RFM_EINVAL, "rfm_set_features: ncomp*J exceeds 16384");
     RFM_CHECK(W && b, RFM_EINVAL, "rfm_set_features: NULL argument");
     const size_t nf = (size_t)P.geom.nbox * P.ncomp * J;
+    RFM_CHECK(nf < (size_t)INT32_MAX, RFM_EINVAL, "rfm_set_features: nbox*ncomp*J out of range");
     P.W = host_doubles(W, nf * P.dim);
     P.b = host_doubles(b, nf);
     RFM_CHECK(all_finite(P.W) && all_finite(P.b), RFM_ENUMERIC, "rfm_set_features: non-finite weights");

@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "mfma_f64.h"
 #include "rfm_internal.h"
 
 namespace rfm {
@@ -410,49 +411,9 @@ __global__ void __launch_bounds__(256) k_gemm_nn(double* __restrict__ C, int64_t
 // accumulators per lane on v_mfma_f64_4x4x4_4b_f64 (measured on gfx950 at
 // about 1.5x the FP64 rate of the 16x16x4 form).  Operands are staged through
 // LDS 16 values of k at a time; the next chunk's global loads (16 bytes per
-// lane) are issued before the current chunk's MFMAs.
+// lane) are issued before the current chunk's MFMAs.  The chunk routine and
+// the XCD-aware workgroup order are in mfma_f64.h.
 // ---------------------------------------------------------------------------
-constexpr int kBig = 128;
-constexpr int kKC = 16;
-
-typedef double v2d __attribute__((ext_vector_type(2)));
-
-// Workgroups are dealt to the 8 XCDs round robin (workgroup id mod 8), and each XCD has its own L2.
-// The position of workgroup `id` in a sequence where every XCD takes a contiguous range, so that
-// workgroups that share operands can be placed on one XCD and run there close in time.
-__device__ __forceinline__ int xcd_order(int id, int total) {
-  const int per = total / 8, x = id % 8, q = id / 8;
-  return q < per ? x * per + q : 8 * per + x;
-}
-
-// One 16-deep k-chunk on LDS tiles Xs[k][row], Ys[k][col] (row and column of the output).
-// v_mfma_f64_4x4x4_4b_f64 holds, for block b, A(i,k) in lane 16k+4b+i, B(k,j) in lane 16k+4b+j
-// and D(i,j) in lane 16i+4b+j.  With the A operand carrying 4 output columns (the same in every
-// block) and the B operand 16 output rows, acc[rg][cg] in lane l is output row rg*16 + l%16 and
-// column cg*4 + l/16 of the wavefront's 64 x 64 block: 16 consecutive rows of one column per
-// 16 lanes, which suits column-major stores.
-__device__ __forceinline__ void mfma4_chunk(const double (*Xs)[kBig + 1], const double (*Ys)[kBig + 1], int lane,
-                                            int wr, int wc, double (&acc)[4][16]) {
-#pragma unroll
-  for (int ks = 0; ks < kKC / 4; ++ks) {
-    const int kr = ks * 4 + lane / 16;
-    double x[4];
-#pragma unroll
-    for (int rg = 0; rg < 4; ++rg) x[rg] = Xs[kr][wr * 64 + rg * 16 + lane % 16];
-    // the column operands in two halves keep the kernel within 256 VGPRs
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      double y[8];
-#pragma unroll
-      for (int cg = 0; cg < 8; ++cg) y[cg] = Ys[kr][wc * 64 + (h * 8 + cg) * 4 + lane % 4];
-#pragma unroll
-      for (int rg = 0; rg < 4; ++rg)
-#pragma unroll
-        for (int cg = 0; cg < 8; ++cg)
-          acc[rg][h * 8 + cg] = __builtin_amdgcn_mfma_f64_4x4x4f64(y[cg], x[rg], acc[rg][h * 8 + cg], 0, 0, 0);
-    }
-  }
-}
 
 // C[M x N] += A[M x K] B, A column-major (lda even, 16-byte aligned), B[k][n] = Bt[n * ldb + k] (ldb even,
 // aligned); K a multiple of 16.  Loaders: A as row pairs (m = 2 (tid % 64), k = tid / 64 + 4 i), B as k pairs

@@ -90,6 +90,38 @@ __device__ __forceinline__ double feat_normal(const RowsCtx& C, int64_t f, doubl
   return dt * s;
 }
 
+// Nonlinear part of PDE equation q at field values val[]: the sum of its
+// polynomial and pointwise terms in Fp, and d Fp / d val[c] in dp[c].
+__device__ __forceinline__ void nonlinear_terms(const RowsCtx& C, int q, const double* val, double& Fp,
+                                                double* dp) {
+  const int K = C.g.ncomp;
+  Fp = 0.0;
+#pragma unroll
+  for (int c = 0; c < kMaxComp; ++c) dp[c] = 0.0;
+  for (int i = 0; i < C.op.npoly; ++i) {
+    if (C.op.poly_eq[i] != q) continue;
+    double prod = C.op.poly_coeff[i];
+    for (int c = 0; c < K; ++c) prod *= ipow(val[c], C.op.poly_pow[i][c]);
+    Fp += prod;
+    for (int c = 0; c < K; ++c) {
+      const int pc = C.op.poly_pow[i][c];
+      if (pc == 0) continue;
+      double d = C.op.poly_coeff[i] * pc * ipow(val[c], pc - 1);
+      for (int c2 = 0; c2 < K; ++c2)
+        if (c2 != c) d *= ipow(val[c2], C.op.poly_pow[i][c2]);
+      dp[c] += d;
+    }
+  }
+  for (int i = 0; i < C.op.nfn; ++i) {
+    if (C.op.fn_eq[i] != q) continue;
+    const int c = C.op.fn_comp[i];
+    double f, df;
+    fn_eval(C.op.fn_kind[i], val[c], &f, &df);
+    Fp += C.op.fn_coeff[i] * f;
+    dp[c] += C.op.fn_coeff[i] * df;
+  }
+}
+
 // Values of row r (positions c*J + j for PDE rows, j and J + j for continuity
 // rows) in vals[], lane-strided; the unscaled residual (data included) in F.
 // vals index: seg * KPER + k for feature j = lane + 64 k of segment/component seg.
@@ -138,29 +170,8 @@ __device__ void row_values(const RowsCtx& C, int64_t r, const double* __restrict
 #pragma unroll
     for (int c = 0; c < kMaxComp; ++c) val[c] = c < K ? wave_sum(accv[c]) : 0.0;
     accL = wave_sum(accL);
-    double Fp = 0.0, dp[kMaxComp] = {0, 0, 0, 0};
-    for (int i = 0; i < C.op.npoly; ++i) {
-      if (C.op.poly_eq[i] != q) continue;
-      double prod = C.op.poly_coeff[i];
-      for (int c = 0; c < K; ++c) prod *= ipow(val[c], C.op.poly_pow[i][c]);
-      Fp += prod;
-      for (int c = 0; c < K; ++c) {
-        const int pc = C.op.poly_pow[i][c];
-        if (pc == 0) continue;
-        double d = C.op.poly_coeff[i] * pc * ipow(val[c], pc - 1);
-        for (int c2 = 0; c2 < K; ++c2)
-          if (c2 != c) d *= ipow(val[c2], C.op.poly_pow[i][c2]);
-        dp[c] += d;
-      }
-    }
-    for (int i = 0; i < C.op.nfn; ++i) {
-      if (C.op.fn_eq[i] != q) continue;
-      const int c = C.op.fn_comp[i];
-      double f, df;
-      fn_eval(C.op.fn_kind[i], val[c], &f, &df);
-      Fp += C.op.fn_coeff[i] * f;
-      dp[c] += C.op.fn_coeff[i] * df;
-    }
+    double Fp, dp[kMaxComp];
+    nonlinear_terms(C, q, val, Fp, dp);
 #pragma unroll
     for (int c = 0; c < kMaxComp; ++c) {
       if (c >= K) break;
@@ -246,6 +257,128 @@ __global__ void __launch_bounds__(256) k_assemble(RowsCtx C, const TileDesc* __r
   for (int i = 0; i < 4 * KPER; ++i) {
     const int pos = val_pos<KPER>(kind, C.g.J, i, lane);
     if (pos >= 0 && pos < w) row[pos] = D * vals[i];
+  }
+  if (lane == 0) {
+    DF[r] = D * F;
+    Dout[r] = D;
+  }
+}
+
+// Rows wider than the register-held form (more than 512 features per box):
+// the row is swept three times, recomputing every feature value each time
+// (tanh is cheap next to the row's store): the field values and the linear
+// part for the residual and the nonlinear derivatives, then the row maximum
+// for the scale, then the scaled values into the stored row.  Entry (seg, j):
+// segment seg is the component of a PDE row or the side of a continuity row.
+__device__ __forceinline__ double wide_entry(const RowsCtx& C, const RowDesc& rd, const double* l,
+                                             const double* nrm, int64_t f, int seg, double& t) {
+  t = feat_t(C, f, l);
+  if (rd.kind == RFM_PDE) {
+    double Lv = 0.0;
+    for (int i = 0; i < C.op.nlin; ++i)
+      if (C.op.lin_eq[i] == rd.sel && C.op.lin_comp[i] == seg)
+        Lv += C.op.lin_coeff[i] * feat_deriv(C, C.op.lin_deriv[i], f, t);
+    return Lv;
+  }
+  double v;
+  if (rd.kind == RFM_CONTINUITY) {
+    v = rd.order == 0 ? t : feat_normal(C, f, t, nrm);
+    return seg ? -v : v;
+  }
+  return rd.kind == RFM_DIRICHLET ? t : feat_normal(C, f, t, nrm);
+}
+
+__global__ void __launch_bounds__(256) k_assemble_wide(RowsCtx C, const TileDesc* __restrict__ tiles,
+                                                       const int32_t* __restrict__ rowtile, int64_t m,
+                                                       const double* __restrict__ u, double cscale,
+                                                       double* __restrict__ Jv, double* __restrict__ DF,
+                                                       double* __restrict__ Dout) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
+  if (r >= m) return;
+  const RowDesc rd = C.rows[r];
+  const int K = C.g.ncomp, J = C.g.J, dim = C.g.dim;
+  double x[kMaxDim], nrm[kMaxDim], l[2][kMaxDim];
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) {
+    x[a] = a < dim ? C.px[(int64_t)rd.pt * dim + a] : 0.0;
+    nrm[a] = a < dim ? C.pn[(int64_t)rd.pt * dim + a] : 0.0;
+  }
+  norm_coords(C.g, rd.owner, x, l[0]);
+  const bool cont = rd.kind == RFM_CONTINUITY;
+  if (cont) norm_coords(C.g, rd.neighbor, x, l[1]);
+  const int nseg = rd.kind == RFM_PDE ? K : (cont ? 2 : 1);
+  // feature block of segment seg
+  auto fbase = [&](int seg) -> int64_t {
+    if (rd.kind == RFM_PDE) return ((int64_t)rd.owner * K + seg) * J;
+    const int e = (cont && seg) ? rd.neighbor : rd.owner;
+    return ((int64_t)e * K + rd.sel) * J;
+  };
+  // sweep 1: sums
+  double accv[kMaxComp] = {0, 0, 0, 0};
+  double accL = 0.0;
+  for (int seg = 0; seg < nseg; ++seg) {
+    const int64_t fb = fbase(seg);
+    const double* ls = l[cont ? seg : 0];
+    double av = 0.0;
+    for (int j = lane; j < J; j += kWave) {
+      double t;
+      const double v = wide_entry(C, rd, ls, nrm, fb + j, seg, t);
+      const double uj = u[fb + j];
+      accL += v * uj;
+      av += t * uj;
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c)
+      if (c == seg) accv[c] = av;
+  }
+  accL = wave_sum(accL);
+  double dp[kMaxComp] = {0, 0, 0, 0};
+  double F;
+  if (rd.kind == RFM_PDE) {
+    double val[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) val[c] = c < K ? wave_sum(accv[c]) : 0.0;
+    double Fp;
+    nonlinear_terms(C, rd.sel, val, Fp, dp);
+    F = accL + Fp - C.rowdata[r];
+  } else {
+    F = accL - (cont ? 0.0 : C.rowdata[r]);
+  }
+  // sweep 2: row maximum
+  double mx = 0.0;
+  for (int seg = 0; seg < nseg; ++seg) {
+    const int64_t fb = fbase(seg);
+    const double* ls = l[cont ? seg : 0];
+    double dps = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c)
+      if (c == seg) dps = dp[c];
+    for (int j = lane; j < J; j += kWave) {
+      double t;
+      const double v = wide_entry(C, rd, ls, nrm, fb + j, seg, t);
+      mx = fmax(mx, fabs(v + dps * t));
+    }
+  }
+  mx = wave_max(mx);
+  const double D = mx > 0.0 ? cscale / mx : 1.0;
+  // sweep 3: scaled values
+  const TileDesc td = tiles[rowtile[r]];
+  const int w = td.wA + td.wB;
+  double* row = Jv + td.val_off + (int64_t)(r - td.row0) * w;
+  for (int seg = 0; seg < nseg; ++seg) {
+    const int64_t fb = fbase(seg);
+    const double* ls = l[cont ? seg : 0];
+    double dps = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c)
+      if (c == seg) dps = dp[c];
+    for (int j = lane; j < J; j += kWave) {
+      double t;
+      const double v = wide_entry(C, rd, ls, nrm, fb + j, seg, t);
+      const int pos = seg * J + j;
+      if (pos < w) row[pos] = D * (v + dps * t);
+    }
   }
   if (lane == 0) {
     DF[r] = D * F;
@@ -539,7 +672,8 @@ void launch_assemble(Problem& P, const double* u, double c) {
     RFM_CASE(1) RFM_CASE(2) RFM_CASE(3) RFM_CASE(4) RFM_CASE(5) RFM_CASE(6) RFM_CASE(7) RFM_CASE(8)
 #undef RFM_CASE
     default:
-      throw Error(RFM_EINVAL, "features per box above 512");
+      hipLaunchKernelGGL(k_assemble_wide, grid, dim3(256), 0, P.stream, C, P.d_tiles.p, P.d_rowtile.p, P.m, u, c,
+                         P.d_J.p, P.d_DF.p, P.d_D.p);
   }
   RFM_HIP(hipGetLastError());
 }

@@ -91,7 +91,7 @@ constexpr int kMaxComp = 4;
 constexpr int kMaxLin = 16;
 constexpr int kMaxPoly = 8;
 constexpr int kMaxFn = 8;
-constexpr int kMaxRowWidth = 1024;  // widest Jacobian row (16 values per lane of a wave)
+constexpr int kMaxRowWidth = 16384;  // widest Jacobian row
 constexpr int kTileRows = 64;       // rows per Jacobian tile
 constexpr int kMaxPieces = 16;      // pieces of D J in a low-precision sketch
 
@@ -234,6 +234,8 @@ struct Problem {
   int64_t nvals = 0, npart = 0;
   int ntiles = 0;
   std::vector<int32_t> cb_ptr_h, cb_tile_h, cb_off_h;  // column block -> contributing tiles
+  std::vector<int64_t> sk_ptr_h, sk_off_h;  // column block -> its rows: d_J offset of each row's segment
+  std::vector<int32_t> sk_row_h;            // ... and the row index
   // low-precision sketch operand: per column block, the 32-row groups of rows touching it
   std::vector<int32_t> cbs_ptr_h, slot_group_h;
   std::vector<int64_t> slot_rowoff_h;     // [slot][32]: offset of the row's segment in d_J, or -1
@@ -246,6 +248,8 @@ struct Problem {
   DBuf<RowDesc> d_rows;
   DBuf<TileDesc> d_tiles;
   DBuf<int32_t> d_cb_ptr, d_cb_tile, d_cb_off;
+  DBuf<int64_t> d_sk_ptr, d_sk_off;
+  DBuf<int32_t> d_sk_row;
   DBuf<int32_t> d_rowtile;  // tile index of each row
 
   // device: current Jacobian (scaled), residual, scale

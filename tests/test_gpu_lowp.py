@@ -41,6 +41,8 @@ CASES = {
     "poisson2d_full": lambda: W.config1(),
     "grayscott_small": lambda: W.config2(nsub=(2, 2, 2), J=40, q=4, test_per_dim=3),
     "allencahn_small": lambda: W.config4_nohole(nsub=(2, 1, 2), J=70, q=4, test_per_dim=3),
+    # J = 600 > 512 features per box: 1200-wide continuity rows
+    "helmholtz_cosh_wide": lambda: W.helmholtz_cosh(nsub=(2, 1, 1), J=600, q=10, test_per_dim=3),
 }
 
 FMTS = {"bf16": 2, "fp8": 3}

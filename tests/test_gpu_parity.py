@@ -62,6 +62,13 @@ CASES = {
     "allencahn_hole_small": lambda: W.config4(nsub=(2, 2, 2), J=50, q=5, n_t=16, n_theta=12, test_per_dim=3),
     # Lap u - 100 u + 10 cosh(u) = f (a pointwise transcendental term), J = 40
     "helmholtz_cosh_small": lambda: W.helmholtz_cosh(nsub=(2, 2, 1), J=40, q=6, test_per_dim=3),
+    # more than 512 features per box: J = 600 gives 600-wide PDE and boundary rows and 1200-wide
+    # continuity rows (the register-free assembly) and two 512-column slabs of the FP64 sketch;
+    # m = 3200, n = 1200
+    "helmholtz_cosh_wide": lambda: W.helmholtz_cosh(nsub=(2, 1, 1), J=600, q=10, test_per_dim=3),
+    # Gray-Scott pair at J = 520: 1040-wide PDE rows with polynomial terms in both components;
+    # m = 3584, n = 2080
+    "grayscott_wide": lambda: W.config2(nsub=(2, 1, 1), J=520, q=8, test_per_dim=3),
 }
 
 
