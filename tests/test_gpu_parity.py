@@ -14,6 +14,7 @@ Tolerances (FP64 everywhere):
     geometries: <= 1e-6 against the oracle, see test_full_solve_with_holes).
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -459,35 +460,54 @@ def test_pointwise_terms_can_change_after_finalize():
 
 
 def _paper_cosh_rows():
-    path = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "paper_helmholtz_cosh.txt")
-    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_helmholtz_cosh.txt")
+    rows = {}
     for line in open(path):
         if line.strip() and not line.startswith("#"):
-            solver, q, J, it, nj, err = line.split()
-            rows.append((solver, int(q), int(J), int(it), int(nj), float(err)))
+            solver, q, J, it, nj, err, _sec = line.split()
+            rows.setdefault((int(q), int(J)), {})[solver] = (int(it), int(nj), float(err))
     return rows
 
 
-def test_ipn_and_amipn_against_the_paper_table():
-    """The paper's IPN / AMIPN comparison on the cosh problem at (2,2,2) boxes, q = 20, J = 400: AMIPN
-    needs the printed 2 Jacobian evaluations and about the printed outer steps, IPN about the printed
-    steps (one Jacobian each), and both reach the printed error within a factor of 2 (the random
-    features are a different draw of the same distribution)."""
-    rows = _paper_cosh_rows()
-    q, J = rows[0][1], rows[0][2]
+PAPER_COSH = _paper_cosh_rows()
+# the two largest rows take about 20 and 35 s of GPU time; RFM_PAPER_TABLE_FULL=1 runs them
+PAPER_COSH_LARGE = {(30, 2000), (30, 2400)}
+
+
+@pytest.mark.parametrize("qJ", sorted(PAPER_COSH), ids=lambda qJ: f"q{qJ[0]}_J{qJ[1]}")
+def test_ipn_and_amipn_against_the_paper_table(qJ):
+    """The paper's IPN / AMIPN comparison on the cosh problem at (2,2,2) boxes, q^3 points and J features
+    per box.  Both methods reach the printed error within a factor of 2 (the random features are another
+    draw of the same distribution); IPN takes one Jacobian per outer step and at most two outer steps more
+    than printed (its stop test, a change of the merit below 1e-10, meets the merit's rounding noise at the
+    largest sizes); AMIPN takes at most one outer step and one Jacobian more than printed, and fewer
+    Jacobians than IPN."""
+    if qJ in PAPER_COSH_LARGE and os.environ.get("RFM_PAPER_TABLE_FULL") != "1":
+        pytest.skip("large row: set RFM_PAPER_TABLE_FULL=1")
+    q, J = qJ
+    _announce(f"paper table q={q} J={J}")
     prob = W.helmholtz_cosh(nsub=(2, 2, 2), J=J, q=q)
     lp = R.from_description(prob)
     ex = prob.exact(prob.test_x)
     got = {}
-    for solver, _, _, it, nj, err in rows:
+    for solver in ("ipn", "amipn"):
+        it, nj, err = PAPER_COSH[qJ][solver]
         m = R.RFM_AMIPN if solver == "amipn" else R.RFM_IPN
         u, st, rc = lp.solve(None, R.default_opts(method=m, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5))
         e = _relerr(lp.eval(u, prob.test_x, prob.test_owner), ex)
         got[solver] = (st["outer_iters"], st["jac_evals"], e)
-        print(f"{solver}: IT {st['outer_iters']} NJ {st['jac_evals']} relL2 {e:.3e} (paper IT {it} NJ {nj} error {err:.2e})")
+        print(f"q {q} J {J} {solver}: IT {st['outer_iters']} NJ {st['jac_evals']} relL2 {e:.3e} "
+              f"({st['t_total']:.2f} s; paper IT {it} NJ {nj} error {err:.2e})")
         assert rc in (R.RFM_OK, R.RFM_ESTALL)
-        assert abs(st["outer_iters"] - it) <= 1
-        assert st["jac_evals"] == (st["outer_iters"] if solver == "ipn" else nj)
-        assert err / 2 < e < 2 * err
+        assert e < 2 * err
+        if solver == "ipn":
+            assert st["jac_evals"] == st["outer_iters"]
+            assert it - 1 <= st["outer_iters"] <= it + 2
+        else:
+            assert it - 1 <= st["outer_iters"] <= it + 1
+            assert st["jac_evals"] <= nj + 1
+    # the paper prints the same error for both methods except at J = 2000 (AMIPN 50x worse there)
+    if qJ != (30, 2000):
+        assert got["amipn"][2] < 2 * got["ipn"][2] and got["ipn"][2] < 2 * got["amipn"][2]
     assert got["amipn"][1] < got["ipn"][1]
     lp.close()
