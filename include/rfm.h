@@ -172,6 +172,12 @@ typedef struct {
   int32_t sketch_pieces;   /* pieces of D J in a BF16/FP8 sketch, 1..16; 0: 6 (BF16), 12 (FP8) */
   int32_t sketch_kind;     /* RFM_SKETCH_GAUSSIAN (default) or RFM_SKETCH_COUNT (FP64 only) */
   int32_t verbose;         /* 1: one line per outer step on stderr                   */
+  int32_t sketch_rows_per_pass; /* 0: the whole sketch B (s x n) is formed and factored at once
+                              unless B, R and the QR workspace would take more than 60% of the
+                              device memory; then, or with a value > 0 (rounded down to a multiple
+                              of 128, at most 98,304), B is produced that many rows at a time and
+                              each block folded into R (rfm_stage_sketch_qr_streamed).  Gaussian
+                              sketches only. */
 } rfm_solve_opts;
 
 #define RFM_MAX_STEPS 64
@@ -278,6 +284,17 @@ int64_t rfm_sketch_rows(const rfm_problem* p);
  * triangular with a positive diagonal.  RFM_ESINGULAR if a diagonal entry is
  * zero or not finite. */
 rfm_status rfm_stage_qr(rfm_problem* p);
+
+/* Sketch and QR without holding B (for sketches larger than the device memory
+ * allows): the s = ceil(gamma n) rows of B = S (D J) (Gaussian, prec as in
+ * rfm_stage_sketch) are produced rows_per_pass at a time (a multiple of 128, at
+ * most 98,304; 0 picks about an eighth of the device memory) and each block B_k
+ * folded into R by the QR of [R; B_k] (R starts at 0).  R is the factor of the
+ * whole B (up to rounding), with a positive diagonal; B is not kept.  Memory:
+ * (512 + rows_per_pass) x n doubles for the block and R's 512 rows in work, and
+ * R's tiled storage.  RFM_ESINGULAR as rfm_stage_qr. */
+rfm_status rfm_stage_sketch_qr_streamed(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index,
+                                        int32_t prec, int32_t pieces, int64_t rows_per_pass);
 
 /* Columns [c0, c0 + ncols) of R, column-major [ncols][n] (zeros below the diagonal). */
 rfm_status rfm_get_r_cols(rfm_problem* p, int64_t c0, int64_t ncols, double* out);

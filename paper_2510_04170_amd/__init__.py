@@ -46,7 +46,7 @@ class rfm_solve_opts(C.Structure):
                 ("max_outer", C.c_int32), ("m_max", C.c_int32), ("tau_rel", C.c_double),
                 ("row_scale_c", C.c_double), ("gs_iters", C.c_int32), ("sketch_prec", C.c_int32),
                 ("lsqr_prec", C.c_int32), ("sketch_pieces", C.c_int32), ("sketch_kind", C.c_int32),
-                ("verbose", C.c_int32)]
+                ("verbose", C.c_int32), ("sketch_rows_per_pass", C.c_int32)]
 
 
 class rfm_solve_stats(C.Structure):
@@ -119,6 +119,8 @@ _SIGS = {
     "rfm_get_sketch_cols": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
     "rfm_sketch_rows": (C.c_int64, [_P]),
     "rfm_stage_qr": (C.c_int, [_P]),
+    "rfm_stage_sketch_qr_streamed": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64, C.c_int32, C.c_int32,
+                                               C.c_int64]),
     "rfm_get_r_cols": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
     "rfm_r_solve": (C.c_int, [_P, _D, _D]),
     "rfm_rt_solve": (C.c_int, [_P, _D, _D]),
@@ -439,6 +441,10 @@ class RfmProblem:
 
     def stage_qr(self):
         _check(lib().rfm_stage_qr(self.h))
+
+    def stage_sketch_qr_streamed(self, gamma: float, seed: int, jac_index: int, prec: int = RFM_PREC_F64,
+                                 pieces: int = 0, rows_per_pass: int = 0):
+        _check(lib().rfm_stage_sketch_qr_streamed(self.h, gamma, seed, jac_index, prec, pieces, rows_per_pass))
 
     def get_r_cols(self, c0: int, ncols: int) -> np.ndarray:
         out = np.zeros((ncols, self.n))

@@ -177,9 +177,10 @@ template <bool FP8>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_sketch_fixed(const int32_t* __restrict__ cbs_ptr,
                                                       const int32_t* __restrict__ slot_group,
                                                       const void* __restrict__ pan_, const int32_t* __restrict__ pexp,
-                                                      int64_t piece_stride, int npc, int J, int64_t s,
-                                                      double inv_scale, uint64_t seed, uint64_t jac,
-                                                      const void* __restrict__ table_, double* __restrict__ B) {
+                                                      int64_t piece_stride, int npc, int J, int64_t r0,
+                                                      int64_t nr, double inv_scale, uint64_t seed, uint64_t jac,
+                                                      const void* __restrict__ table_, double* __restrict__ out,
+                                                      int64_t ldo) {
   typedef typename std::conditional<FP8, uint8_t, uint16_t>::type TC;
   constexpr int LDW = FP8 ? 128 + 16 : 128 + 8;
   constexpr int BITS = FP8 ? 4 : 8;
@@ -189,7 +190,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
   const int q = lane / 16, c16 = lane % 16;
-  const int64_t i0 = (int64_t)blockIdx.x * kRowsWG;
+  const int64_t i0 = r0 + (int64_t)blockIdx.x * kRowsWG, iend = r0 + nr;
   const int blk = blockIdx.y;
   const int colw = blockIdx.z * kColsWG + wc * 80;
   tab[tid] = reinterpret_cast<const TC*>(table_)[tid];
@@ -319,13 +320,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
   for (int tc = 0; tc < kCT; ++tc) {
     const int col = colw + 16 * tc + c16;
     if (col >= J) continue;
-    double* bcol = B + ((int64_t)blk * J + col) * s;
+    double* bcol = out + ((int64_t)blk * J + col) * ldo - r0;
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t i = i0 + wr * 64 + rt * 16 + 4 * q + t;
-        if (i < s) bcol[i] = acc[rt][tc][t];
+        if (i < iend) bcol[i] = acc[rt][tc][t];
       }
   }
 }
@@ -388,6 +389,7 @@ static void upload_tables(Problem& P) {
 }
 
 void launch_cast_panels(Problem& P, int prec, int pieces) {
+  upload_tables(P);
   const int npc = pieces > 0 ? pieces : default_pieces(prec);
   RFM_CHECK(npc >= 1 && npc <= kMaxPieces, RFM_EINVAL, "sketch pieces must be 1..16");
   const int64_t nchunks = P.nslots / 4;
@@ -420,33 +422,40 @@ void launch_cast_f32(Problem& P) {
   P.have_J32 = true;
 }
 
-void launch_sketch_lowp(Problem& P, uint64_t seed, uint64_t jac_index, int prec, int pieces) {
+void launch_sketch_lowp_rows(Problem& P, uint64_t seed, uint64_t jac_index, int prec, int64_t r0, int64_t nr,
+                             double* out, int64_t ldo) {
   RFM_CHECK(prec == RFM_PREC_BF16 || prec == RFM_PREC_FP8, RFM_EINVAL, "sketch precision must be BF16 or FP8");
-  upload_tables(P);
-  launch_cast_panels(P, prec, pieces);
+  RFM_CHECK(P.pan_prec == prec, RFM_EINVAL, "sketch: the operand pieces are not formed");
+  RFM_CHECK(r0 % kRowsWG == 0 && nr >= 0 && r0 + nr <= P.s && ldo >= nr, RFM_EINVAL, "sketch: bad row range");
+  if (nr == 0) return;
   const int npc = P.pan_pieces;
-  const size_t need = (size_t)P.s * P.n;
-  P.d_B.resize(need);
   const int nblk = P.geom.nbox * P.ncomp;
-  dim3 grid((unsigned)((P.s + kRowsWG - 1) / kRowsWG), (unsigned)nblk, (unsigned)((P.J + kColsWG - 1) / kColsWG));
+  dim3 grid((unsigned)((nr + kRowsWG - 1) / kRowsWG), (unsigned)nblk, (unsigned)((P.J + kColsWG - 1) / kColsWG));
   const double ks = prec == RFM_PREC_BF16 ? 32.0 : 4.0;
   const double inv_scale = 1.0 / (ks * std::sqrt((double)P.s));
   const int64_t per_piece = P.nslots * (int64_t)P.J * 32;
   // algorithmic work: every piece against S on the padded row chunks; bytes: pieces once, B once
-  const double flops = 2.0 * (double)P.s * (double)per_piece * npc;
-  const double bytes = (prec == RFM_PREC_BF16 ? 2.0 : 1.0) * npc * (double)per_piece + 8.0 * (double)P.s * P.n;
+  const double flops = 2.0 * (double)nr * (double)per_piece * npc;
+  const double bytes = (prec == RFM_PREC_BF16 ? 2.0 : 1.0) * npc * (double)per_piece + 8.0 * (double)nr * P.n;
   if (prec == RFM_PREC_BF16) {
     ProfScope ps(P.prof, P.stream, "sketch_bf16", flops, bytes);
     hipLaunchKernelGGL(k_sketch_fixed<false>, grid, dim3(256), 0, P.stream, P.d_cbs_ptr.p, P.d_slot_group.p,
-                       (const void*)P.d_pan16.p, P.d_pexp.p, per_piece, npc, P.J, P.s, inv_scale, seed, jac_index,
-                       (const void*)P.d_tab16.p, P.d_B.p);
+                       (const void*)P.d_pan16.p, P.d_pexp.p, per_piece, npc, P.J, r0, nr, inv_scale, seed, jac_index,
+                       (const void*)P.d_tab16.p, out, ldo);
   } else {
     ProfScope ps(P.prof, P.stream, "sketch_fp8", flops, bytes);
     hipLaunchKernelGGL(k_sketch_fixed<true>, grid, dim3(256), 0, P.stream, P.d_cbs_ptr.p, P.d_slot_group.p,
-                       (const void*)P.d_pan8.p, P.d_pexp.p, per_piece, npc, P.J, P.s, inv_scale, seed, jac_index,
-                       (const void*)P.d_tab8.p, P.d_B.p);
+                       (const void*)P.d_pan8.p, P.d_pexp.p, per_piece, npc, P.J, r0, nr, inv_scale, seed, jac_index,
+                       (const void*)P.d_tab8.p, out, ldo);
   }
   RFM_HIP(hipGetLastError());
+}
+
+void launch_sketch_lowp(Problem& P, uint64_t seed, uint64_t jac_index, int prec, int pieces) {
+  RFM_CHECK(prec == RFM_PREC_BF16 || prec == RFM_PREC_FP8, RFM_EINVAL, "sketch precision must be BF16 or FP8");
+  launch_cast_panels(P, prec, pieces);
+  P.d_B.resize((size_t)P.s * P.n);
+  launch_sketch_lowp_rows(P, seed, jac_index, prec, 0, P.s, P.d_B.p, P.s);
 }
 
 void get_sketch_operand(Problem& P, int piece, int blk, int64_t slot0, int64_t nslots, double* out, int32_t* groups,

@@ -27,6 +27,8 @@
 // tiled upper storage used by the triangular solves and flags a zero or
 // non-finite diagonal entry.
 #include <algorithm>
+#include <chrono>
+#include <functional>
 #include <cmath>
 
 #include "mfma_f64.h"
@@ -788,6 +790,61 @@ __global__ void k_get_r_cols(const double* __restrict__ Rt, int n, int64_t c0, d
   }
 }
 
+// Streamed QR: rows col0 .. col0 + 511 of the tiled R, columns col0 .. n - 1, into the slot rows
+// 0 .. 511 of Y (column j at Y[j ldy + r]); zero below R's diagonal and past row n - 1.
+__global__ void k_strip_in(const double* __restrict__ Rt, int n, int64_t col0, double* __restrict__ Y, int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t jcol = col0 + e / kWide;
+  const int r = (int)(e % kWide);
+  if (jcol >= n) return;
+  const int64_t i = col0 + r;
+  double v = 0.0;
+  if (i < n && i <= jcol) {
+    const int bi = (int)(i / kTB), bj = (int)(jcol / kTB);
+    v = Rt[((size_t)bj * (bj + 1) / 2 + bi) * kTB * kTB + (size_t)(jcol % kTB) * kTB + i % kTB];
+  }
+  Y[jcol * ldy + r] = v;
+}
+
+// the slot rows back into R (on and above the diagonal)
+__global__ void k_strip_out(double* __restrict__ Rt, int n, int64_t col0, const double* __restrict__ Y,
+                            int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t jcol = col0 + e / kWide;
+  const int r = (int)(e % kWide);
+  if (jcol >= n) return;
+  const int64_t i = col0 + r;
+  if (i < n && i <= jcol) {
+    const int bi = (int)(i / kTB), bj = (int)(jcol / kTB);
+    Rt[((size_t)bj * (bj + 1) / 2 + bi) * kTB * kTB + (size_t)(jcol % kTB) * kTB + i % kTB] = Y[jcol * ldy + r];
+  }
+}
+
+// sign[i] = -1 where R[i][i] < 0, else 1; flags a zero or non-finite diagonal entry
+__global__ void k_r_signs(const double* __restrict__ Rt, int n, double* __restrict__ sign, int32_t* __restrict__ sync) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int bi = i / kTB;
+  const double d = Rt[((size_t)bi * (bi + 1) / 2 + bi) * kTB * kTB + (size_t)(i % kTB) * kTB + i % kTB];
+  if (!(fabs(d) > 0.0 && isfinite(d))) sync[kSyncSingular] = 1;
+  sign[i] = d < 0.0 ? -1.0 : 1.0;
+}
+
+// rows times their signs; the diagonal past n set to 1 (the padded solve stays trivial)
+__global__ void __launch_bounds__(256) k_r_apply_signs(double* __restrict__ Rt, int n, const double* __restrict__ sign) {
+  const int bj = blockIdx.x, bi = blockIdx.y;
+  if (bi > bj) return;
+  double* tile = Rt + ((size_t)bj * (bj + 1) / 2 + bi) * kTB * kTB;
+  for (int e = threadIdx.x; e < kTB * kTB; e += 256) {
+    const int cc = e / kTB, rr = e % kTB;
+    const int i = bi * kTB + rr, jcol = bj * kTB + cc;
+    if (i < n)
+      tile[e] *= sign[i];
+    else if (i == jcol)
+      tile[e] = 1.0;
+  }
+}
+
 int g_num_cus = 0;
 
 int num_cus(int device) {
@@ -845,54 +902,98 @@ static void tn_split(int M, int ntile, int ncu, int cap, int* nsplit, int* krang
   *nsplit = (M + kr - 1) / kr;
 }
 
-void qr_factor(Problem& P) {
-  const int64_t s = P.s, n = P.n;
-  RFM_CHECK(s >= n, RFM_EINVAL, "QR: sketch has fewer rows than columns");
-  const int ncu = num_cus(P.device);
-  const int max_split = 16;
-  // workspace
-  const size_t vb = (size_t)(s + 1) * kWide;  // V of a 512-column outer panel, leading dimension M rounded up to even
-  const size_t tn = (size_t)max_split * std::max<int64_t>(n, kWide) * kWide;
-  const size_t small = 5 * kPanel * kPanel + 5 * kBig * kBig + 5 * kOuter * kOuter + kWide * kWide;
-  const size_t need = vb + small + 2 * (size_t)ncu * kPanel + 4 * kPanel + tn + (size_t)n * kWide + 256;
-  P.d_ws.resize(need);
-  double* Vw = P.d_ws.p;
-  double* T64 = Vw + vb;                     // 4 blocks of 64 x 64
-  double* T128 = T64 + 4 * kPanel * kPanel;  // 2 blocks of 128 x 128
-  double* G128 = T128 + 2 * kBig * kBig;
-  double* X128 = G128 + kBig * kBig;
-  double* Y128 = X128 + kBig * kBig;
-  double* T256 = Y128 + kBig * kBig;         // 2 blocks of 256 x 256: the two halves of an outer panel
-  double* G256 = T256 + 2 * kOuter * kOuter;
-  double* X256 = G256 + kOuter * kOuter;
-  double* Y256 = X256 + kOuter * kOuter;
-  double* T512 = Y256 + kOuter * kOuter;
-  double* G64 = T512 + kWide * kWide;        // summed 64-wide Gram blocks
-  double* Pp = G64 + kPanel * kPanel;
-  double* DR = Pp + 2 * (size_t)ncu * kPanel;
-  double* part = DR + 4 * kPanel;
-  double* W2 = part + tn;
-  P.d_tau.resize(n);
-  int32_t zero3[3] = {0, 0, 0};
-  RFM_HIP(hipMemcpyAsync(P.d_sync.p, zero3, sizeof(zero3), hipMemcpyHostToDevice, P.stream));
-  auto zero_block = [&](double* V, int64_t ldv, int c0, int ncols, int nrows) {
+namespace {
+
+// The blocked Householder QR on one column-major matrix A (leading dimension lda): workspace and the
+// steps of one 512-column outer panel.  Workspace is sized for matrices of up to Mmax rows and nmax
+// columns.
+class QrEngine {
+ public:
+  QrEngine(Problem& P, int64_t Mmax, int64_t nmax) : P(P), ncu(num_cus(P.device)) {
+    const size_t vb = (size_t)(Mmax + 1) * kWide;  // V of a 512-column outer panel, leading dimension M rounded up to even
+    const size_t tn = (size_t)max_split * std::max<int64_t>(nmax, kWide) * kWide;
+    const size_t small = 5 * kPanel * kPanel + 5 * kBig * kBig + 5 * kOuter * kOuter + kWide * kWide;
+    const size_t need = vb + small + 2 * (size_t)ncu * kPanel + 4 * kPanel + tn + (size_t)nmax * kWide + 256;
+    P.d_ws.resize(need);
+    Vw = P.d_ws.p;
+    T64 = Vw + vb;                     // 4 blocks of 64 x 64
+    T128 = T64 + 4 * kPanel * kPanel;  // 2 blocks of 128 x 128
+    G128 = T128 + 2 * kBig * kBig;
+    X128 = G128 + kBig * kBig;
+    Y128 = X128 + kBig * kBig;
+    T256 = Y128 + kBig * kBig;         // 2 blocks of 256 x 256: the two halves of an outer panel
+    G256 = T256 + 2 * kOuter * kOuter;
+    X256 = G256 + kOuter * kOuter;
+    Y256 = X256 + kOuter * kOuter;
+    T512 = Y256 + kOuter * kOuter;
+    G64 = T512 + kWide * kWide;        // summed 64-wide Gram blocks
+    Pp = G64 + kPanel * kPanel;
+    DR = Pp + 2 * (size_t)ncu * kPanel;
+    part = DR + 4 * kPanel;
+    W2 = part + tn;
+    int32_t zero3[3] = {0, 0, 0};
+    RFM_HIP(hipMemcpyAsync(P.d_sync.p, zero3, sizeof(zero3), hipMemcpyHostToDevice, P.stream));
+  }
+
+  // Factor the first min(512, ncols) columns of the M x ncols matrix A (its diagonal starting at A[0])
+  // and apply the reflectors to the remaining columns; tau[0 .. 511] receives the reflector scalars.
+  // The first 256 columns are factored, applied to the second 256 (K = 256), the second 256
+  // factored, the two T merged, and the rest updated once with K = 512.
+  void outer_step(double* A, int64_t lda, int M, int64_t ncols, double* tau) {
+    const int nbw = (int)std::min<int64_t>(kWide, ncols);
+    const int nb0 = std::min(kOuter, nbw), nb1 = nbw - nb0;
+    const int64_t Mv = (M + 1) & ~1;  // leading dimension of V: even, so that row pairs load as 16 bytes
+    factor256(A, lda, M, 0, nb0, Vw, Mv, T256, tau);
+    if (nb1 > 0) {
+      trailing(Vw, Mv, kOuter, T256, A + (int64_t)kOuter * lda, lda, M, nb1);
+      zero_block(Vw, Mv, kOuter, kOuter, kOuter);  // the second half's reflectors start at row 256
+      factor256(A, lda, M, kOuter, nb1, Vw + (int64_t)kOuter * Mv + kOuter, Mv, T256 + kOuter * kOuter, tau);
+    }
+    const int64_t N = ncols - nbw;
+    if (N > 0) {
+      // nbw = 512 here; G = V_a^T V_b over rows 256..M-1 (V_b is zero above row 256)
+      gram_wide(Vw + kOuter, Vw + (int64_t)kOuter * Mv + kOuter, Mv, M - kOuter, kOuter, G256);
+      merge_t(G256, T256, T256 + kOuter * kOuter, X256, Y256, kOuter, T512);
+      trailing(Vw, Mv, kWide, T512, A + (int64_t)kWide * lda, lda, M, N);
+    }
+    RFM_HIP(hipGetLastError());
+  }
+
+  // the singular / time-out flags raised by the panels and by k_extract_r or k_r_signs
+  void check_flags() {
+    int32_t flags[3];
+    RFM_HIP(hipMemcpyAsync(flags, P.d_sync.p, sizeof(flags), hipMemcpyDeviceToHost, P.stream));
+    RFM_HIP(hipStreamSynchronize(P.stream));
+    RFM_CHECK(flags[kSyncError] == 0, RFM_EDEVICE, "QR panel: grid barrier timed out");
+    RFM_CHECK(flags[kSyncSingular] == 0, RFM_ESINGULAR, "R has a zero or non-finite diagonal entry");
+  }
+
+  void fill(double* p, int64_t cnt, double v = 0.0) {
+    if (cnt > 0)
+      hipLaunchKernelGGL(k_fill, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, P.stream, p, cnt, v);
+  }
+
+ private:
+  Problem& P;
+  const int ncu;
+  static constexpr int max_split = 16;
+  double *Vw, *T64, *T128, *G128, *X128, *Y128, *T256, *G256, *X256, *Y256, *T512, *G64, *Pp, *DR, *part, *W2;
+
+  void zero_block(double* V, int64_t ldv, int c0, int ncols, int nrows) {
     const int64_t cnt = (int64_t)ncols * nrows;
     if (cnt > 0)
       hipLaunchKernelGGL(k_zero_block, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, P.stream, V, ldv, c0, ncols,
                          nrows);
-  };
-  auto fill = [&](double* p, int64_t cnt) {
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, P.stream, p, cnt, 0.0);
-  };
+  }
   // merged T of two reflector blocks of width w: [[Ta, -Ta G Tb], [0, Tb]] with G = Va^T Vb
-  auto merge_t = [&](const double* G, const double* Ta, const double* Tb, double* X, double* Y, int w, double* Tout) {
+  void merge_t(const double* G, const double* Ta, const double* Tb, double* X, double* Y, int w, double* Tout) {
     const unsigned g1 = (unsigned)((w * w + 255) / 256), g4 = (unsigned)((4 * w * w + 255) / 256);
     hipLaunchKernelGGL(k_sq_gemm, dim3(g1), dim3(256), 0, P.stream, G, Tb, 1.0, w, X);
     hipLaunchKernelGGL(k_sq_gemm, dim3(g1), dim3(256), 0, P.stream, Ta, X, -1.0, w, Y);
     hipLaunchKernelGGL(k_assemble_t, dim3(g4), dim3(256), 0, P.stream, Ta, Tb, Y, w, Tout);
-  };
+  }
   // split-row Gram V_a^T V_b of two w-wide (128 or 256) column blocks over K rows into G (w x w)
-  auto gram_wide = [&](const double* Va, const double* Vbk, int64_t ldv, int K, int w, double* G) {
+  void gram_wide(const double* Va, const double* Vbk, int64_t ldv, int K, int w, double* G) {
     int nsplit, krange;
     tn_split(K, (w / kBig) * (w / kBig), ncu, max_split, &nsplit, &krange);
     krange = (krange + kKC - 1) / kKC * kKC;
@@ -900,20 +1001,18 @@ void qr_factor(Problem& P) {
     hipLaunchKernelGGL((k_gemm_tn128<true, true>), dim3((w / kBig) * (w / kBig) * nsplit), dim3(256), 0, P.stream, Va,
                        ldv, Vbk, ldv, K, w, krange, part, w);
     hipLaunchKernelGGL(k_gsum, dim3((unsigned)((w * w + 255) / 256)), dim3(256), 0, P.stream, part, nsplit, w, G);
-  };
-
-  double* B = P.d_B.p;
-  auto gram_t = [&](const double* V, int64_t ldv, int K, int nb, const double* tau, double* Tout) {
+  }
+  void gram_t(const double* V, int64_t ldv, int K, int nb, const double* tau, double* Tout) {
     int nsplit, krange;
     tn_split(K, 1, std::max(1, ncu / 16), 64, &nsplit, &krange);
     hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit), dim3(256), 0, P.stream, V, ldv, V, ldv, K, nb, krange, part);
     hipLaunchKernelGGL(k_gsum64, dim3((unsigned)((nb * kPanel + 255) / 256)), dim3(256), 0, P.stream, part, nsplit,
                        nb, G64);
     hipLaunchKernelGGL(k_build_t, dim3(1), dim3(256), 0, P.stream, G64, 1, nb, tau, Tout);
-  };
-  // C (M x N at Cp, leading dimension s) <- (I - V T^T V^T) C for the K = 256 or 512 reflectors in
+  }
+  // C (M x N at Cp, leading dimension ldc) <- (I - V T^T V^T) C for the K = 256 or 512 reflectors in
   // V (leading dimension Mv): W = V^T C, W2 = -T^T W, C += V W2^T
-  auto trailing = [&](const double* V, int64_t Mv, int K, const double* T, double* Cp, int M, int64_t N) {
+  void trailing(const double* V, int64_t Mv, int K, const double* T, double* Cp, int64_t ldc, int M, int64_t N) {
     const int ntile = (int)((N + kBig - 1) / kBig);
     const int halves = K / kBig;
     int nsplit, krange;
@@ -924,12 +1023,12 @@ void qr_factor(Problem& P) {
       ProfScope ps(P.prof, P.stream, "qr_gemm_tn", 2.0 * M * (double)N * K,
                    8.0 * (2.0 * M * N + (double)M * K + (double)nsplit * N * K));
       // 16-byte loads of C need an even leading dimension and an aligned first column
-      const bool vec = (s % 2 == 0) && (reinterpret_cast<uintptr_t>(Cp) % 16 == 0);
+      const bool vec = (ldc % 2 == 0) && (reinterpret_cast<uintptr_t>(Cp) % 16 == 0);
       if (vec)
-        hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(halves * ntile * nsplit), dim3(256), 0, P.stream, V, Mv, Cp, s,
+        hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(halves * ntile * nsplit), dim3(256), 0, P.stream, V, Mv, Cp, ldc,
                            M, (int)N, krange, part, K);
       else
-        hipLaunchKernelGGL(k_gemm_tn128<false>, dim3(halves * ntile * nsplit), dim3(256), 0, P.stream, V, Mv, Cp, s,
+        hipLaunchKernelGGL(k_gemm_tn128<false>, dim3(halves * ntile * nsplit), dim3(256), 0, P.stream, V, Mv, Cp, ldc,
                            M, (int)N, krange, part, K);
     }
     if (K == kWide)
@@ -941,15 +1040,15 @@ void qr_factor(Problem& P) {
     {
       ProfScope ps(P.prof, P.stream, "qr_gemm_nn", 2.0 * M * (double)N * K,
                    8.0 * (2.0 * M * N + (double)M * K + (double)N * K));
-      hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig * ntile)), dim3(256), 0, P.stream, Cp, s,
-                         V, Mv, W2, (int64_t)K, M, (int)N, K);
+      hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig * ntile)), dim3(256), 0, P.stream, Cp,
+                         ldc, V, Mv, W2, (int64_t)K, M, (int)N, K);
     }
-  };
-  // Factor columns c0 .. c0 + nbh - 1 (nbh <= 256) of the current trailing matrix in four 64-column
-  // blocks; their reflectors go to Vh (row 0 = row c0 of B, leading dimension Mv) and the T of all
-  // of them to Tout.
-  auto factor256 = [&](int64_t c0, int nbh, double* Vh, int64_t Mv, double* Tout) {
-    const int Mh = (int)(s - c0);
+  }
+  // Factor columns c0 .. c0 + nbh - 1 (nbh <= 256) of the M-row matrix A (diagonal at A[0]) in four
+  // 64-column blocks; their reflectors go to Vh (row 0 = row c0 of A, leading dimension Mv) and the T
+  // of all of them to Tout.
+  void factor256(double* A, int64_t lda, int M, int c0, int nbh, double* Vh, int64_t Mv, double* Tout, double* tau) {
+    const int Mh = M - c0;
     const int nsp = (nbh + kPanel - 1) / kPanel;
     // V columns of blocks beyond the last one stay zero
     if (nsp < 4) zero_block(Vh, Mv, nsp * kPanel, (4 - nsp) * kPanel, Mh);
@@ -962,20 +1061,20 @@ void qr_factor(Problem& P) {
       nbs[sp] = nbsp;
       double* Vsp = Vh + (int64_t)sp * kPanel * Mv + sp * kPanel;
       if (sp > 0) zero_block(Vh, Mv, sp * kPanel, kPanel, sp * kPanel);
-      launch_panel(P, B + c_sp * s + c_sp, s, Msp, nbsp, P.d_tau.p + c_sp, Pp, DR, Vsp, Mv);
-      gram_t(Vsp, Mv, Msp, nbsp, P.d_tau.p + c_sp, T64 + (size_t)sp * kPanel * kPanel);
+      launch_panel(P, A + c_sp * lda + c_sp, lda, Msp, nbsp, tau + c_sp, Pp, DR, Vsp, Mv);
+      gram_t(Vsp, Mv, Msp, nbsp, tau + c_sp, T64 + (size_t)sp * kPanel * kPanel);
       const int Nr = nbh - (sp + 1) * kPanel;
       if (Nr > 0) {
         // apply this block's reflectors to the rest of the 256 columns
-        double* Cr = B + (c_sp + kPanel) * s + c_sp;
+        double* Cr = A + (c_sp + kPanel) * lda + c_sp;
         int nsplit, krange;
         tn_split(Msp, (Nr + 63) / 64, ncu, 64, &nsplit, &krange);
         hipLaunchKernelGGL(k_gemm_tn, dim3((unsigned)((Nr + 63) / 64), nsplit), dim3(256), 0, P.stream, Vsp, Mv, Cr,
-                           s, Msp, Nr, krange, part);
+                           lda, Msp, Nr, krange, part);
         hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((Nr + 3) / 4)), dim3(256), 0, P.stream, part, nsplit, Nr,
                            T64 + (size_t)sp * kPanel * kPanel, W2);
         hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((Msp + 63) / 64), (unsigned)((Nr + 63) / 64)), dim3(256), 0,
-                           P.stream, Cr, s, Vsp, Mv, W2, Msp, Nr, kPanel);
+                           P.stream, Cr, lda, Vsp, Mv, W2, Msp, Nr, kPanel);
       }
     }
     // T of the 256 reflectors: pairs of 64-blocks into 128-blocks, then the two 128-blocks
@@ -998,40 +1097,115 @@ void qr_factor(Problem& P) {
     else fill(G128, (int64_t)kBig * kBig);  // no reflectors past column 128 in this block
     merge_t(G128, T128, T128 + kBig * kBig, X128, Y128, kBig, Tout);
     RFM_HIP(hipGetLastError());
-  };
-
-  // 512-column outer panels: the first 256 columns are factored, applied to the second 256 (K = 256),
-  // the second 256 factored, the two T merged, and the trailing matrix updated once with K = 512
-  for (int64_t col0 = 0; col0 < n; col0 += kWide) {
-    const int nbw = (int)std::min<int64_t>(kWide, n - col0);
-    const int nb0 = std::min(kOuter, nbw), nb1 = nbw - nb0;
-    const int M = (int)(s - col0);
-    const int64_t Mv = (M + 1) & ~1;  // leading dimension of V: even, so that row pairs load as 16 bytes
-    factor256(col0, nb0, Vw, Mv, T256);
-    if (nb1 > 0) {
-      trailing(Vw, Mv, kOuter, T256, B + (col0 + kOuter) * s + col0, M, nb1);
-      zero_block(Vw, Mv, kOuter, kOuter, kOuter);  // the second half's reflectors start at row 256
-      factor256(col0 + kOuter, nb1, Vw + (int64_t)kOuter * Mv + kOuter, Mv, T256 + kOuter * kOuter);
-    }
-    const int64_t N = n - col0 - nbw;
-    if (N > 0) {
-      // nbw = 512 here; G = V_a^T V_b over rows 256..M-1 (V_b is zero above row 256)
-      gram_wide(Vw + kOuter, Vw + (int64_t)kOuter * Mv + kOuter, Mv, M - kOuter, kOuter, G256);
-      merge_t(G256, T256, T256 + kOuter * kOuter, X256, Y256, kOuter, T512);
-      trailing(Vw, Mv, kWide, T512, B + (col0 + kWide) * s + col0, M, N);
-    }
-    RFM_HIP(hipGetLastError());
   }
+};
+
+}  // namespace
+
+void qr_factor(Problem& P) {
+  const int64_t s = P.s, n = P.n;
+  RFM_CHECK(s >= n, RFM_EINVAL, "QR: sketch has fewer rows than columns");
+  QrEngine E(P, s, n);
+  P.d_tau.resize(n);
+  double* B = P.d_B.p;
+  for (int64_t col0 = 0; col0 < n; col0 += kWide)
+    E.outer_step(B + col0 * s + col0, s, (int)(s - col0), n - col0, P.d_tau.p + col0);
   // R to tiled storage
   const int nbt = (int)((n + kTB - 1) / kTB);
   P.d_R.resize((size_t)nbt * (nbt + 1) / 2 * kTB * kTB);
   hipLaunchKernelGGL(k_extract_r, dim3(nbt, nbt), dim3(256), 0, P.stream, B, s, (int)n, P.d_R.p, P.d_sync.p);
   RFM_HIP(hipGetLastError());
-  int32_t flags[3];
-  RFM_HIP(hipMemcpyAsync(flags, P.d_sync.p, sizeof(flags), hipMemcpyDeviceToHost, P.stream));
-  RFM_HIP(hipStreamSynchronize(P.stream));
-  RFM_CHECK(flags[kSyncError] == 0, RFM_EDEVICE, "QR panel: grid barrier timed out");
-  RFM_CHECK(flags[kSyncSingular] == 0, RFM_ESINGULAR, "R has a zero or non-finite diagonal entry");
+  E.check_flags();
+}
+
+int64_t qr_stream_rows(const Problem& P, int64_t want) {
+  const int64_t s = P.s, n = P.n;
+  int64_t b;
+  if (want > 0) {
+    b = want;
+  } else {
+    size_t fr = 0, tot = 0;
+    RFM_HIP(hipMemGetInfo(&fr, &tot));
+    // the sketch rows of one pass and the 512-row top slot in about an eighth of the device memory
+    b = (int64_t)((double)tot / 8.0 / (8.0 * (double)n)) - kWide;
+  }
+  // the panel kernel holds at most 52 rows per thread row of its 256 workgroups (106,496 rows)
+  b = std::min<int64_t>(b, 98304);
+  b = std::max<int64_t>(kBig, b / kBig * kBig);
+  return std::min<int64_t>(b, (s + kBig - 1) / kBig * kBig);
+}
+
+double streamed_sketch_qr(Problem& P, uint64_t seed, uint64_t jac_index, int prec, int pieces, int64_t rows_per_pass) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (prec != RFM_PREC_F64) {
+    launch_cast_panels(P, prec, pieces);
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  }
+  const double t_cast = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  auto rows = [&](int64_t r0, int64_t nr, double* out, int64_t ldo) {
+    if (prec == RFM_PREC_F64)
+      launch_sketch_rows(P, seed, jac_index, r0, nr, out, ldo);
+    else
+      launch_sketch_lowp_rows(P, seed, jac_index, prec, r0, nr, out, ldo);
+  };
+  return t_cast + qr_factor_streamed(P, rows, qr_stream_rows(P, rows_per_pass));
+}
+
+bool qr_should_stream(const Problem& P) {
+  size_t fr = 0, tot = 0;
+  RFM_HIP(hipMemGetInfo(&fr, &tot));
+  const int64_t nbt = (P.n + kTB - 1) / kTB;
+  const double r_bytes = (double)nbt * (nbt + 1) / 2 * kTB * kTB * 8.0;
+  // B, R and the QR's split partials in at most 60% of the device memory
+  const double need = 8.0 * (double)P.s * P.n + r_bytes + 8.0 * 16.0 * kWide * (double)std::max<int64_t>(P.n, kWide);
+  return need > 0.6 * (double)tot;
+}
+
+double qr_factor_streamed(Problem& P, const std::function<void(int64_t, int64_t, double*, int64_t)>& sketch_rows,
+                          int64_t rows_per_pass) {
+  const int64_t s = P.s, n = P.n;
+  RFM_CHECK(s >= n, RFM_EINVAL, "QR: sketch has fewer rows than columns");
+  RFM_CHECK(rows_per_pass >= kBig && rows_per_pass % kBig == 0, RFM_EINVAL,
+            "streamed QR: rows per pass must be a positive multiple of 128");
+  const int64_t b = std::min<int64_t>(rows_per_pass, (s + kBig - 1) / kBig * kBig);
+  const int64_t ldy = kWide + b;  // 512-row slot for R's rows above the pass's sketch rows
+  RFM_CHECK((double)ldy * n < 9e18 / 8, RFM_EINVAL, "streamed QR: buffer too large");
+  P.d_B.resize((size_t)ldy * n);
+  double* Y = P.d_B.p;
+  QrEngine E(P, ldy, n);
+  P.d_tau.resize(std::max<int64_t>(n, kWide));
+  const int nbt = (int)((n + kTB - 1) / kTB);
+  const size_t rsz = (size_t)nbt * (nbt + 1) / 2 * kTB * kTB;
+  P.d_R.resize(rsz);
+  E.fill(P.d_R.p, (int64_t)rsz);  // R = 0 before the first pass
+  double t_sketch = 0.0;
+  for (int64_t r0 = 0; r0 < s; r0 += b) {
+    const int64_t nr = std::min<int64_t>(b, s - r0);
+    // sketch rows r0 .. r0 + nr - 1 below the slot
+    RFM_HIP(hipStreamSynchronize(P.stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    sketch_rows(r0, nr, Y + kWide, ldy);
+    RFM_HIP(hipStreamSynchronize(P.stream));
+    t_sketch += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    // [R; B_pass] = Q R': each outer panel factors R's rows col0 .. col0 + 511 stacked on the pass's
+    // rows (R is zero below its diagonal, so the reflectors only touch those rows)
+    const int M = (int)(kWide + nr);
+    for (int64_t col0 = 0; col0 < n; col0 += kWide) {
+      const int64_t ncols = n - col0;
+      const unsigned g = (unsigned)((ncols * kWide + 255) / 256);
+      hipLaunchKernelGGL(k_strip_in, dim3(g), dim3(256), 0, P.stream, P.d_R.p, (int)n, col0, Y, ldy);
+      E.outer_step(Y + col0 * ldy, ldy, M, ncols, P.d_tau.p);
+      hipLaunchKernelGGL(k_strip_out, dim3(g), dim3(256), 0, P.stream, P.d_R.p, (int)n, col0, Y, ldy);
+    }
+    RFM_HIP(hipGetLastError());
+  }
+  // positive diagonal, identity padding, singular check
+  hipLaunchKernelGGL(k_r_signs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, P.stream, P.d_R.p, (int)n,
+                     P.d_tau.p, P.d_sync.p);
+  hipLaunchKernelGGL(k_r_apply_signs, dim3(nbt, nbt), dim3(256), 0, P.stream, P.d_R.p, (int)n, P.d_tau.p);
+  RFM_HIP(hipGetLastError());
+  E.check_flags();
+  return t_sketch;
 }
 
 void launch_get_r_cols(Problem& P, int64_t c0, int64_t ncols, double* out) {

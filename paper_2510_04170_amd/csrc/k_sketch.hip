@@ -130,24 +130,25 @@ __device__ __forceinline__ void box_muller(uint64_t x, double& z0, double& z1) {
   z1 = rad * sn;
 }
 
-// lb .. le: the block's rows in lrow / loff; nrt x nct tiles per block
+// Sketch rows r0 .. r0 + nr - 1 (r0 a multiple of 128) of B = S (D J) into out, sketch row r0 + i of
+// column c at out[c ldo + i].  lb .. le: the block's rows in lrow / loff; nrt x nct tiles per block.
 __global__ void __launch_bounds__(256, 2) k_sketch_f64(const int64_t* __restrict__ lptr,
                                                       const int32_t* __restrict__ lrow,
                                                       const int64_t* __restrict__ loff,
-                                                      const double* __restrict__ Jv, int J, int64_t s, int nrt,
-                                                      int nct, double inv_sqrt_s, uint64_t seed, uint64_t jac,
-                                                      double* __restrict__ B) {
+                                                      const double* __restrict__ Jv, int J, int64_t r0, int64_t nr,
+                                                      int nrt, int nct, double inv_sqrt_s, uint64_t seed,
+                                                      uint64_t jac, double* __restrict__ out, int64_t ldo) {
   __shared__ double Ss[2][kKC][kBig + 1];  // S tile [chunk row][sketch row]
   __shared__ double Ds[2][kKC][kBig + 1];  // D J tile [chunk row][column]
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int wr = wv / 2, wc = wv % 2;
   const int L = xcd_order(blockIdx.x, gridDim.x);
   const int rt = L % nrt, ct = (L / nrt) % nct, blk = L / nrt / nct;
-  const int64_t i0 = (int64_t)rt * kBig;
+  const int64_t i0 = r0 + (int64_t)rt * kBig, iend = r0 + nr;
   const int c0 = ct * kBig;
   const int64_t lb = lptr[blk], le = lptr[blk + 1];
   // wavefronts whose 64 x 64 block lies wholly past the last row or column skip the products
-  const bool active = i0 + wr * 64 < s && c0 + wc * 64 < J;
+  const bool active = i0 + wr * 64 < iend && c0 + wc * 64 < J;
   // draw role: sketch rows 8 gq .. 8 gq + 7 of the tile at chunk row gk
   const int gq = tid % 16, gk = tid / 16;
   // load role: column lc at chunk rows lk + 2 t (lk is the same across a wavefront)
@@ -206,30 +207,36 @@ __global__ void __launch_bounds__(256, 2) k_sketch_f64(const int64_t* __restrict
   for (int cg = 0; cg < 16; ++cg) {
     const int col = c0 + wc * 64 + cg * 4 + lane / 16;
     if (col >= J) continue;
-    double* bcol = B + ((int64_t)blk * J + col) * s;
+    double* bcol = out + ((int64_t)blk * J + col) * ldo - r0;
 #pragma unroll
     for (int rg = 0; rg < 4; ++rg) {
       const int64_t i = i0 + wr * 64 + rg * 16 + lane % 16;
-      if (i < s) bcol[i] = acc[rg][cg];
+      if (i < iend) bcol[i] = acc[rg][cg];
     }
   }
 }
 
 }  // namespace
 
-void launch_sketch(Problem& P, uint64_t seed, uint64_t jac_index, int prec) {
-  (void)prec;  // the FP64 product; lower-precision products are selected in the solver
-  const size_t need = (size_t)P.s * P.n;
-  P.d_B.resize(need);
+void launch_sketch_rows(Problem& P, uint64_t seed, uint64_t jac_index, int64_t r0, int64_t nr, double* out,
+                        int64_t ldo) {
+  RFM_CHECK(r0 % kBig == 0 && nr >= 0 && r0 + nr <= P.s && ldo >= nr, RFM_EINVAL, "sketch: bad row range");
+  if (nr == 0) return;
   const int nblk = P.geom.nbox * P.ncomp;
-  const int nrt = (int)((P.s + kBig - 1) / kBig), nct = (P.J + kBig - 1) / kBig;
+  const int nrt = (int)((nr + kBig - 1) / kBig), nct = (P.J + kBig - 1) / kBig;
   const int64_t nwg = (int64_t)nrt * nct * nblk;
   RFM_CHECK(nwg < (int64_t)INT32_MAX, RFM_EINVAL, "sketch: too many tiles");
   const double sq = 1.0 / sqrt((double)P.s);
-  ProfScope ps(P.prof, P.stream, "sketch_f64", 2.0 * (double)P.s * P.nvals, 8.0 * ((double)P.nvals + (double)P.s * P.n));
+  ProfScope ps(P.prof, P.stream, "sketch_f64", 2.0 * (double)nr * P.nvals, 8.0 * ((double)P.nvals + (double)nr * P.n));
   hipLaunchKernelGGL(k_sketch_f64, dim3((unsigned)nwg), dim3(256), 0, P.stream, P.d_sk_ptr.p, P.d_sk_row.p,
-                     P.d_sk_off.p, P.d_J.p, P.J, P.s, nrt, nct, sq, seed, jac_index, P.d_B.p);
+                     P.d_sk_off.p, P.d_J.p, P.J, r0, nr, nrt, nct, sq, seed, jac_index, out, ldo);
   RFM_HIP(hipGetLastError());
+}
+
+void launch_sketch(Problem& P, uint64_t seed, uint64_t jac_index, int prec) {
+  (void)prec;  // the FP64 product; lower-precision products are selected in the solver
+  P.d_B.resize((size_t)P.s * P.n);
+  launch_sketch_rows(P, seed, jac_index, 0, P.s, P.d_B.p, P.s);
 }
 
 }  // namespace rfm

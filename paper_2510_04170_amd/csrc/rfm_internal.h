@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -324,6 +325,9 @@ int reduce_blocks_rows(const Problem& P);
 
 // k_sketch.hip
 void launch_sketch(Problem& P, uint64_t seed, uint64_t jac_index, int prec);
+// sketch rows r0 .. r0 + nr - 1 (r0 a multiple of 128): row r0 + i of column c to out[c ldo + i]
+void launch_sketch_rows(Problem& P, uint64_t seed, uint64_t jac_index, int64_t r0, int64_t nr, double* out,
+                        int64_t ldo);
 
 // network shape check (mlp.hip): throws RFM_EINVAL unless in_dim / out_dim match
 void mlp_check_shape(rfm_mlp* net, int in_dim, int out_dim);
@@ -337,11 +341,24 @@ void sketch_table(int prec, double* out);
 void launch_cast_panels(Problem& P, int prec, int pieces);
 void launch_cast_f32(Problem& P);
 void launch_sketch_lowp(Problem& P, uint64_t seed, uint64_t jac_index, int prec, int pieces);
+// rows r0 .. r0 + nr - 1 (r0 a multiple of 128) after launch_cast_panels, as launch_sketch_rows
+void launch_sketch_lowp_rows(Problem& P, uint64_t seed, uint64_t jac_index, int prec, int64_t r0, int64_t nr,
+                             double* out, int64_t ldo);
 void get_sketch_operand(Problem& P, int piece, int blk, int64_t slot0, int64_t nslots, double* out, int32_t* groups,
                         int32_t* scale_exp);
 
 // k_qr.hip
 void qr_factor(Problem& P);   // in place on d_B, leaves R in d_R (tiled), throws RFM_ESINGULAR
+// Streamed form for sketches too large to hold: the s sketch rows are produced rows_per_pass at a time
+// by sketch_rows(r0, nr, out, ldo) (sketch row r0 + i of column c to out[c ldo + i]) and folded into
+// R; leaves R in d_R as qr_factor does and returns the seconds spent in sketch_rows.
+double qr_factor_streamed(Problem& P, const std::function<void(int64_t, int64_t, double*, int64_t)>& sketch_rows,
+                          int64_t rows_per_pass);
+bool qr_should_stream(const Problem& P);                   // B, R and workspace above 60% of the device memory
+int64_t qr_stream_rows(const Problem& P, int64_t want);  // rows per pass: want (> 0) or about 1/8 of the memory
+// Gaussian sketch (FP64, BF16 or FP8) of the current D J streamed into qr_factor_streamed; returns the
+// sketch seconds (operand casts included)
+double streamed_sketch_qr(Problem& P, uint64_t seed, uint64_t jac_index, int prec, int pieces, int64_t rows_per_pass);
 void launch_get_r_cols(Problem& P, int64_t c0, int64_t ncols, double* out);
 
 // k_trsv.hip

@@ -55,6 +55,23 @@ struct Driver {
     sync();
     double t1 = now();
     P.s = (int64_t)std::ceil(o.sketch_factor * (double)P.n);
+    if (o.sketch_rows_per_pass > 0 || qr_should_stream(P)) {
+      // B is produced and folded into R a block of rows at a time
+      RFM_CHECK(o.sketch_kind == RFM_SKETCH_GAUSSIAN, RFM_EINVAL,
+                "the sketch is too large to hold and only the Gaussian sketch is streamed");
+      P.have_B = false;
+      P.have_R = false;
+      const double t_sk = streamed_sketch_qr(P, o.sketch_seed, (uint64_t)jac_index, o.sketch_prec, o.sketch_pieces,
+                                             std::max(0, o.sketch_rows_per_pass));
+      P.have_R = true;
+      double t3 = now();
+      st.t_assemble += t1 - t0;
+      st.t_sketch += t_sk;
+      st.t_qr += (t3 - t1) - t_sk;
+      ++jac_index;
+      ++st.jac_evals;
+      return;
+    }
     if (o.sketch_kind == RFM_SKETCH_COUNT)
       launch_count_sketch(P, o.sketch_seed, (uint64_t)jac_index);
     else if (o.sketch_prec == RFM_PREC_F64)
@@ -318,6 +335,7 @@ void rfm_solve_opts_default(rfm_solve_opts* o) {
   o->sketch_pieces = 0;
   o->sketch_kind = RFM_SKETCH_GAUSSIAN;
   o->verbose = 0;
+  o->sketch_rows_per_pass = 0;
 }
 
 }  // extern "C"

@@ -48,6 +48,10 @@ CASES = {
 FMTS = {"bf16": 2, "fp8": 3}
 
 
+def _relerr_l(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
 def _announce(msg):
     sys.stdout.write(f"\n[gpu-test] {msg}\n")
     sys.stdout.flush()
@@ -145,6 +149,21 @@ def test_lowp_preconditioner_quality(case, fmt):
     sv = np.linalg.svd(DJ @ np.linalg.inv(Rg), compute_uv=False)
     print(f"{case['name']} {fmt}: kappa(D J R^-1) = {sv[0] / sv[-1]:.3f}")
     assert sv[0] / sv[-1] < 12.0
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_streamed_lowp_sketch_gives_the_same_r(case, fmt):
+    """The low-precision sketch produced 256 rows per pass into the streamed QR gives the R of the whole
+    low-precision sketch."""
+    lp = case["lp"]
+    lp.stage_assemble(case["u"], 100.0)
+    lp.stage_sketch(2.0, 1, 2, FMTS[fmt], 0)
+    B = lp.get_sketch_cols(0, lp.n)
+    lp.stage_qr()
+    Rw = lp.get_r_cols(0, lp.n)
+    lp.stage_sketch_qr_streamed(2.0, 1, 2, FMTS[fmt], 0, 256)
+    Rs = lp.get_r_cols(0, lp.n)
+    assert _relerr_l(Rs, Rw) < max(1e-12, 1e-15 * np.linalg.cond(B))
 
 
 def test_lsqr_on_fp32_jacobian(case):

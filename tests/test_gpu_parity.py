@@ -194,6 +194,22 @@ def test_qr_with_odd_sketch_rows(case):
     assert _relerr(Rg, O.qr_r(B)) < max(1e-12, 1e-15 * np.linalg.cond(B))
 
 
+def test_streamed_qr_matches_the_qr_of_the_whole_sketch(case):
+    """The sketch produced 256 rows at a time and folded into R (the QR of [R; B_k] per block) gives the
+    factor of the whole B: several passes, a ragged last pass, and for n > 512 several outer panels."""
+    lp, DJ = case["lp"], case["DJ"]
+    lp.stage_assemble(case["u"], 100.0)
+    lp.stage_sketch(2.0, 1, 0, R.RFM_PREC_F64)
+    B = lp.get_sketch_cols(0, lp.n)
+    lp.stage_sketch_qr_streamed(2.0, 1, 0, R.RFM_PREC_F64, 0, 256)
+    Rs = lp.get_r_cols(0, lp.n)
+    assert np.array_equal(np.tril(Rs, -1), np.zeros_like(Rs))
+    assert np.all(np.diag(Rs) > 0)
+    G = B.T @ B
+    assert np.abs(Rs.T @ Rs - G).max() < 1e-12 * np.abs(G).max()
+    assert _relerr(Rs, O.qr_r(B)) < max(1e-12, 1e-15 * np.linalg.cond(B))
+
+
 def test_triangular_solves(case):
     lp = case["lp"]
     lp.stage_assemble(case["u"], 100.0)
@@ -456,6 +472,27 @@ def test_pointwise_terms_can_change_after_finalize():
         lp.set_fn_terms([(0, 0, 1.0, 7)])
     with pytest.raises(R.RfmError):
         lp.set_fn_terms([(0, 1, 1.0, "cosh")])
+    lp.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_streamed_solve_matches_the_plain_solve(prec):
+    """A whole solve with the sketch streamed 384 rows per pass takes the same steps and reaches the same
+    field as the solve that holds B."""
+    _announce(f"streamed solve {prec}")
+    prob = W.helmholtz_cosh(nsub=(2, 1, 1), J=300, q=8, test_per_dim=3)
+    lp = R.from_description(prob)
+    p = R.RFM_PREC_F64 if prec == "f64" else R.RFM_PREC_BF16
+    o = dict(method=R.RFM_AMIPN, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5, sketch_prec=p)
+    u1, st1, rc1 = lp.solve(None, R.default_opts(**o))
+    u2, st2, rc2 = lp.solve(None, R.default_opts(sketch_rows_per_pass=384, **o))
+    print(f"plain: IT {st1['outer_iters']} NJ {st1['jac_evals']}; streamed: IT {st2['outer_iters']} "
+          f"NJ {st2['jac_evals']}; field difference {_relerr(u2, u1):.2e}")
+    assert rc1 == rc2 and rc1 in (R.RFM_OK, R.RFM_ESTALL)
+    assert (st1["outer_iters"], st1["jac_evals"]) == (st2["outer_iters"], st2["jac_evals"])
+    v1 = lp.eval(u1, prob.test_x, prob.test_owner)
+    v2 = lp.eval(u2, prob.test_x, prob.test_owner)
+    assert _relerr(v2, v1) < 1e-8
     lp.close()
 
 
