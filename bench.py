@@ -111,13 +111,20 @@ def main() -> None:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["gray-scott", "allen-cahn-hole", "helmholtz-cosh"], default="gray-scott",
+    ap.add_argument("--workload", choices=["gray-scott", "allen-cahn-hole", "helmholtz-cosh", "helmholtz-holes"],
+                    default="gray-scott",
                     help="allen-cahn-hole: space-time Allen-Cahn around a moving disc, 4 x 4 x 8 boxes, "
                          "J = 400, q = 12 (n = 51,200); helmholtz-cosh: Lap u - 100 u + 10 cosh(u) = f on the "
-                         "unit cube, 2 x 2 x 2 boxes, --features J, --points q; neither runs the warm-start "
-                         "study or the CPU baseline")
+                         "unit cube, 2 x 2 x 2 boxes, --features J, --points q; helmholtz-holes: -Lap u - 64 u "
+                         "+ u^3 = f on the unit cube minus four spheres, --boxes per axis (8: n = 128,000, "
+                         "the sketch streamed), J = 250, q = 8; none of them runs the warm-start study or the "
+                         "CPU baseline")
     ap.add_argument("--features", type=int, default=400, help="helmholtz-cosh: J per box")
     ap.add_argument("--points", type=int, default=20, help="helmholtz-cosh: q (q^3 points per box)")
+    ap.add_argument("--boxes", type=int, default=8, help="helmholtz-holes: boxes per axis")
+    ap.add_argument("--rows-per-pass", type=int, default=0,
+                    help="sketch rows per pass of the streamed QR (0: stream only when B does not fit)")
+    ap.add_argument("--verbose", action="store_true", help="progress lines from the solver on stderr")
     ap.add_argument("--method", choices=["ipn", "amipn"], default="ipn")
     ap.add_argument("--sketch-prec", choices=["bf16", "fp8", "f64"], default="bf16")
     ap.add_argument("--sketch-kind", choices=["gaussian", "count"], default="gaussian",
@@ -151,6 +158,11 @@ def main() -> None:
         a.no_cpu_baseline = True
         prob = W.config4()
         workload = "allen_cahn_space_time_moving_hole_4x4x8_J400_q12"
+    elif a.workload == "helmholtz-holes":
+        a.no_warm_start_study = True
+        a.no_cpu_baseline = True
+        prob = W.config3(nsub=(a.boxes,) * 3)
+        workload = f"helmholtz_3d_4_holes_{a.boxes}x{a.boxes}x{a.boxes}_J250_q8"
     elif a.workload == "helmholtz-cosh":
         a.no_warm_start_study = True
         a.no_cpu_baseline = True
@@ -168,8 +180,10 @@ def main() -> None:
         a.sketch_prec = "f64"
     opts = R.default_opts(method=method, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5,
                           sketch_prec=PREC[a.sketch_prec], lsqr_prec=PREC[a.lsqr_prec],
-                          sketch_kind=R.RFM_SKETCH_COUNT if a.sketch_kind == "count" else R.RFM_SKETCH_GAUSSIAN)
-    opts64 = R.default_opts(method=method, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5)
+                          sketch_kind=R.RFM_SKETCH_COUNT if a.sketch_kind == "count" else R.RFM_SKETCH_GAUSSIAN,
+                          sketch_rows_per_pass=a.rows_per_pass, verbose=int(a.verbose))
+    opts64 = R.default_opts(method=method, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5,
+                            sketch_rows_per_pass=a.rows_per_pass, verbose=int(a.verbose))
     dev = torch.device("cuda", 0)
     u = torch.zeros(n, dtype=torch.float64, device=dev)
     print(f"[bench] workload ready: m={m} n={n}; warmup {a.warmup}", file=sys.stderr, flush=True)

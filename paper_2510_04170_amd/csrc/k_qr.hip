@@ -1198,6 +1198,11 @@ double qr_factor_streamed(Problem& P, const std::function<void(int64_t, int64_t,
       hipLaunchKernelGGL(k_strip_out, dim3(g), dim3(256), 0, P.stream, P.d_R.p, (int)n, col0, Y, ldy);
     }
     RFM_HIP(hipGetLastError());
+    if (P.verbose) {
+      RFM_HIP(hipStreamSynchronize(P.stream));
+      std::fprintf(stderr, "[rfm] streamed QR: sketch rows %lld .. %lld of %lld folded into R\n", (long long)r0,
+                   (long long)(r0 + nr), (long long)s);
+    }
   }
   // positive diagonal, identity padding, singular check
   hipLaunchKernelGGL(k_r_signs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, P.stream, P.d_R.p, (int)n,

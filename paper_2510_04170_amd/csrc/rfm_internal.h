@@ -285,6 +285,7 @@ struct Problem {
   DBuf<int32_t> d_sync;   // grid-barrier / ticket / flag words
   int64_t ws_elems = 0;
   bool have_B = false, have_R = false;
+  int verbose = 0;  // progress lines on stderr from long stages (set by rfm_solve from its options)
   uint32_t trsv_epoch = 0;
   uint32_t barrier_epoch = 0;
 

@@ -39,7 +39,11 @@ struct Driver {
   // search), for the rest of the solve
   int lsqr_prec = RFM_PREC_F64;
 
-  Driver(Problem& p, const rfm_solve_opts& opts) : P(p), o(opts), lsqr_prec(opts.lsqr_prec) { ab = P.d_lsab.p; }
+  Driver(Problem& p, const rfm_solve_opts& opts) : P(p), o(opts), lsqr_prec(opts.lsqr_prec) {
+    ab = P.d_lsab.p;
+    P.verbose = opts.verbose;
+  }
+  ~Driver() { P.verbose = 0; }
 
   void sync() { RFM_HIP(hipStreamSynchronize(P.stream)); }
 
