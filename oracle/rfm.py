@@ -152,6 +152,26 @@ def group_F_J(prob: Problem, g, u: np.ndarray, with_J: bool = True):
                 Fq += coeff * f(val[c])
                 if with_J:
                     Jq[:, col_slice(prob, e, c)] += (coeff * df(val[c]))[:, None] * jets[c][0]
+            # products of field derivatives coeff prod_k (D_k u_{c_k})^{p_k} (a quasi-linear operator
+            # written out, e.g. -div((1 + u^2) grad u) = -Lap u - u^2 Lap u - 2 u |grad u|^2); by the
+            # product rule the derivative by the coefficients of c_k is
+            # coeff p_k (D_k u)^{p_k - 1} (the other factors) D_k phi, summed over the factors
+            for (eq, coeff, facs) in getattr(prob, "prod_terms", ()):
+                if eq != q:
+                    continue
+                Dk = [apply_deriv(prob, d, *jets[c]) for (c, d, p) in facs]
+                vk = [Dk[k] @ coef[c] for k, (c, d, p) in enumerate(facs)]
+                term = np.full(g.npts, coeff)
+                for k, (c, d, p) in enumerate(facs):
+                    term = term * vk[k] ** p
+                Fq += term
+                if with_J:
+                    for k, (c, d, p) in enumerate(facs):
+                        dk = coeff * p * vk[k] ** (p - 1)
+                        for k2, (c2, d2, p2) in enumerate(facs):
+                            if k2 != k:
+                                dk = dk * vk[k2] ** p2
+                        Jq[:, col_slice(prob, e, c)] += dk[:, None] * Dk[k]
             Fs.append(Fq)
             Js.append(Jq)
     elif g.kind in (KIND_DIRICHLET, KIND_NEUMANN):

@@ -81,6 +81,8 @@ class Problem:
     test_owner: np.ndarray             # [ntest] int32
     params: dict = field(default_factory=dict)
     fn_terms: List[Tuple[int, int, float, str]] = field(default_factory=list)  # (eq, comp, coeff, function)
+    # (eq, coeff, ((comp, deriv, power), ...)): coeff times the product of derivatives of the field
+    prod_terms: List[Tuple[int, float, Tuple[Tuple[int, int, int], ...]]] = field(default_factory=list)
 
     @property
     def nbox(self) -> int:
@@ -235,23 +237,26 @@ def jet_config4(x: np.ndarray) -> Jet:
     return val[:, None], np.stack([gx, gy, gt], 1)[:, None, :], lap[:, None], lap_space[:, None]
 
 
-def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int, fn_terms=()) -> np.ndarray:
-    """Right-hand side f = P(u*) at the points, one column per equation."""
+def _jet_quantity(jet: Jet, c: int, deriv: int) -> np.ndarray:
     val, grad, lap, lap_space = jet
+    if deriv == D_ID:
+        return val[:, c]
+    if D_X0 <= deriv <= D_X3:
+        return grad[:, c, deriv - 1]
+    if deriv == D_LAPLACE:
+        return lap[:, c]
+    if deriv == D_LAPLACE_SPACE:
+        return lap_space[:, c]
+    raise ValueError(deriv)
+
+
+def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int, fn_terms=(), prod_terms=()) -> np.ndarray:
+    """Right-hand side f = P(u*) at the points, one column per equation."""
+    val = jet[0]
     n = val.shape[0]
     f = np.zeros((n, neq))
     for (q, c, coeff, deriv) in lin_terms:
-        if deriv == D_ID:
-            term = val[:, c]
-        elif D_X0 <= deriv <= D_X3:
-            term = grad[:, c, deriv - 1]
-        elif deriv == D_LAPLACE:
-            term = lap[:, c]
-        elif deriv == D_LAPLACE_SPACE:
-            term = lap_space[:, c]
-        else:
-            raise ValueError(deriv)
-        f[:, q] += coeff * term
+        f[:, q] += coeff * _jet_quantity(jet, c, deriv)
     for (q, coeff, pw) in poly_terms:
         term = np.ones(n)
         for c, p in enumerate(pw):
@@ -260,6 +265,11 @@ def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int, fn_terms=()
         f[:, q] += coeff * term
     for (q, c, coeff, fn) in fn_terms:
         f[:, q] += coeff * _FN_VALUE[fn](val[:, c])
+    for (q, coeff, facs) in prod_terms:
+        term = np.full(n, coeff)
+        for (c, deriv, p) in facs:
+            term = term * _jet_quantity(jet, c, deriv) ** p
+        f[:, q] += term
     return f
 
 
@@ -269,7 +279,7 @@ def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int, fn_terms=()
 
 def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_terms, poly_terms,
            seed=0, dirichlet_faces=None, test_per_dim=None, inside=None, extra_groups=None,
-           params=None, fn_terms=()):
+           params=None, fn_terms=(), prod_terms=()):
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
     nsub = np.asarray(nsub, np.int64)
@@ -286,7 +296,7 @@ def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_term
         pts = pts[keep(pts)]
         if pts.shape[0] == 0:
             continue
-        f = apply_operator_to_jet(jet_fn(pts), lin_terms, poly_terms, ncomp, fn_terms)
+        f = apply_operator_to_jet(jet_fn(pts), lin_terms, poly_terms, ncomp, fn_terms, prod_terms)
         groups.append(PointGroup(KIND_PDE, pts, e, data=f))
 
     # continuity groups: direction, plane, transverse box (axis 0 fastest)
@@ -340,7 +350,7 @@ def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_term
                    groups=groups, lin_terms=list(lin_terms), poly_terms=list(poly_terms),
                    exact=exact, test_x=np.concatenate(tx), test_owner=np.concatenate(to),
                    params=dict(params or {}, seed=seed, R=R, q_int=q_int, q_face=q_face),
-                   fn_terms=list(fn_terms))
+                   fn_terms=list(fn_terms), prod_terms=list(prod_terms))
 
 
 # ----------------------------------------------------------------------------
@@ -572,9 +582,42 @@ def helmholtz_cosh(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, test_per_dim=None
                   jet_helmholtz_cosh, lin, [], seed=seed, test_per_dim=test_per_dim, fn_terms=fn)
 
 
+def jet_quasilinear(x: np.ndarray) -> Jet:
+    """u* = (x + y + z) sin(pi x) sin(pi y) cos(pi z), its gradient and Laplacian."""
+    pi = math.pi
+    sx, sy, sz = (np.sin(pi * x[:, a]) for a in range(3))
+    cx, cy, cz = (np.cos(pi * x[:, a]) for a in range(3))
+    P = sx * sy * cz
+    dP = np.stack([pi * cx * sy * cz, pi * sx * cy * cz, -pi * sx * sy * sz], 1)
+    s = x[:, :3].sum(1)
+    val = s * P
+    grad = P[:, None] + s[:, None] * dP
+    lap = -3.0 * pi * pi * s * P + 2.0 * dP.sum(1)
+    return val[:, None], grad[:, None, :], lap[:, None], lap[:, None]
+
+
+def quasilinear_terms():
+    """-div((1 + u^2) grad u) = -Lap u - u^2 Lap u - 2 u |grad u|^2: one linear and four product terms."""
+    lin = [(0, 0, -1.0, D_LAPLACE)]
+    prod = [(0, -1.0, ((0, D_ID, 2), (0, D_LAPLACE, 1)))]
+    prod += [(0, -2.0, ((0, D_ID, 1), (0, D_X0 + a, 2))) for a in range(3)]
+    return lin, prod
+
+
+def quasilinear(nsub=(2, 2, 2), J=800, q=20, seed=0, R=1.0, test_per_dim=None) -> Problem:
+    """3-D quasi-linear elliptic benchmark of the paper (Sec. 3.4 and the AMIPN table of Sec. 5):
+    -div((1 + u^2) grad u) = f on the unit cube, u* = (x + y + z) sin(pi x) sin(pi y) cos(pi z),
+    Dirichlet u* on the boundary; q^3 collocation points per box, q x q face and interface grids."""
+    lin, prod = quasilinear_terms()
+    return _build("quasilinear_3d", 3, 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), nsub, J, R, q, q,
+                  jet_quasilinear, lin, [], seed=seed, test_per_dim=test_per_dim, prod_terms=prod)
+
+
 def jet_of(problem: Problem):
     """Closed-form jet of the problem's manufactured solution."""
     name = problem.name
+    if name == "quasilinear_3d":
+        return jet_quasilinear
     if name == "helmholtz_cosh_3d":
         return jet_helmholtz_cosh
     if name == "poisson_cubic_2d":

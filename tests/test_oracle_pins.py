@@ -573,3 +573,76 @@ def test_cosh_problem_by_manufactured_solution():
     u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
     assert st.status == "ok"
     assert np.all(O.rel_l2(prob, u) < 2e-3)
+
+
+def _flux_divergence(u, x, h=1e-3):
+    """-div((1 + u^2) grad u) by central differences of the flux at half steps (a form that does not
+    expand the operator into the product terms)."""
+    out = np.zeros(x.shape[0])
+    u0 = u(x)[:, 0]
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        up, um = u(x + e)[:, 0], u(x - e)[:, 0]
+        uhp, uhm = u(x + e / 2)[:, 0], u(x - e / 2)[:, 0]
+        out -= ((1 + uhp ** 2) * (up - u0) - (1 + uhm ** 2) * (u0 - um)) / (h * h)
+    return out
+
+
+def test_quasilinear_data_matches_the_flux_form():
+    """The data of the quasi-linear benchmark (Sec. 3.4): f = -div((1 + u*^2) grad u*), written out as
+    product terms, against central differences of the flux itself; also the jet of u* against central
+    differences of u*."""
+    prob = W.quasilinear(nsub=(2, 2, 2), J=4, q=5)
+    g = prob.groups[1]
+    assert g.kind == W.KIND_PDE
+    f = _flux_divergence(prob.exact, g.x)
+    assert np.abs(f - g.data[:, 0]).max() < 1e-4 * max(1.0, np.abs(g.data).max())
+    val, grad, sec = _fd_jet(prob.exact, g.x)
+    jv, jg, jl, _ = W.jet_quasilinear(g.x)
+    assert np.abs(jv - val).max() < 1e-12
+    assert np.abs(jg - grad).max() < 1e-6
+    assert np.abs(jl[:, 0] - sec[:, 0].sum(-1)).max() < 1e-4
+
+
+def test_product_term_jacobian_matches_central_differences():
+    """Product terms of field derivatives (u^2 Lap u, u (d_x u)^2, u_x u_y^3 Lap u): the oracle's Jacobian
+    rows against central differences of its residual, and each term entering F with its coefficient."""
+    prob = W.quasilinear(nsub=(2, 1, 2), J=4, q=3)
+    prob.prod_terms = [(0, -1.0, ((0, W.D_ID, 2), (0, W.D_LAPLACE, 1))),
+                       (0, -2.0, ((0, W.D_ID, 1), (0, W.D_X0, 2))),
+                       (0, 0.5, ((0, W.D_X0, 1), (0, W.D_X1, 3), (0, W.D_LAPLACE, 1)))]
+    u = 0.3 * np.random.default_rng(4).normal(size=prob.n)
+    F, J = O.assemble(prob, u)
+    Jfd = np.zeros_like(J)
+    for j in range(prob.n):
+        h = 1e-6
+        up, um = u.copy(), u.copy()
+        up[j] += h
+        um[j] -= h
+        Jfd[:, j] = (O.residual(prob, up) - O.residual(prob, um)) / (2 * h)
+    assert np.abs(J - Jfd).max() / np.abs(J).max() < 1e-7
+    # the last term alone: 0.5 u_x u_y^3 Lap u from the feature jets directly
+    prob0 = W.quasilinear(nsub=(2, 1, 2), J=4, q=3)
+    prob0.prod_terms = prob.prod_terms[:2]
+    F0 = O.residual(prob0, u)
+    parts = []
+    for g in prob.groups:
+        if g.kind != W.KIND_PDE:
+            continue
+        phi, dphi, d2phi = O.feature_jet(prob, g.owner, 0, g.x)
+        cu = u[O.col_slice(prob, g.owner, 0)]
+        parts.append(0.5 * (dphi[..., 0] @ cu) * (dphi[..., 1] @ cu) ** 3 * (d2phi.sum(-1) @ cu))
+    ref = np.concatenate(parts)
+    npde = ref.size
+    assert np.allclose(F[:npde] - F0[:npde], ref, rtol=1e-11, atol=1e-12)
+    assert np.array_equal(F[npde:], F0[npde:])
+
+
+def test_quasilinear_problem_by_manufactured_solution():
+    """The exact-Newton iteration reaches u* of the quasi-linear benchmark to the discretisation's
+    accuracy."""
+    prob = W.quasilinear(nsub=(1, 1, 1), J=500, q=12, test_per_dim=4)
+    u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
+    assert st.status == "ok"
+    assert np.all(O.rel_l2(prob, u) < 5e-4)
