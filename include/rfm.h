@@ -75,6 +75,15 @@ typedef struct { int32_t eq; double coeff; int32_t pow[4]; } rfm_poly_term;
 typedef struct { int32_t eq, comp; double coeff; int32_t fn; } rfm_fn_term;
 enum { RFM_FN_COSH = 0, RFM_FN_SINH = 1, RFM_FN_EXP = 2 };
 
+/* Product term coeff * prod_k (D_k u_{comp_k})^{pow_k} of equation eq, with D_k
+ * a derivative selector RFM_D_* of the field: the quasi-linear operators of the
+ * paper's benchmarks written out, e.g. -div((1 + u^2) grad u) = -Lap u
+ * - u^2 Lap u - 2 u |grad u|^2 (Sec. 3.4, Sec. 5).  Its Jacobian contribution
+ * is, by the product rule, sum_k coeff pow_k (D_k u)^{pow_k - 1} (the other
+ * factors) D_k phi. */
+typedef struct { int32_t comp, deriv, pow; } rfm_factor;
+typedef struct { int32_t eq; double coeff; int32_t nfac; rfm_factor fac[4]; } rfm_prod_term;
+
 /* Create an empty problem on HIP device `device`.  dim: 1..4 coordinates
  * (time, if any, is the last one, Sec. 2.1); ncomp: 1..4 solution components,
  * with one equation per component.  hip_stream: a hipStream_t, or NULL for the
@@ -118,7 +127,8 @@ rfm_status rfm_add_points(rfm_problem* p, int32_t kind, int64_t npts, const doub
                           const double* data);
 
 /* Operator P(u) = sum of linear terms + sum of polynomial terms (Sec. 2.1)
- * (+ the pointwise terms of rfm_set_fn_terms, which this call leaves in place).
+ * (+ the pointwise terms of rfm_set_fn_terms and the product terms of
+ * rfm_set_prod_terms, which this call leaves in place).
  * At most 16 linear and 8 polynomial terms. */
 rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nlin,
                             const rfm_poly_term* nl, int32_t nnl);
@@ -128,6 +138,13 @@ rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nli
  * [0, ncomp), fn one of RFM_FN_*, finite coeff, else RFM_EINVAL / RFM_ENUMERIC.
  * Like rfm_set_operator it may be called again after rfm_finalize. */
 rfm_status rfm_set_fn_terms(rfm_problem* p, const rfm_fn_term* terms, int32_t n);
+
+/* Product terms (rfm_prod_term) added to the operator: replaces any earlier ones;
+ * at most 8 terms (n = 0 removes them) of 1..4 factors each, with powers 1..8, eq
+ * and comp in [0, ncomp), deriv a selector valid for the problem's dimension,
+ * finite coeff, and at most 8 distinct (comp, deriv) pairs over all terms; else
+ * RFM_EINVAL / RFM_ENUMERIC.  May be called again after rfm_finalize. */
+rfm_status rfm_set_prod_terms(rfm_problem* p, const rfm_prod_term* terms, int32_t n);
 
 /* Replaces the data of point group `group` (numbered in rfm_add_points order;
  * not a continuity group): data [npts][ncomp] for comp = -1, else [npts].

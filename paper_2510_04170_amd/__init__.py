@@ -40,6 +40,14 @@ class rfm_fn_term(C.Structure):
     _fields_ = [("eq", C.c_int32), ("comp", C.c_int32), ("coeff", C.c_double), ("fn", C.c_int32)]
 
 
+class rfm_factor(C.Structure):
+    _fields_ = [("comp", C.c_int32), ("deriv", C.c_int32), ("pow", C.c_int32)]
+
+
+class rfm_prod_term(C.Structure):
+    _fields_ = [("eq", C.c_int32), ("coeff", C.c_double), ("nfac", C.c_int32), ("fac", rfm_factor * 4)]
+
+
 class rfm_solve_opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("sketch_factor", C.c_double), ("sketch_seed", C.c_uint64),
                 ("lsqr_tol", C.c_double), ("lsqr_max_iter", C.c_int32), ("outer_tol", C.c_double),
@@ -96,6 +104,7 @@ _SIGS = {
     "rfm_add_points": (C.c_int, [_P, C.c_int32, C.c_int64, _D, C.c_int32, C.c_int32, _D, C.c_int32, C.c_int32, _D]),
     "rfm_set_operator": (C.c_int, [_P, C.POINTER(rfm_lin_term), C.c_int32, C.POINTER(rfm_poly_term), C.c_int32]),
     "rfm_set_fn_terms": (C.c_int, [_P, C.POINTER(rfm_fn_term), C.c_int32]),
+    "rfm_set_prod_terms": (C.c_int, [_P, C.POINTER(rfm_prod_term), C.c_int32]),
     "rfm_finalize": (C.c_int, [_P]),
     "rfm_set_group_data": (C.c_int, [_P, C.c_int32, _D]),
     "rfm_num_unknowns": (C.c_int64, [_P]),
@@ -329,6 +338,16 @@ class RfmProblem:
             T[i] = rfm_fn_term(eq, comp, coeff, _FN_CODE[fn] if isinstance(fn, str) else int(fn))
         _check(lib().rfm_set_fn_terms(self.h, T, len(fn_terms)))
 
+    def set_prod_terms(self, prod_terms):
+        """Product terms (eq, coeff, ((comp, deriv, power), ...)) with 1..4 factors each."""
+        T = (rfm_prod_term * max(1, len(prod_terms)))()
+        for i, (eq, coeff, facs) in enumerate(prod_terms):
+            if not 1 <= len(facs) <= 4:
+                raise ValueError("a product term has 1..4 factors")
+            fac = (rfm_factor * 4)(*[rfm_factor(int(c), int(d), int(p)) for (c, d, p) in facs])
+            T[i] = rfm_prod_term(eq, coeff, len(facs), fac)
+        _check(lib().rfm_set_prod_terms(self.h, T, len(prod_terms)))
+
     def finalize(self):
         _check(lib().rfm_finalize(self.h))
 
@@ -341,6 +360,7 @@ class RfmProblem:
         partition, features and points (a member of the same parameter family)."""
         self.set_operator(desc.lin_terms, desc.poly_terms)
         self.set_fn_terms(getattr(desc, "fn_terms", []))
+        self.set_prod_terms(getattr(desc, "prod_terms", []))
         for i, g in enumerate(desc.groups):
             if g.data is not None and len(g.x):
                 self.set_group_data(i, g.data)
@@ -526,5 +546,7 @@ def from_description(desc, device: int = 0, stream: Optional[int] = None) -> Rfm
     p.set_operator(desc.lin_terms, desc.poly_terms)
     if getattr(desc, "fn_terms", None):
         p.set_fn_terms(desc.fn_terms)
+    if getattr(desc, "prod_terms", None):
+        p.set_prod_terms(desc.prod_terms)
     p.finalize()
     return p

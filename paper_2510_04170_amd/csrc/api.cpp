@@ -131,6 +131,23 @@ static void box_centre_halfwidth(const GeomDesc& g, int e, double* mu, double* s
   }
 }
 
+const OpDesc* device_op(Problem& P) {
+  if (!P.have_d_op || std::memcmp(&P.op, &P.op_on_device, sizeof(OpDesc)) != 0) {
+    P.d_op.resize(1);
+    RFM_HIP(hipStreamSynchronize(P.stream));  // no kernel still reads the old copy
+    RFM_HIP(hipMemcpy(P.d_op.p, &P.op, sizeof(OpDesc), hipMemcpyHostToDevice));
+    std::memcpy(&P.op_on_device, &P.op, sizeof(OpDesc));  // bytes, padding included, for the memcmp
+    P.have_d_op = true;
+  }
+  return P.d_op.p;
+}
+
+// a derivative selector RFM_D_* valid for the problem's dimension
+static bool deriv_ok(const Problem& P, int d) {
+  return d == RFM_D_ID || (d >= RFM_D_X0 && d < RFM_D_X0 + P.dim) || d == RFM_D_LAPLACE ||
+         (d == RFM_D_LAPLACE_SPACE && P.dim >= 2);
+}
+
 static int row_width_of_group(const Problem& P, const GroupH& g) {
   if (g.kind == RFM_PDE) return P.ncomp * P.J;
   if (g.kind == RFM_CONTINUITY) return 2 * P.J;
@@ -372,7 +389,7 @@ static void finalize(Problem& P) {
   P.d_vec.resize(6 * std::max(P.m, P.n));
   P.d_red.resize(65536);
   P.d_scal.resize(64);
-  P.d_lsab.resize((size_t)P.m * (2 + 2 * K));
+  P.d_lsab.resize((size_t)P.m * (2 + 2 * K + 2 * kMaxQ));
   P.d_lsqr.resize(1);
   P.d_sync.resize(1 << 16);
   RFM_HIP(hipMemset(P.d_sync.p, 0, P.d_sync.n * sizeof(int32_t)));
@@ -547,9 +564,7 @@ rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nli
       const auto& t = lin[i];
       RFM_CHECK(t.eq >= 0 && t.eq < P.ncomp && t.comp >= 0 && t.comp < P.ncomp, RFM_EINVAL,
                 "rfm_set_operator: term index out of range");
-      bool ok = t.deriv == RFM_D_ID || (t.deriv >= RFM_D_X0 && t.deriv < RFM_D_X0 + P.dim) ||
-                t.deriv == RFM_D_LAPLACE || (t.deriv == RFM_D_LAPLACE_SPACE && P.dim >= 2);
-      RFM_CHECK(ok, RFM_EINVAL, "rfm_set_operator: bad derivative selector");
+      RFM_CHECK(deriv_ok(P, t.deriv), RFM_EINVAL, "rfm_set_operator: bad derivative selector");
       RFM_CHECK(std::isfinite(t.coeff), RFM_ENUMERIC, "rfm_set_operator: non-finite coefficient");
       op.lin_eq[i] = t.eq;
       op.lin_comp[i] = t.comp;
@@ -592,6 +607,47 @@ rfm_status rfm_set_fn_terms(rfm_problem* p, const rfm_fn_term* terms, int32_t n)
       op.fn_comp[i] = t.comp;
       op.fn_kind[i] = t.fn;
       op.fn_coeff[i] = t.coeff;
+    }
+    P.op = op;
+  });
+}
+
+rfm_status rfm_set_prod_terms(rfm_problem* p, const rfm_prod_term* terms, int32_t n) {
+  return guarded([&] {
+    Problem& P = get(p);
+    RFM_CHECK(n >= 0 && n <= kMaxProd, RFM_EINVAL, "rfm_set_prod_terms: at most 8 terms");
+    RFM_CHECK(n == 0 || terms, RFM_EINVAL, "rfm_set_prod_terms: NULL terms");
+    OpDesc op = P.op;
+    op.nprod = n;
+    op.nq = 0;
+    for (int i = 0; i < n; ++i) {
+      const auto& t = terms[i];
+      RFM_CHECK(t.eq >= 0 && t.eq < P.ncomp, RFM_EINVAL, "rfm_set_prod_terms: equation out of range");
+      RFM_CHECK(t.nfac >= 1 && t.nfac <= kMaxFac, RFM_EINVAL, "rfm_set_prod_terms: 1..4 factors per term");
+      RFM_CHECK(std::isfinite(t.coeff), RFM_ENUMERIC, "rfm_set_prod_terms: non-finite coefficient");
+      op.prod_eq[i] = t.eq;
+      op.prod_nfac[i] = t.nfac;
+      op.prod_coeff[i] = t.coeff;
+      for (int k = 0; k < kMaxFac; ++k) {
+        op.prod_q[i][k] = 0;
+        op.prod_pow[i][k] = 0;
+      }
+      for (int k = 0; k < t.nfac; ++k) {
+        const rfm_factor& f = t.fac[k];
+        RFM_CHECK(f.comp >= 0 && f.comp < P.ncomp, RFM_EINVAL, "rfm_set_prod_terms: component out of range");
+        RFM_CHECK(deriv_ok(P, f.deriv), RFM_EINVAL, "rfm_set_prod_terms: bad derivative selector");
+        RFM_CHECK(f.pow >= 1 && f.pow <= 8, RFM_EINVAL, "rfm_set_prod_terms: powers 1..8");
+        int q = 0;
+        while (q < op.nq && !(op.q_comp[q] == f.comp && op.q_deriv[q] == f.deriv)) ++q;
+        if (q == op.nq) {
+          RFM_CHECK(op.nq < kMaxQ, RFM_EINVAL, "rfm_set_prod_terms: more than 8 distinct field derivatives");
+          op.q_comp[q] = f.comp;
+          op.q_deriv[q] = f.deriv;
+          ++op.nq;
+        }
+        op.prod_q[i][k] = q;
+        op.prod_pow[i][k] = f.pow;
+      }
     }
     P.op = op;
   });

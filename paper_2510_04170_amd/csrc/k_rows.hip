@@ -35,7 +35,7 @@ __device__ __forceinline__ double ipow(double x, int p) {
 
 struct RowsCtx {
   GeomDesc g;
-  OpDesc op;
+  const OpDesc* op;  // device copy: run-time indexing into an argument makes a private copy of it
   FeatDev f;
   const RowDesc* rows;
   const double* px;
@@ -76,7 +76,14 @@ __device__ __forceinline__ double feat_t(const RowsCtx& C, int64_t f, const doub
 __device__ __forceinline__ double feat_deriv(const RowsCtx& C, int deriv, int64_t f, double t) {
   double dt = 1.0 - t * t;
   if (deriv == RFM_D_ID) return t;
-  if (deriv >= RFM_D_X0 && deriv <= RFM_D_X3) return dt * C.f.WS[deriv - RFM_D_X0][f];
+  if (deriv >= RFM_D_X0 && deriv <= RFM_D_X3) {
+    // the weight table by an unrolled select (no run-time index into the argument)
+    const double* ws = C.f.WS[0];
+#pragma unroll
+    for (int a = 1; a < kMaxDim; ++a)
+      if (deriv - RFM_D_X0 == a) ws = C.f.WS[a];
+    return dt * ws[f];
+  }
   if (deriv == RFM_D_LAPLACE) return -2.0 * t * dt * C.f.S2[f];
   return -2.0 * t * dt * C.f.S2s[f];  // RFM_D_LAPLACE_SPACE
 }
@@ -98,35 +105,97 @@ __device__ __forceinline__ void nonlinear_terms(const RowsCtx& C, int q, const d
   Fp = 0.0;
 #pragma unroll
   for (int c = 0; c < kMaxComp; ++c) dp[c] = 0.0;
-  for (int i = 0; i < C.op.npoly; ++i) {
-    if (C.op.poly_eq[i] != q) continue;
-    double prod = C.op.poly_coeff[i];
-    for (int c = 0; c < K; ++c) prod *= ipow(val[c], C.op.poly_pow[i][c]);
+  for (int i = 0; i < C.op->npoly; ++i) {
+    if (C.op->poly_eq[i] != q) continue;
+    double prod = C.op->poly_coeff[i];
+    for (int c = 0; c < K; ++c) prod *= ipow(val[c], C.op->poly_pow[i][c]);
     Fp += prod;
     for (int c = 0; c < K; ++c) {
-      const int pc = C.op.poly_pow[i][c];
+      const int pc = C.op->poly_pow[i][c];
       if (pc == 0) continue;
-      double d = C.op.poly_coeff[i] * pc * ipow(val[c], pc - 1);
+      double d = C.op->poly_coeff[i] * pc * ipow(val[c], pc - 1);
       for (int c2 = 0; c2 < K; ++c2)
-        if (c2 != c) d *= ipow(val[c2], C.op.poly_pow[i][c2]);
+        if (c2 != c) d *= ipow(val[c2], C.op->poly_pow[i][c2]);
       dp[c] += d;
     }
   }
-  for (int i = 0; i < C.op.nfn; ++i) {
-    if (C.op.fn_eq[i] != q) continue;
-    const int c = C.op.fn_comp[i];
+  for (int i = 0; i < C.op->nfn; ++i) {
+    if (C.op->fn_eq[i] != q) continue;
+    const int c = C.op->fn_comp[i];
     double f, df;
-    fn_eval(C.op.fn_kind[i], val[c], &f, &df);
-    Fp += C.op.fn_coeff[i] * f;
-    dp[c] += C.op.fn_coeff[i] * df;
+    fn_eval(C.op->fn_kind[i], val[c], &f, &df);
+    Fp += C.op->fn_coeff[i] * f;
+    dp[c] += C.op->fn_coeff[i] * df;
   }
+}
+
+// v[q] for a run-time q < kMaxQ without dynamic register indexing
+__device__ __forceinline__ double qsel(const double* v, int q) {
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < kMaxQ; ++k)
+    if (k == q) r = v[k];
+  return r;
+}
+
+// Product terms coeff prod_k v_{q_k}^{p_k} of equation qrow at the field quantities vq[]: their sum
+// added to Fp, and by the product rule d/dv_q of the sum added to dq[q].
+__device__ __forceinline__ void prod_terms(const RowsCtx& C, int qrow, const double* vq, double& Fp, double* dq) {
+  for (int i = 0; i < C.op->nprod; ++i) {
+    if (C.op->prod_eq[i] != qrow) continue;
+    const int nf = C.op->prod_nfac[i];
+    const double coeff = C.op->prod_coeff[i];
+    double fv[kMaxFac], fd[kMaxFac];
+    double term = coeff;
+#pragma unroll
+    for (int k = 0; k < kMaxFac; ++k) {
+      fv[k] = 1.0;
+      fd[k] = 0.0;
+      if (k < nf) {
+        const double v = qsel(vq, C.op->prod_q[i][k]);
+        const int pw = C.op->prod_pow[i][k];
+        fv[k] = ipow(v, pw);
+        fd[k] = pw * ipow(v, pw - 1);
+        term *= fv[k];
+      }
+    }
+    Fp += term;
+#pragma unroll
+    for (int k = 0; k < kMaxFac; ++k) {
+      if (k >= nf) continue;
+      double d = coeff * fd[k];
+#pragma unroll
+      for (int k2 = 0; k2 < kMaxFac; ++k2)
+        if (k2 != k) d *= fv[k2];
+      const int qk = C.op->prod_q[i][k];
+#pragma unroll
+      for (int qq = 0; qq < kMaxQ; ++qq)
+        if (qq == qk) dq[qq] += d;
+    }
+  }
+}
+
+// sum over the field quantities q of component c of w[q] D_q phi_f (t = tanh of feature f)
+__device__ __forceinline__ double quantity_comb(const RowsCtx& C, int c, int64_t f, double t, const double* w) {
+  double r = 0.0;
+#pragma unroll
+  for (int qq = 0; qq < kMaxQ; ++qq)
+    if (qq < C.op->nq && C.op->q_comp[qq] == c) r += w[qq] * feat_deriv(C, C.op->q_deriv[qq], f, t);
+  return r;
+}
+
+// acc[q] += D_q phi_f * x for the field quantities q of component c
+__device__ __forceinline__ void quantity_acc(const RowsCtx& C, int c, int64_t f, double t, double x, double* acc) {
+#pragma unroll
+  for (int qq = 0; qq < kMaxQ; ++qq)
+    if (qq < C.op->nq && C.op->q_comp[qq] == c) acc[qq] += feat_deriv(C, C.op->q_deriv[qq], f, t) * x;
 }
 
 // Values of row r (positions c*J + j for PDE rows, j and J + j for continuity
 // rows) in vals[], lane-strided; the unscaled residual (data included) in F.
 // vals index: seg * KPER + k for feature j = lane + 64 k of segment/component seg.
 template <int KPER>
-__device__ void row_values(const RowsCtx& C, int64_t r, const double* __restrict__ u, int lane,
+__device__ __forceinline__ void row_values(const RowsCtx& C, int64_t r, const double* __restrict__ u, int lane,
                            double (&vals)[4 * KPER], double& F) {
   const RowDesc rd = C.rows[r];
   const int K = C.g.ncomp, J = C.g.J, dim = C.g.dim;
@@ -143,7 +212,9 @@ __device__ void row_values(const RowsCtx& C, int64_t r, const double* __restrict
     norm_coords(C.g, rd.owner, x, l);
     double tv[4 * KPER];
     double accv[kMaxComp] = {0, 0, 0, 0};
+    double accq[kMaxQ] = {0, 0, 0, 0, 0, 0, 0, 0};
     double accL = 0.0;
+    const bool has_q = C.op->nq > 0;
 #pragma unroll
     for (int c = 0; c < kMaxComp; ++c) {
       if (c >= K) break;
@@ -156,11 +227,12 @@ __device__ void row_values(const RowsCtx& C, int64_t r, const double* __restrict
           const int64_t f = fb + j;
           const double t = feat_t(C, f, l);
           double Lv = 0.0;
-          for (int i = 0; i < C.op.nlin; ++i)
-            if (C.op.lin_eq[i] == q && C.op.lin_comp[i] == c) Lv += C.op.lin_coeff[i] * feat_deriv(C, C.op.lin_deriv[i], f, t);
+          for (int i = 0; i < C.op->nlin; ++i)
+            if (C.op->lin_eq[i] == q && C.op->lin_comp[i] == c) Lv += C.op->lin_coeff[i] * feat_deriv(C, C.op->lin_deriv[i], f, t);
           const double uj = u[f];
           accv[c] += t * uj;
           accL += Lv * uj;
+          if (has_q) quantity_acc(C, c, f, t, uj, accq);
           vals[c * KPER + k] = Lv;
           tv[c * KPER + k] = t;
         }
@@ -177,6 +249,25 @@ __device__ void row_values(const RowsCtx& C, int64_t r, const double* __restrict
       if (c >= K) break;
 #pragma unroll
       for (int k = 0; k < KPER; ++k) vals[c * KPER + k] += dp[c] * tv[c * KPER + k];
+    }
+    if (has_q) {
+      double vq[kMaxQ], dq[kMaxQ];
+#pragma unroll
+      for (int qq = 0; qq < kMaxQ; ++qq) {
+        vq[qq] = qq < C.op->nq ? wave_sum(accq[qq]) : 0.0;
+        dq[qq] = 0.0;
+      }
+      prod_terms(C, q, vq, Fp, dq);
+#pragma unroll
+      for (int c = 0; c < kMaxComp; ++c) {
+        if (c >= K) break;
+        const int64_t fb = ((int64_t)rd.owner * K + c) * J;
+#pragma unroll
+        for (int k = 0; k < KPER; ++k) {
+          const int j = lane + kWave * k;
+          if (j < J) vals[c * KPER + k] += quantity_comb(C, c, fb + j, tv[c * KPER + k], dq);
+        }
+      }
     }
     F = accL + Fp - C.rowdata[r];
   } else if (rd.kind == RFM_CONTINUITY) {
@@ -275,9 +366,9 @@ __device__ __forceinline__ double wide_entry(const RowsCtx& C, const RowDesc& rd
   t = feat_t(C, f, l);
   if (rd.kind == RFM_PDE) {
     double Lv = 0.0;
-    for (int i = 0; i < C.op.nlin; ++i)
-      if (C.op.lin_eq[i] == rd.sel && C.op.lin_comp[i] == seg)
-        Lv += C.op.lin_coeff[i] * feat_deriv(C, C.op.lin_deriv[i], f, t);
+    for (int i = 0; i < C.op->nlin; ++i)
+      if (C.op->lin_eq[i] == rd.sel && C.op->lin_comp[i] == seg)
+        Lv += C.op->lin_coeff[i] * feat_deriv(C, C.op->lin_deriv[i], f, t);
     return Lv;
   }
   double v;
@@ -316,7 +407,9 @@ __global__ void __launch_bounds__(256) k_assemble_wide(RowsCtx C, const TileDesc
   };
   // sweep 1: sums
   double accv[kMaxComp] = {0, 0, 0, 0};
+  double accq[kMaxQ] = {0, 0, 0, 0, 0, 0, 0, 0};
   double accL = 0.0;
+  const bool has_q = rd.kind == RFM_PDE && C.op->nq > 0;
   for (int seg = 0; seg < nseg; ++seg) {
     const int64_t fb = fbase(seg);
     const double* ls = l[cont ? seg : 0];
@@ -327,6 +420,7 @@ __global__ void __launch_bounds__(256) k_assemble_wide(RowsCtx C, const TileDesc
       const double uj = u[fb + j];
       accL += v * uj;
       av += t * uj;
+      if (has_q) quantity_acc(C, seg, fb + j, t, uj, accq);
     }
 #pragma unroll
     for (int c = 0; c < kMaxComp; ++c)
@@ -334,6 +428,7 @@ __global__ void __launch_bounds__(256) k_assemble_wide(RowsCtx C, const TileDesc
   }
   accL = wave_sum(accL);
   double dp[kMaxComp] = {0, 0, 0, 0};
+  double dq[kMaxQ] = {0, 0, 0, 0, 0, 0, 0, 0};
   double F;
   if (rd.kind == RFM_PDE) {
     double val[kMaxComp];
@@ -341,6 +436,12 @@ __global__ void __launch_bounds__(256) k_assemble_wide(RowsCtx C, const TileDesc
     for (int c = 0; c < kMaxComp; ++c) val[c] = c < K ? wave_sum(accv[c]) : 0.0;
     double Fp;
     nonlinear_terms(C, rd.sel, val, Fp, dp);
+    if (has_q) {
+      double vq[kMaxQ];
+#pragma unroll
+      for (int qq = 0; qq < kMaxQ; ++qq) vq[qq] = qq < C.op->nq ? wave_sum(accq[qq]) : 0.0;
+      prod_terms(C, rd.sel, vq, Fp, dq);
+    }
     F = accL + Fp - C.rowdata[r];
   } else {
     F = accL - (cont ? 0.0 : C.rowdata[r]);
@@ -357,7 +458,8 @@ __global__ void __launch_bounds__(256) k_assemble_wide(RowsCtx C, const TileDesc
     for (int j = lane; j < J; j += kWave) {
       double t;
       const double v = wide_entry(C, rd, ls, nrm, fb + j, seg, t);
-      mx = fmax(mx, fabs(v + dps * t));
+      const double w = has_q ? quantity_comb(C, seg, fb + j, t, dq) : 0.0;
+      mx = fmax(mx, fabs(v + dps * t + w));
     }
   }
   mx = wave_max(mx);
@@ -376,8 +478,9 @@ __global__ void __launch_bounds__(256) k_assemble_wide(RowsCtx C, const TileDesc
     for (int j = lane; j < J; j += kWave) {
       double t;
       const double v = wide_entry(C, rd, ls, nrm, fb + j, seg, t);
+      const double wq = has_q ? quantity_comb(C, seg, fb + j, t, dq) : 0.0;
       const int pos = seg * J + j;
-      if (pos < w) row[pos] = D * (v + dps * t);
+      if (pos < w) row[pos] = D * (v + dps * t + wq);
     }
   }
   if (lane == 0) {
@@ -387,9 +490,10 @@ __global__ void __launch_bounds__(256) k_assemble_wide(RowsCtx C, const TileDesc
 }
 
 // Linear part and field values along u and du for the line search:
-//   ab[r] = {a_r, b_r, vu_0..vu_{K-1}, vd_0..vd_{K-1}}
+//   ab[r] = {a_r, b_r, vu_0..vu_{K-1}, vd_0..vd_{K-1}, qu_0..qu_{nq-1}, qd_0..qd_{nq-1}}
 //   F_r(alpha) = a_r + alpha b_r + sum_poly coeff prod_c (vu_c + alpha vd_c)^p_c
-//                + sum_fn coeff f(vu_c + alpha vd_c)
+//                + sum_fn coeff f(vu_c + alpha vd_c) + sum_prod coeff prod_k (qu_k + alpha qd_k)^p_k
+// (qu, qd: the product terms' field quantities along u and du)
 template <int KPER>
 __global__ void __launch_bounds__(256) k_row_eval(RowsCtx C, int64_t m, const double* __restrict__ u,
                                                   const double* __restrict__ du, double* __restrict__ ab) {
@@ -398,7 +502,8 @@ __global__ void __launch_bounds__(256) k_row_eval(RowsCtx C, int64_t m, const do
   if (r >= m) return;
   const RowDesc rd = C.rows[r];
   const int K = C.g.ncomp, J = C.g.J, dim = C.g.dim;
-  const int stride = 2 + 2 * K;
+  const int nq = C.op->nq;
+  const int stride = 2 + 2 * K + 2 * nq;
   double x[kMaxDim], l[kMaxDim], nrm[kMaxDim];
 #pragma unroll
   for (int a = 0; a < kMaxDim; ++a) {
@@ -407,6 +512,7 @@ __global__ void __launch_bounds__(256) k_row_eval(RowsCtx C, int64_t m, const do
   }
   double au = 0.0, ad = 0.0;
   double vu[kMaxComp] = {0, 0, 0, 0}, vd[kMaxComp] = {0, 0, 0, 0};
+  double qu[kMaxQ] = {0, 0, 0, 0, 0, 0, 0, 0}, qd[kMaxQ] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (rd.kind == RFM_PDE) {
     const int q = rd.sel;
     norm_coords(C.g, rd.owner, x, l);
@@ -416,14 +522,18 @@ __global__ void __launch_bounds__(256) k_row_eval(RowsCtx C, int64_t m, const do
         const int64_t f = fb + j;
         const double t = feat_t(C, f, l);
         double Lv = 0.0;
-        for (int i = 0; i < C.op.nlin; ++i)
-          if (C.op.lin_eq[i] == q && C.op.lin_comp[i] == c) Lv += C.op.lin_coeff[i] * feat_deriv(C, C.op.lin_deriv[i], f, t);
+        for (int i = 0; i < C.op->nlin; ++i)
+          if (C.op->lin_eq[i] == q && C.op->lin_comp[i] == c) Lv += C.op->lin_coeff[i] * feat_deriv(C, C.op->lin_deriv[i], f, t);
         const double a = u[f];
         const double d = du ? du[f] : 0.0;
         vu[c] += t * a;
         vd[c] += t * d;
         au += Lv * a;
         ad += Lv * d;
+        if (nq) {
+          quantity_acc(C, c, f, t, a, qu);
+          quantity_acc(C, c, f, t, d, qd);
+        }
       }
     }
   } else if (rd.kind == RFM_CONTINUITY) {
@@ -459,6 +569,13 @@ __global__ void __launch_bounds__(256) k_row_eval(RowsCtx C, int64_t m, const do
     vu[c] = wave_sum(vu[c]);
     vd[c] = wave_sum(vd[c]);
   }
+#pragma unroll
+  for (int qq = 0; qq < kMaxQ; ++qq) {
+    if (qq < nq) {
+      qu[qq] = wave_sum(qu[qq]);
+      qd[qq] = wave_sum(qd[qq]);
+    }
+  }
   if (lane == 0) {
     double* o = ab + r * stride;
     o[0] = au - (rd.kind == RFM_CONTINUITY ? 0.0 : C.rowdata[r]);
@@ -466,6 +583,13 @@ __global__ void __launch_bounds__(256) k_row_eval(RowsCtx C, int64_t m, const do
     for (int c = 0; c < K; ++c) {
       o[2 + c] = vu[c];
       o[2 + K + c] = vd[c];
+    }
+#pragma unroll
+    for (int qq = 0; qq < kMaxQ; ++qq) {
+      if (qq < nq) {
+        o[2 + 2 * K + qq] = qu[qq];
+        o[2 + 2 * K + nq + qq] = qd[qq];
+      }
     }
   }
 }
@@ -478,25 +602,35 @@ __global__ void __launch_bounds__(kRedBlock) k_phi(RowsCtx C, int64_t m, const d
                                                    double* __restrict__ partial, double* __restrict__ Fout) {
   __shared__ double sh[kRedBlock];
   const int K = C.g.ncomp;
-  const int stride = 2 + 2 * K;
+  const int nq = C.op->nq;
+  const int stride = 2 + 2 * K + 2 * nq;
   double acc = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; r < m; r += (int64_t)gridDim.x * kRedBlock) {
     const double* o = ab + r * stride;
     double F = o[0] + alpha * o[1];
     const RowDesc rd = C.rows[r];
     if (rd.kind == RFM_PDE) {
-      for (int i = 0; i < C.op.npoly; ++i) {
-        if (C.op.poly_eq[i] != rd.sel) continue;
-        double prod = C.op.poly_coeff[i];
-        for (int c = 0; c < K; ++c) prod *= ipow(o[2 + c] + alpha * o[2 + K + c], C.op.poly_pow[i][c]);
+      for (int i = 0; i < C.op->npoly; ++i) {
+        if (C.op->poly_eq[i] != rd.sel) continue;
+        double prod = C.op->poly_coeff[i];
+        for (int c = 0; c < K; ++c) prod *= ipow(o[2 + c] + alpha * o[2 + K + c], C.op->poly_pow[i][c]);
         F += prod;
       }
-      for (int i = 0; i < C.op.nfn; ++i) {
-        if (C.op.fn_eq[i] != rd.sel) continue;
-        const int c = C.op.fn_comp[i];
+      for (int i = 0; i < C.op->nfn; ++i) {
+        if (C.op->fn_eq[i] != rd.sel) continue;
+        const int c = C.op->fn_comp[i];
         double f, df;
-        fn_eval(C.op.fn_kind[i], o[2 + c] + alpha * o[2 + K + c], &f, &df);
-        F += C.op.fn_coeff[i] * f;
+        fn_eval(C.op->fn_kind[i], o[2 + c] + alpha * o[2 + K + c], &f, &df);
+        F += C.op->fn_coeff[i] * f;
+      }
+      for (int i = 0; i < C.op->nprod; ++i) {
+        if (C.op->prod_eq[i] != rd.sel) continue;
+        double term = C.op->prod_coeff[i];
+        for (int k = 0; k < C.op->prod_nfac[i]; ++k) {
+          const int qk = C.op->prod_q[i][k];
+          term *= ipow(o[2 + 2 * K + qk] + alpha * o[2 + 2 * K + nq + qk], C.op->prod_pow[i][k]);
+        }
+        F += term;
       }
     }
     if (Fout) Fout[r] = F;
@@ -643,10 +777,10 @@ __global__ void k_jac_rows(const TileDesc* __restrict__ tiles, const int32_t* __
   }
 }
 
-RowsCtx make_ctx(const Problem& P) {
+RowsCtx make_ctx(Problem& P) {
   RowsCtx C;
   C.g = P.geom;
-  C.op = P.op;
+  C.op = device_op(P);
   C.f = P.feat;
   C.rows = P.d_rows.p;
   C.px = P.d_px.p;

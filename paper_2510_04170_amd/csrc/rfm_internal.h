@@ -92,6 +92,9 @@ constexpr int kMaxComp = 4;
 constexpr int kMaxLin = 16;
 constexpr int kMaxPoly = 8;
 constexpr int kMaxFn = 8;
+constexpr int kMaxProd = 8;  // product terms
+constexpr int kMaxFac = 4;   // factors per product term
+constexpr int kMaxQ = 8;     // distinct field quantities (component, derivative) of the product terms
 constexpr int kMaxRowWidth = 16384;  // widest Jacobian row
 constexpr int kTileRows = 64;       // rows per Jacobian tile
 constexpr int kMaxPieces = 16;      // pieces of D J in a low-precision sketch
@@ -107,6 +110,13 @@ struct OpDesc {
   int nfn;
   int fn_eq[kMaxFn], fn_comp[kMaxFn], fn_kind[kMaxFn];  // kind: RFM_FN_*
   double fn_coeff[kMaxFn];
+  // product terms coeff prod_k v_{q_k}^{p_k} over the field quantities v_q = D_{q_deriv} u_{q_comp}
+  int nq;
+  int q_comp[kMaxQ], q_deriv[kMaxQ];
+  int nprod;
+  int prod_eq[kMaxProd], prod_nfac[kMaxProd];
+  int prod_q[kMaxProd][kMaxFac], prod_pow[kMaxProd][kMaxFac];
+  double prod_coeff[kMaxProd];
 };
 
 // f(v) and f'(v) of a pointwise term
@@ -223,6 +233,9 @@ struct Problem {
   bool have_partition = false, have_features = false, have_operator = false, finalized = false;
   GeomDesc geom{};
   OpDesc op{};
+  DBuf<OpDesc> d_op;      // device copy of op read by the row kernels
+  OpDesc op_on_device{};  // what d_op holds
+  bool have_d_op = false;
   std::vector<double> W, b;           // host copies as given
   std::vector<double> px, pnormal;    // points [npts][dim], normals [npts][dim]
   std::vector<double> rowdata;        // data per row (0 for continuity rows)
@@ -293,7 +306,7 @@ struct Problem {
   DBuf<double> d_u, d_du, d_vec;  // coefficient vectors and scratch
   DBuf<double> d_red;             // reduction partials
   DBuf<double> d_scal;            // reduction results
-  DBuf<double> d_lsab;            // line search: a_r, b_r, vu[K], vd[K] per row
+  DBuf<double> d_lsab;            // line search: a_r, b_r, vu[K], vd[K], qu[nq], qd[nq] per row
   DBuf<LsqrState> d_lsqr;
   DBuf<double> d_ws_lsqr;         // LSQR vectors and partials
   DBuf<double> d_F0, d_F1;        // residual vectors of the drivers
@@ -347,6 +360,9 @@ void launch_sketch_lowp_rows(Problem& P, uint64_t seed, uint64_t jac_index, int 
                              double* out, int64_t ldo);
 void get_sketch_operand(Problem& P, int piece, int blk, int64_t slot0, int64_t nslots, double* out, int32_t* groups,
                         int32_t* scale_exp);
+
+// device copy of P.op, uploaded when it changed (waits for the stream first)
+const OpDesc* device_op(Problem& P);
 
 // k_qr.hip
 void qr_factor(Problem& P);   // in place on d_B, leaves R in d_R (tiled), throws RFM_ESINGULAR
