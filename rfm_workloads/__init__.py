@@ -613,9 +613,51 @@ def quasilinear(nsub=(2, 2, 2), J=800, q=20, seed=0, R=1.0, test_per_dim=None) -
                   jet_quasilinear, lin, [], seed=seed, test_per_dim=test_per_dim, prod_terms=prod)
 
 
+def jet_ball(x: np.ndarray) -> Jet:
+    """u* = (x^2 + y^2 + z^2) sin(pi x) sin(pi y) sin(pi z), its gradient and Laplacian."""
+    pi = math.pi
+    s = [np.sin(pi * x[:, a]) for a in range(3)]
+    c = [np.cos(pi * x[:, a]) for a in range(3)]
+    S = s[0] * s[1] * s[2]
+    dS = np.stack([pi * c[0] * s[1] * s[2], pi * s[0] * c[1] * s[2], pi * s[0] * s[1] * c[2]], 1)
+    p = (x[:, :3] ** 2).sum(1)
+    val = p * S
+    grad = 2.0 * x[:, :3] * S[:, None] + p[:, None] * dS
+    lap = 6.0 * S + 4.0 * (x[:, :3] * dS).sum(1) - 3.0 * pi * pi * p * S
+    return val[:, None], grad[:, None, :], lap[:, None], lap[:, None]
+
+
+def diffusion_reaction_ball(nsub=(2, 2, 2), J=400, q=30, nbdy=30000, seed=0, R=1.0, test_per_dim=None) -> Problem:
+    """3-D steady diffusion-reaction on the unit ball (the paper's AMIPN example of Sec. 5):
+    -div((1 + u^2) grad u) + (u^3 - u) + e^u = f, u* = (x^2 + y^2 + z^2) sin(pi x) sin(pi y) sin(pi z).
+    The ball sits in [-1, 1]^3, split into nsub boxes; the q^3 grid points of each box and the q x q
+    interface grids are kept where x^2 + y^2 + z^2 < 1; Dirichlet u* at nbdy Fibonacci points of the
+    unit sphere, each owned by the box that holds it (no rows on the faces of the cube)."""
+    lin, prod = quasilinear_terms()
+    lin = lin + [(0, 0, -1.0, D_ID)]
+    poly = [(0, 1.0, (3,))]
+    fn = [(0, 0, 1.0, FN_EXP)]
+    lo, hi = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+
+    def inside(p):
+        return (p[:, :3] ** 2).sum(1) < 1.0
+
+    def sphere(lo_, hi_, nsub_, jet_fn):
+        x = fibonacci_sphere(np.zeros(3), 1.0, nbdy)
+        owner = box_of(x, lo_, hi_, nsub_)
+        return [PointGroup(KIND_DIRICHLET, x[owner == e], int(e), comp=-1, data=jet_fn(x[owner == e])[0])
+                for e in np.unique(owner)]
+
+    return _build("diffusion_reaction_ball", 3, 1, lo, hi, nsub, J, R, q, q, jet_ball, lin, poly, seed=seed,
+                  dirichlet_faces=[], test_per_dim=test_per_dim, inside=inside, extra_groups=sphere,
+                  fn_terms=fn, prod_terms=prod)
+
+
 def jet_of(problem: Problem):
     """Closed-form jet of the problem's manufactured solution."""
     name = problem.name
+    if name == "diffusion_reaction_ball":
+        return jet_ball
     if name == "quasilinear_3d":
         return jet_quasilinear
     if name == "helmholtz_cosh_3d":

@@ -646,3 +646,38 @@ def test_quasilinear_problem_by_manufactured_solution():
     u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
     assert st.status == "ok"
     assert np.all(O.rel_l2(prob, u) < 5e-4)
+
+
+def test_ball_problem_data_and_geometry():
+    """The diffusion-reaction problem on the unit ball (Sec. 5): its data against central differences of
+    the flux (1 + u*^2) grad u* plus u*^3 - u* + e^u*, every collocation and interface point inside the
+    ball, the Dirichlet points on the unit sphere and owned by the box that holds them, no rows on the
+    cube's faces, and the jet of u* against central differences."""
+    prob = W.diffusion_reaction_ball(J=4, q=7, nbdy=500)
+    for g in prob.groups:
+        r2 = (g.x ** 2).sum(1)
+        if g.kind == W.KIND_DIRICHLET:
+            assert np.allclose(r2, 1.0, atol=1e-12)
+            blo, bhi = W.box_bounds(g.owner, prob.lo, prob.hi, prob.nsub)
+            assert np.all((g.x >= blo - 1e-12) & (g.x <= bhi + 1e-12))
+        else:
+            assert np.all(r2 < 1.0)
+    assert sum(g.x.shape[0] for g in prob.groups if g.kind == W.KIND_DIRICHLET) == 500
+    g = next(g for g in prob.groups if g.kind == W.KIND_PDE and g.x.shape[0] > 20)
+    u = prob.exact(g.x)[:, 0]
+    f = _flux_divergence(prob.exact, g.x) + u ** 3 - u + np.exp(u)
+    assert np.abs(f - g.data[:, 0]).max() < 1e-4 * max(1.0, np.abs(g.data).max())
+    val, grad, sec = _fd_jet(prob.exact, g.x)
+    jv, jg, jl, _ = W.jet_ball(g.x)
+    assert np.abs(jv - val).max() < 1e-12
+    assert np.abs(jg - grad).max() < 1e-6
+    assert np.abs(jl[:, 0] - sec[:, 0].sum(-1)).max() < 1e-4
+
+
+def test_ball_problem_by_manufactured_solution():
+    """Exact Newton reaches u* of the ball problem to the discretisation's accuracy (2x2x2 boxes,
+    J = 200, q = 10, 2000 sphere points)."""
+    prob = W.diffusion_reaction_ball(J=200, q=10, nbdy=2000, test_per_dim=4)
+    u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
+    assert st.status == "ok"
+    assert np.all(O.rel_l2(prob, u) < 5e-3)
