@@ -653,9 +653,54 @@ def diffusion_reaction_ball(nsub=(2, 2, 2), J=400, q=30, nbdy=30000, seed=0, R=1
                   fn_terms=fn, prod_terms=prod)
 
 
+def jet_gray_scott_nonlinear(x: np.ndarray) -> Jet:
+    """u* = sin(x(1 - x)) sin(y(1 - y)) e^z and v* = sin(pi x) sin(pi y) sin(pi z): values [P, 2],
+    gradients [P, 2, 3] and Laplacians [P, 2]."""
+    pi = math.pi
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+
+    def a(t):
+        w = t * (1.0 - t)
+        return np.sin(w), np.cos(w) * (1.0 - 2.0 * t), -np.sin(w) * (1.0 - 2.0 * t) ** 2 - 2.0 * np.cos(w)
+
+    ax, dax, d2ax = a(X)
+    ay, day, d2ay = a(Y)
+    ez = np.exp(Z)
+    u = ax * ay * ez
+    gu = np.stack([dax * ay * ez, ax * day * ez, u], 1)
+    lu = (d2ax * ay + ax * d2ay + ax * ay) * ez
+    s = [np.sin(pi * x[:, k]) for k in range(3)]
+    c = [np.cos(pi * x[:, k]) for k in range(3)]
+    v = s[0] * s[1] * s[2]
+    gv = pi * np.stack([c[0] * s[1] * s[2], s[0] * c[1] * s[2], s[0] * s[1] * c[2]], 1)
+    lv = -3.0 * pi * pi * v
+    val = np.stack([u, v], 1)
+    grad = np.stack([gu, gv], 1)
+    lap = np.stack([lu, lv], 1)
+    return val, grad, lap, lap
+
+
+GS2_F, GS2_K = 0.060, 0.062
+
+
+def gray_scott_nonlinear(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, F=GS2_F, k=GS2_K, test_per_dim=None) -> Problem:
+    """The paper's steady Gray-Scott system with solution-dependent diffusion (Sec. 5):
+    (1 + u^2) Lap u - u v^2 + F (1 - u) = f1, (1 + v^2) Lap v + u v^2 - (F + k) v = f2 on the unit cube,
+    u* = sin(x(1 - x)) sin(y(1 - y)) e^z, v* = sin(pi x) sin(pi y) sin(pi z), Dirichlet u*, v*; the
+    constant F of the first equation is carried by the data."""
+    lin = [(0, 0, 1.0, D_LAPLACE), (0, 0, -F, D_ID), (1, 1, 1.0, D_LAPLACE), (1, 1, -(F + k), D_ID)]
+    poly = [(0, -1.0, (1, 2)), (1, 1.0, (1, 2))]
+    prod = [(0, 1.0, ((0, D_ID, 2), (0, D_LAPLACE, 1))), (1, 1.0, ((1, D_ID, 2), (1, D_LAPLACE, 1)))]
+    return _build("gray_scott_nonlinear_3d", 3, 2, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), nsub, J, R, q, q,
+                  jet_gray_scott_nonlinear, lin, poly, seed=seed, test_per_dim=test_per_dim,
+                  prod_terms=prod, params=dict(F=F, k=k))
+
+
 def jet_of(problem: Problem):
     """Closed-form jet of the problem's manufactured solution."""
     name = problem.name
+    if name == "gray_scott_nonlinear_3d":
+        return jet_gray_scott_nonlinear
     if name == "diffusion_reaction_ball":
         return jet_ball
     if name == "quasilinear_3d":

@@ -681,3 +681,32 @@ def test_ball_problem_by_manufactured_solution():
     u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
     assert st.status == "ok"
     assert np.all(O.rel_l2(prob, u) < 5e-3)
+
+
+def test_gray_scott_nonlinear_data_matches_finite_differences():
+    """The paper's Gray-Scott system with D = 1 + u^2, 1 + v^2 (Sec. 5): its data (the constant F of
+    the first equation carried by the data) against central differences of (u*, v*), and the jet."""
+    prob = W.gray_scott_nonlinear(nsub=(2, 2, 2), J=4, q=5)
+    g = prob.groups[2]
+    assert g.kind == W.KIND_PDE
+    val, grad, sec = _fd_jet(prob.exact, g.x)
+    u, v = val[:, 0], val[:, 1]
+    lu, lv = sec[:, 0].sum(-1), sec[:, 1].sum(-1)
+    F, k = W.GS2_F, W.GS2_K
+    f1 = (1 + u * u) * lu - u * v * v + F * (1 - u) - F
+    f2 = (1 + v * v) * lv + u * v * v - (F + k) * v
+    scale = max(1.0, np.abs(g.data).max())
+    assert np.abs(f1 - g.data[:, 0]).max() < 2e-5 * scale
+    assert np.abs(f2 - g.data[:, 1]).max() < 2e-5 * scale
+    jv, jg, jl, _ = W.jet_gray_scott_nonlinear(g.x)
+    assert np.abs(jv - val).max() < 1e-12
+    assert np.abs(jg - grad).max() < 1e-6
+    assert np.abs(jl - sec.sum(-1)).max() < 1e-4
+
+
+def test_gray_scott_nonlinear_by_manufactured_solution():
+    """Exact Newton reaches (u*, v*) of the nonlinear-diffusion Gray-Scott system (one box)."""
+    prob = W.gray_scott_nonlinear(nsub=(1, 1, 1), J=300, q=12, test_per_dim=4)
+    u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
+    assert st.status == "ok"
+    assert np.all(O.rel_l2(prob, u) < 5e-3)
