@@ -40,7 +40,7 @@ from typing import List, Optional
 import numpy as np
 import scipy.linalg
 
-from rfm_workloads import (KIND_CONTINUITY, KIND_DIRICHLET, KIND_NEUMANN, KIND_PDE, D_ID, D_LAPLACE,
+from rfm_workloads import (box_multi, KIND_CONTINUITY, KIND_DIRICHLET, KIND_NEUMANN, KIND_PDE, D_ID, D_LAPLACE,
                            D_LAPLACE_SPACE, D_X0, D_X3, Problem, box_bounds)
 from . import lowprec, philox
 
@@ -75,6 +75,66 @@ def feature_jet(prob: Problem, e: int, c: int, x: np.ndarray):
     return t, dphi, d2phi
 
 
+# ---------------------------------------------------------------------------
+# smooth partition of unity (Sec. 2.2): psi_e(x) = prod_a varphi^b(l_a(x)), l the box's affine map
+# to [-1, 1]^d; varphi^b = 1 on |y| <= 3/4, (1 - sin(2 pi |y|)) / 2 on 3/4 <= |y| <= 5/4, 0 beyond
+# ---------------------------------------------------------------------------
+
+def bump_b(y: np.ndarray):
+    """varphi^b(y) and its first and second derivatives."""
+    a = np.abs(y)
+    band = (a > 0.75) & (a < 1.25)
+    f = np.where(a <= 0.75, 1.0, np.where(band, 0.5 * (1.0 - np.sin(2.0 * np.pi * a)), 0.0))
+    d1 = np.where(band, -np.pi * np.cos(2.0 * np.pi * a) * np.sign(y), 0.0)
+    d2 = np.where(band, 2.0 * np.pi ** 2 * np.sin(2.0 * np.pi * a), 0.0)
+    return f, d1, d2
+
+
+def pou_b(prob: Problem, e: int, x: np.ndarray):
+    """psi_e [n], its gradient [n, d] and pure second derivatives [n, d] at x.  On an axis where the box
+    touches the boundary of the domain the bump is 1 on the side facing it, so that the functions sum to
+    1 on the whole domain (the tensor-product bumps alone sum to 1/2 on the boundary)."""
+    mu, sig = box_centre_radius(prob, e)
+    y = (x - mu) / sig
+    f, d1, d2 = bump_b(y)
+    d = x.shape[1]
+    idx = box_multi(e, prob.nsub)
+    for a in range(d):
+        flat = ((idx[a] == 0) & (y[:, a] < 0)) | ((idx[a] == prob.nsub[a] - 1) & (y[:, a] > 0))
+        f[flat, a], d1[flat, a], d2[flat, a] = 1.0, 0.0, 0.0
+    psi = np.prod(f, axis=1)
+    g = np.zeros_like(x)
+    h = np.zeros_like(x)
+    for a in range(d):
+        others = np.prod(np.delete(f, a, axis=1), axis=1)
+        g[:, a] = d1[:, a] / sig[a] * others
+        h[:, a] = d2[:, a] / sig[a] ** 2 * others
+    return psi, g, h
+
+
+def in_support_b(prob: Problem, e: int, x: np.ndarray) -> np.ndarray:
+    """Points strictly inside the support of psi_e (|l_a(x)| < 5/4 on every axis)."""
+    mu, sig = box_centre_radius(prob, e)
+    return np.all(np.abs((x - mu) / sig) < 1.25, axis=1)
+
+
+def blended_jet(prob: Problem, e: int, c: int, x: np.ndarray):
+    """psi_e phi of the J features of (e, c): values [n,J], gradients [n,J,d], pure second derivatives
+    [n,J,d] by the product rule (d_a (psi phi) = psi d_a phi + phi d_a psi,
+    d_aa (psi phi) = psi d_aa phi + 2 d_a psi d_a phi + phi d_aa psi)."""
+    phi, dphi, d2phi = feature_jet(prob, e, c, x)
+    psi, g, h = pou_b(prob, e, x)
+    v = psi[:, None] * phi
+    dv = psi[:, None, None] * dphi + phi[:, :, None] * g[:, None, :]
+    d2v = psi[:, None, None] * d2phi + 2.0 * g[:, None, :] * dphi + phi[:, :, None] * h[:, None, :]
+    return v, dv, d2v
+
+
+def covering_boxes(prob: Problem, x: np.ndarray) -> List[int]:
+    """Boxes whose smooth partition function is non-zero at some of the points x."""
+    return [e for e in range(prob.nbox) if in_support_b(prob, e, x).any()]
+
+
 def apply_deriv(prob: Problem, deriv: int, phi, dphi, d2phi):
     """Linear derivative selector applied to feature (or field) jets."""
     if deriv == D_ID:
@@ -107,8 +167,95 @@ def _comps(prob: Problem, g) -> List[int]:
     return list(range(prob.ncomp)) if g.comp < 0 else [g.comp]
 
 
+def _group_F_J_pou_b(prob: Problem, g, u: np.ndarray, with_J: bool):
+    """group_F_J with the smooth partition of unity: u_n(x) = sum_e psi_e(x) sum_j phi_ej(x) u_ej over
+    the boxes whose support holds x, each of their columns getting psi_e phi (and its derivatives)."""
+    if g.kind == KIND_CONTINUITY:
+        raise ValueError("no continuity rows with the smooth partition of unity")
+    n, x = prob.n, g.x
+    boxes = covering_boxes(prob, x)
+    jets = {e: [blended_jet(prob, e, c, x) for c in range(prob.ncomp)] for e in boxes}
+    coef = {e: [u[col_slice(prob, e, c)] for c in range(prob.ncomp)] for e in boxes}
+
+    def field(c, deriv):
+        return sum(apply_deriv(prob, deriv, *jets[e][c]) @ coef[e][c] for e in boxes)
+
+    def add_J(Jq, c, deriv, w):
+        for e in boxes:
+            Jq[:, col_slice(prob, e, c)] += w[:, None] * apply_deriv(prob, deriv, *jets[e][c])
+
+    Fs, Js = [], []
+    if g.kind == KIND_PDE:
+        val = [field(c, D_ID) for c in range(prob.ncomp)]
+        for q in _comps(prob, g):
+            Fq = -g.data[:, q].copy() if g.comp < 0 else -g.data[:, 0].copy()
+            Jq = np.zeros((g.npts, n)) if with_J else None
+            for (eq, c, coeff, deriv) in prob.lin_terms:
+                if eq != q:
+                    continue
+                Fq += coeff * field(c, deriv)
+                if with_J:
+                    add_J(Jq, c, deriv, np.full(g.npts, coeff))
+            for (eq, coeff, pw) in prob.poly_terms:
+                if eq != q:
+                    continue
+                prod = np.ones(g.npts)
+                for c, p in enumerate(pw):
+                    prod = prod * val[c] ** p
+                Fq += coeff * prod
+                if with_J:
+                    for c, p in enumerate(pw):
+                        if p == 0:
+                            continue
+                        dprod = p * val[c] ** (p - 1)
+                        for c2, p2 in enumerate(pw):
+                            if c2 != c:
+                                dprod = dprod * val[c2] ** p2
+                        add_J(Jq, c, D_ID, coeff * dprod)
+            for (eq, c, coeff, fn) in getattr(prob, "fn_terms", ()):
+                if eq != q:
+                    continue
+                f, df = _FN[fn]
+                Fq += coeff * f(val[c])
+                if with_J:
+                    add_J(Jq, c, D_ID, coeff * df(val[c]))
+            for (eq, coeff, facs) in getattr(prob, "prod_terms", ()):
+                if eq != q:
+                    continue
+                vk = [field(c, d) for (c, d, p) in facs]
+                term = np.full(g.npts, coeff)
+                for k, (c, d, p) in enumerate(facs):
+                    term = term * vk[k] ** p
+                Fq += term
+                if with_J:
+                    for k, (c, d, p) in enumerate(facs):
+                        dk = coeff * p * vk[k] ** (p - 1)
+                        for k2, (c2, d2, p2) in enumerate(facs):
+                            if k2 != k:
+                                dk = dk * vk[k2] ** p2
+                        add_J(Jq, c, d, dk)
+            Fs.append(Fq)
+            Js.append(Jq)
+    else:  # Dirichlet or Neumann
+        for k, c in enumerate(_comps(prob, g)):
+            F = -g.data[:, k].copy()
+            Jr = np.zeros((g.npts, n)) if with_J else None
+            for e in boxes:
+                v, dv, _ = jets[e][c]
+                op = v if g.kind == KIND_DIRICHLET else np.einsum("pjd,pd->pj", dv, g.normal)
+                F += op @ coef[e][c]
+                if with_J:
+                    Jr[:, col_slice(prob, e, c)] = op
+            Fs.append(F)
+            Js.append(Jr)
+    return Fs, Js
+
+
 def group_F_J(prob: Problem, g, u: np.ndarray, with_J: bool = True):
     """Residual rows and dense Jacobian rows [rows, n] of one point group."""
+    if getattr(prob, "pou", "a") == "b":
+        Fs, Js = _group_F_J_pou_b(prob, g, u, with_J)
+        return np.concatenate(Fs), (np.concatenate(Js, axis=0) if with_J else None)
     n = prob.n
     x = g.x
     e = g.owner
@@ -608,7 +755,14 @@ def solve(prob: Problem, u0=None, opts: Optional[Opts] = None):
 
 
 def eval_field(prob: Problem, u: np.ndarray, x: np.ndarray, owner: np.ndarray) -> np.ndarray:
-    """u_n(x) [npts, ncomp] with the piecewise (indicator) partition of unity."""
+    """u_n(x) [npts, ncomp]: with the indicator partition of unity the features of the owner box, with
+    the smooth one sum_e psi_e phi_e u_e over the boxes whose support holds x."""
+    if getattr(prob, "pou", "a") == "b":
+        out = np.zeros((x.shape[0], prob.ncomp))
+        for e in covering_boxes(prob, x):
+            for c in range(prob.ncomp):
+                out[:, c] += blended_jet(prob, e, c, x)[0] @ u[col_slice(prob, e, c)]
+        return out
     out = np.zeros((x.shape[0], prob.ncomp))
     for e in np.unique(owner):
         sel = np.nonzero(owner == e)[0]

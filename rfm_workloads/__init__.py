@@ -83,6 +83,9 @@ class Problem:
     fn_terms: List[Tuple[int, int, float, str]] = field(default_factory=list)  # (eq, comp, coeff, function)
     # (eq, coeff, ((comp, deriv, power), ...)): coeff times the product of derivatives of the field
     prod_terms: List[Tuple[int, float, Tuple[Tuple[int, int, int], ...]]] = field(default_factory=list)
+    # partition of unity (Sec. 2.2): "a" indicator of each box (with continuity rows), "b" the smooth
+    # tensor-product bump of support 5/4 of each box's half-width (no continuity rows)
+    pou: str = "a"
 
     @property
     def nbox(self) -> int:
@@ -279,7 +282,7 @@ def apply_operator_to_jet(jet: Jet, lin_terms, poly_terms, neq: int, fn_terms=()
 
 def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_terms, poly_terms,
            seed=0, dirichlet_faces=None, test_per_dim=None, inside=None, extra_groups=None,
-           params=None, fn_terms=(), prod_terms=()):
+           params=None, fn_terms=(), prod_terms=(), pou="a"):
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
     nsub = np.asarray(nsub, np.int64)
@@ -299,8 +302,9 @@ def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_term
         f = apply_operator_to_jet(jet_fn(pts), lin_terms, poly_terms, ncomp, fn_terms, prod_terms)
         groups.append(PointGroup(KIND_PDE, pts, e, data=f))
 
-    # continuity groups: direction, plane, transverse box (axis 0 fastest)
-    for a in range(dim):
+    # continuity groups: direction, plane, transverse box (axis 0 fastest); none with the smooth
+    # partition of unity, whose blend is already continuously differentiable
+    for a in (range(dim) if pou == "a" else ()):
         for p in range(int(nsub[a]) - 1):
             for e in range(nbox):
                 mi = box_multi(e, nsub)
@@ -350,19 +354,19 @@ def _build(name, dim, ncomp, lo, hi, nsub, J, R, q_int, q_face, jet_fn, lin_term
                    groups=groups, lin_terms=list(lin_terms), poly_terms=list(poly_terms),
                    exact=exact, test_x=np.concatenate(tx), test_owner=np.concatenate(to),
                    params=dict(params or {}, seed=seed, R=R, q_int=q_int, q_face=q_face),
-                   fn_terms=list(fn_terms), prod_terms=list(prod_terms))
+                   fn_terms=list(fn_terms), prod_terms=list(prod_terms), pou=pou)
 
 
 # ----------------------------------------------------------------------------
 # the workloads
 # ----------------------------------------------------------------------------
 
-def config1(nsub=(2, 2), J=200, q=20, seed=0, R=1.0, test_per_dim=None) -> Problem:
+def config1(nsub=(2, 2), J=200, q=20, seed=0, R=1.0, test_per_dim=None, pou="a") -> Problem:
     """2-D  -Lap u + u^3 = f on [0,1]^2, u* = sin(pi x) sin(pi y) + x y / 2, Dirichlet."""
     lin = [(0, 0, -1.0, D_LAPLACE)]
     poly = [(0, 1.0, (3,))]
     return _build("poisson_cubic_2d", 2, 1, (0, 0), (1, 1), nsub, J, R, q, q, jet_config1, lin, poly,
-                  seed=seed, test_per_dim=test_per_dim)
+                  seed=seed, test_per_dim=test_per_dim, pou=pou)
 
 
 GS_F, GS_K = 0.04, 0.06
@@ -378,12 +382,12 @@ def gray_scott_terms(F=GS_F, k=GS_K, Du=1.0, Dv=0.5):
 
 
 def config2(nsub=(4, 4, 4), J=300, q=10, seed=0, R=1.5, F=GS_F, k=GS_K, amp=0.5,
-            test_per_dim=None) -> Problem:
+            test_per_dim=None, pou="a") -> Problem:
     """3-D steady Gray-Scott on the unit cube with a manufactured pair (u*, v*)."""
     lin, poly = gray_scott_terms(F, k)
     jet = lambda x: jet_config2(x, amp)
     return _build("gray_scott_3d", 3, 2, (0, 0, 0), (1, 1, 1), nsub, J, R, q, q, jet, lin, poly,
-                  seed=seed, test_per_dim=test_per_dim, params=dict(F=F, k=k, amp=amp))
+                  seed=seed, test_per_dim=test_per_dim, params=dict(F=F, k=k, amp=amp), pou=pou)
 
 
 def config3_nohole(nsub=(8, 8, 8), J=250, q=8, seed=0, R=1.0, test_per_dim=None) -> Problem:
@@ -572,14 +576,14 @@ def jet_helmholtz_cosh(x: np.ndarray) -> Jet:
     return val[:, None], grad[:, None, :], lap[:, None], lap[:, None]
 
 
-def helmholtz_cosh(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, test_per_dim=None) -> Problem:
+def helmholtz_cosh(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, test_per_dim=None, pou="a") -> Problem:
     """3-D nonlinear Helmholtz with a cosh term on the unit cube (the paper's IPN / AMIPN comparison,
     Sec. 5): Lap u - 100 u + 10 cosh(u) = f, u* = (2 + |x|^2) sin(pi x) sin(pi y) sin(pi z),
     Dirichlet u* on the boundary; q^3 collocation points per box, q x q face and interface grids."""
     lin = [(0, 0, 1.0, D_LAPLACE), (0, 0, -100.0, D_ID)]
     fn = [(0, 0, 10.0, FN_COSH)]
     return _build("helmholtz_cosh_3d", 3, 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), nsub, J, R, q, q,
-                  jet_helmholtz_cosh, lin, [], seed=seed, test_per_dim=test_per_dim, fn_terms=fn)
+                  jet_helmholtz_cosh, lin, [], seed=seed, test_per_dim=test_per_dim, fn_terms=fn, pou=pou)
 
 
 def jet_quasilinear(x: np.ndarray) -> Jet:
@@ -604,13 +608,13 @@ def quasilinear_terms():
     return lin, prod
 
 
-def quasilinear(nsub=(2, 2, 2), J=800, q=20, seed=0, R=1.0, test_per_dim=None) -> Problem:
+def quasilinear(nsub=(2, 2, 2), J=800, q=20, seed=0, R=1.0, test_per_dim=None, pou="a") -> Problem:
     """3-D quasi-linear elliptic benchmark of the paper (Sec. 3.4 and the AMIPN table of Sec. 5):
     -div((1 + u^2) grad u) = f on the unit cube, u* = (x + y + z) sin(pi x) sin(pi y) cos(pi z),
     Dirichlet u* on the boundary; q^3 collocation points per box, q x q face and interface grids."""
     lin, prod = quasilinear_terms()
     return _build("quasilinear_3d", 3, 1, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), nsub, J, R, q, q,
-                  jet_quasilinear, lin, [], seed=seed, test_per_dim=test_per_dim, prod_terms=prod)
+                  jet_quasilinear, lin, [], seed=seed, test_per_dim=test_per_dim, prod_terms=prod, pou=pou)
 
 
 def jet_ball(x: np.ndarray) -> Jet:

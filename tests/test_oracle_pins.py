@@ -710,3 +710,93 @@ def test_gray_scott_nonlinear_by_manufactured_solution():
     u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
     assert st.status == "ok"
     assert np.all(O.rel_l2(prob, u) < 5e-3)
+
+
+# ---------------------------------------------------------------------------
+# smooth partition of unity (Sec. 2.2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nsub", [(2, 2), (3, 1), (2, 2, 2)])
+def test_smooth_pou_sums_to_one_on_the_domain(nsub):
+    """The smooth partition functions sum to 1 everywhere in the domain, the strips along its boundary
+    included (where an edge box's bump is flat on the side facing the boundary)."""
+    d = len(nsub)
+    prob = W.config1(J=4, q=4, pou="b") if d == 2 else W.quasilinear(nsub=nsub, J=4, q=4, pou="b")
+    prob.nsub = np.asarray(nsub)
+    x = np.random.default_rng(3).uniform(0.0, 1.0, size=(4000, d))
+    x[:200, 0] = 0.0
+    x[200:400, -1] = 1.0
+    s = sum(O.pou_b(prob, e, x)[0] for e in range(int(np.prod(nsub))))
+    assert np.abs(s - 1.0).max() < 1e-14
+
+
+def test_smooth_bump_is_c1_and_its_derivatives():
+    """varphi^b: derivatives against central differences away from the band edges; value and first
+    derivative continuous across |y| = 3/4 and 5/4 (the second derivative jumps there)."""
+    y = np.random.default_rng(4).uniform(-1.5, 1.5, size=5000)
+    y = y[np.min(np.abs(np.abs(y)[:, None] - np.array([0.75, 1.25])[None]), axis=1) > 1e-3]
+    h = 1e-6
+    f, d1, d2 = O.bump_b(y)
+    fp, d1p, _ = O.bump_b(y + h)
+    fm, d1m, _ = O.bump_b(y - h)
+    assert np.abs((fp - fm) / (2 * h) - d1).max() < 1e-7
+    assert np.abs((d1p - d1m) / (2 * h) - d2).max() < 1e-5
+    for edge in (0.75, 1.25, -0.75, -1.25):
+        lo, hi = O.bump_b(np.array([edge - 1e-9])), O.bump_b(np.array([edge + 1e-9]))
+        assert abs(lo[0][0] - hi[0][0]) < 1e-8 and abs(lo[1][0] - hi[1][0]) < 1e-7
+
+
+def test_smooth_pou_field_derivatives_match_central_differences():
+    """Gradient and Laplacian of the blended field sum_e psi_e phi_e u_e (product rule in the oracle)
+    against central differences of the field itself."""
+    prob = W.config1(J=30, q=6, pou="b", test_per_dim=2)
+    u = np.random.default_rng(5).normal(size=prob.n)
+    x = np.random.default_rng(6).uniform(0.02, 0.98, size=(300, 2))
+    own = np.zeros(x.shape[0], np.int32)
+    boxes = O.covering_boxes(prob, x)
+    grad = sum(O.blended_jet(prob, e, 0, x)[1].transpose(0, 2, 1) @ u[O.col_slice(prob, e, 0)] for e in boxes)
+    lap = sum(O.blended_jet(prob, e, 0, x)[2].sum(-1) @ u[O.col_slice(prob, e, 0)] for e in boxes)
+    f0 = O.eval_field(prob, u, x, own)[:, 0]
+    h, fdl = 1e-4, np.zeros(x.shape[0])
+    for a in range(2):
+        # first differences with a small step: at the bump's band edges the field's second derivative
+        # jumps, so central differences lose their second order there
+        hg = 1e-6
+        xp, xm = x.copy(), x.copy()
+        xp[:, a] += hg
+        xm[:, a] -= hg
+        gfd = (O.eval_field(prob, u, xp, own)[:, 0] - O.eval_field(prob, u, xm, own)[:, 0]) / (2 * hg)
+        assert np.abs(gfd - grad[:, a]).max() < 1e-6 * max(1.0, np.abs(grad).max())
+        xp, xm = x.copy(), x.copy()
+        xp[:, a] += h
+        xm[:, a] -= h
+        fp, fm = O.eval_field(prob, u, xp, own)[:, 0], O.eval_field(prob, u, xm, own)[:, 0]
+        fdl += (fp - 2 * f0 + fm) / (h * h)
+    # the bump's second derivative jumps at |y| = 3/4: compare away from those lines
+    far = np.all(np.abs(np.abs((x % 0.5) - 0.25) / 0.25 - 0.75) > 0.01, axis=1)
+    assert np.abs(fdl - lap)[far].max() < 1e-3 * max(1.0, np.abs(lap).max())
+
+
+def test_smooth_pou_jacobian_matches_central_differences():
+    """Residual and Jacobian rows with the smooth partition (quasi-linear product terms, Dirichlet rows,
+    no continuity rows) against central differences of the residual."""
+    prob = W.quasilinear(nsub=(2, 1, 2), J=4, q=3, pou="b")
+    assert not any(g.kind == W.KIND_CONTINUITY for g in prob.groups)
+    u = 0.3 * np.random.default_rng(4).normal(size=prob.n)
+    F, J = O.assemble(prob, u)
+    Jfd = np.zeros_like(J)
+    for j in range(prob.n):
+        h = 1e-6
+        up, um = u.copy(), u.copy()
+        up[j] += h
+        um[j] -= h
+        Jfd[:, j] = (O.residual(prob, up) - O.residual(prob, um)) / (2 * h)
+    assert np.abs(J - Jfd).max() / np.abs(J).max() < 1e-7
+
+
+def test_smooth_pou_problem_by_manufactured_solution():
+    """Exact Newton with the smooth partition (no continuity rows) reaches u* of the 2-D workload."""
+    prob = W.config1(J=200, q=20, pou="b", test_per_dim=10)
+    u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
+    assert st.status == "ok"
+    assert np.all(O.rel_l2(prob, u) < 1e-6)
