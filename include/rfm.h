@@ -97,6 +97,17 @@ void rfm_destroy(rfm_problem* p);
  * (Sec. 2.2); box index e = i_0 + nsub_0 (i_1 + nsub_1 i_2 ...). */
 rfm_status rfm_set_partition(rfm_problem* p, const double* lo, const double* hi, const int32_t* nsub);
 
+/* Partition of unity (Sec. 2.2), before rfm_finalize.  RFM_POU_INDICATOR
+ * (default): each box's features act on the box alone, and continuity rows join
+ * neighbours.  RFM_POU_SMOOTH: u(x) = sum_e psi_e(x) sum_j phi_ej(x) u_ej with
+ * psi_e = prod_a b(l_a(x)), b(y) = 1 for |y| <= 3/4, (1 - sin(2 pi |y|)) / 2 for
+ * 3/4 <= |y| <= 5/4, 0 beyond, except that on an axis where the box touches
+ * the boundary of Omega_c, b = 1 on the side facing it (so the psi_e sum to 1
+ * on Omega_c); a row at x touches every box whose support holds x (at most
+ * 2^dim), and no continuity groups are allowed (the blend is C1). */
+enum { RFM_POU_INDICATOR = 0, RFM_POU_SMOOTH = 1 };
+rfm_status rfm_set_partition_of_unity(rfm_problem* p, int32_t kind);
+
 /* J tanh features per box and component (Sec. 2.2):
  *   phi_{e,c,j}(x) = tanh(sum_a W[e][c][j][a] (x_a - mu_{e,a}) / sigma_{e,a} + b[e][c][j]),
  * with mu, sigma the centre and half-width of box e.  W: [nbox][ncomp][J][dim],

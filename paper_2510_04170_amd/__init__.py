@@ -24,6 +24,7 @@ RFM_IPN, RFM_AMIPN = 0, 1
 RFM_PREC_F64, RFM_PREC_F32, RFM_PREC_BF16, RFM_PREC_FP8 = 0, 1, 2, 3
 RFM_SKETCH_GAUSSIAN, RFM_SKETCH_COUNT = 0, 1
 RFM_FN_COSH, RFM_FN_SINH, RFM_FN_EXP = 0, 1, 2
+RFM_POU_INDICATOR, RFM_POU_SMOOTH = 0, 1
 _FN_CODE = {"cosh": RFM_FN_COSH, "sinh": RFM_FN_SINH, "exp": RFM_FN_EXP}
 RFM_MAX_STEPS = 64
 
@@ -105,6 +106,7 @@ _SIGS = {
     "rfm_set_operator": (C.c_int, [_P, C.POINTER(rfm_lin_term), C.c_int32, C.POINTER(rfm_poly_term), C.c_int32]),
     "rfm_set_fn_terms": (C.c_int, [_P, C.POINTER(rfm_fn_term), C.c_int32]),
     "rfm_set_prod_terms": (C.c_int, [_P, C.POINTER(rfm_prod_term), C.c_int32]),
+    "rfm_set_partition_of_unity": (C.c_int, [_P, C.c_int32]),
     "rfm_finalize": (C.c_int, [_P]),
     "rfm_set_group_data": (C.c_int, [_P, C.c_int32, _D]),
     "rfm_num_unknowns": (C.c_int64, [_P]),
@@ -338,6 +340,11 @@ class RfmProblem:
             T[i] = rfm_fn_term(eq, comp, coeff, _FN_CODE[fn] if isinstance(fn, str) else int(fn))
         _check(lib().rfm_set_fn_terms(self.h, T, len(fn_terms)))
 
+    def set_partition_of_unity(self, kind):
+        """RFM_POU_INDICATOR (or "a") or RFM_POU_SMOOTH (or "b"); before finalize."""
+        k = {"a": RFM_POU_INDICATOR, "b": RFM_POU_SMOOTH}.get(kind, kind)
+        _check(lib().rfm_set_partition_of_unity(self.h, int(k)))
+
     def set_prod_terms(self, prod_terms):
         """Product terms (eq, coeff, ((comp, deriv, power), ...)) with 1..4 factors each."""
         T = (rfm_prod_term * max(1, len(prod_terms)))()
@@ -540,6 +547,8 @@ def from_description(desc, device: int = 0, stream: Optional[int] = None) -> Rfm
     groups, lin_terms, poly_terms) to a new library problem, group by group."""
     p = RfmProblem(desc.dim, desc.ncomp, device, stream)
     p.set_partition(desc.lo, desc.hi, desc.nsub)
+    if getattr(desc, "pou", "a") != "a":
+        p.set_partition_of_unity(desc.pou)
     p.set_features(desc.J, desc.W, desc.b)
     for g in desc.groups:
         p.add_points(g.kind, g.x, g.owner, g.neighbor, g.normal, g.comp, g.cont_order, g.data)

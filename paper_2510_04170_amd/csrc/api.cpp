@@ -162,8 +162,13 @@ static void finalize(Problem& P) {
   RFM_CHECK(P.have_operator, RFM_EINVAL, "rfm_finalize: operator not set");
   RFM_CHECK(!P.groups.empty(), RFM_EINVAL, "rfm_finalize: no points");
   const int K = P.ncomp, J = P.J;
-  for (const auto& g : P.groups)
-    RFM_CHECK(row_width_of_group(P, g) <= kMaxRowWidth, RFM_EINVAL, "row wider than 16384 values");
+  const bool smooth = P.geom.pou == RFM_POU_SMOOTH;
+  for (const auto& g : P.groups) {
+    RFM_CHECK(!(smooth && g.kind == RFM_CONTINUITY), RFM_EINVAL,
+              "rfm_finalize: no continuity rows with the smooth partition of unity");
+    const int segs = smooth ? (1 << P.dim) : 1;
+    RFM_CHECK((int64_t)row_width_of_group(P, g) * segs <= kMaxRowWidth, RFM_EINVAL, "row wider than 16384 values");
+  }
 
   // rows
   std::vector<RowDesc> rows;
@@ -198,7 +203,7 @@ static void finalize(Problem& P) {
   int64_t voff = 0, poff = 0;
   auto add_run = [&](int64_t r0, int64_t nr, int colA, int wA, int colB, int wB) {
     for (int64_t t0 = 0; t0 < nr; t0 += kTileRows) {
-      TileDesc t;
+      TileDesc t{};
       t.row0 = (int32_t)(r0 + t0);
       t.nrows = (int32_t)std::min<int64_t>(kTileRows, nr - t0);
       t.colA = colA;
@@ -207,13 +212,94 @@ static void finalize(Problem& P) {
       t.wB = wB;
       t.val_off = voff;
       t.part_off = poff;
+      t.nseg = wB ? 2 : 1;
+      t.wseg = wA;
+      t.seg_col[0] = colA;
+      t.seg_col[1] = colB;
       voff += (int64_t)t.nrows * (wA + wB);
       poff += wA + wB;
       P.tiles_h.push_back(t);
     }
   };
+  // smooth partition: a run of rows whose points lie in the supports of the same boxes; segment s holds
+  // the columns (box boxes[s], component c0 .. c0 + wseg / J - 1)
+  auto add_run_smooth = [&](int64_t r0, int64_t nr, const std::vector<int>& boxes, int c0, int wseg) {
+    for (int64_t t0 = 0; t0 < nr; t0 += kTileRows) {
+      TileDesc t{};
+      t.row0 = (int32_t)(r0 + t0);
+      t.nrows = (int32_t)std::min<int64_t>(kTileRows, nr - t0);
+      t.nseg = (int32_t)boxes.size();
+      t.wseg = wseg;
+      for (int k = 0; k < t.nseg; ++k) t.seg_col[k] = (boxes[k] * K + c0) * J;
+      t.colA = t.seg_col[0];
+      t.wA = t.nseg * wseg;
+      t.colB = 0;
+      t.wB = 0;
+      t.val_off = voff;
+      t.part_off = poff;
+      voff += (int64_t)t.nrows * t.wA;
+      poff += t.wA;
+      P.tiles_h.push_back(t);
+    }
+  };
+  // the boxes whose smooth partition function is non-zero at point pt, ascending (|l_a(x)| < 5/4 on every
+  // axis among the owner's neighbours; points lie in the domain, where a flat side reaches no further)
+  auto cover = [&](int64_t pt, int owner) {
+    std::vector<int> out;
+    int idx[kMaxDim], rem = owner;
+    for (int a = 0; a < P.dim; ++a) {
+      idx[a] = rem % P.geom.nsub[a];
+      rem /= P.geom.nsub[a];
+    }
+    int ncand = 1;
+    for (int a = 0; a < P.dim; ++a) ncand *= 3;
+    for (int k = 0; k < ncand; ++k) {
+      int kk = k, e = 0, stride = 1;
+      bool ok = true;
+      for (int a = 0; a < P.dim && ok; ++a) {
+        const int ia = idx[a] + kk % 3 - 1;
+        kk /= 3;
+        if (ia < 0 || ia >= P.geom.nsub[a]) {
+          ok = false;
+          break;
+        }
+        const double h = (P.geom.hi[a] - P.geom.lo[a]) / P.geom.nsub[a];
+        const double mu = P.geom.lo[a] + (ia + 0.5) * h, sig = 0.5 * h;
+        const double y = (P.px[(size_t)pt * P.dim + a] - mu) / sig;
+        if (!(std::fabs(y) < 1.25)) ok = false;
+        e += ia * stride;
+        stride *= P.geom.nsub[a];
+      }
+      if (ok) out.push_back(e);
+    }
+    std::sort(out.begin(), out.end());
+    return out;
+  };
+  if (smooth) {
+    for (const auto& g : P.groups) {
+      if (g.npts == 0) continue;
+      const int nsel = g.comp < 0 ? K : 1;
+      const bool pde = g.kind == RFM_PDE;  // PDE rows touch all components of their boxes
+      for (int k = 0; k < nsel; ++k) {
+        const int c = g.comp < 0 ? k : g.comp;
+        const int64_t rbase = g.row0 + (int64_t)k * g.npts;
+        int64_t p0 = 0;
+        std::vector<int> cur = cover(g.pt0, g.owner);
+        for (int64_t p = 1; p <= g.npts; ++p) {
+          std::vector<int> nxt;
+          if (p < g.npts) nxt = cover(g.pt0 + p, g.owner);
+          if (p == g.npts || nxt != cur) {
+            RFM_CHECK(!cur.empty() && (int)cur.size() <= kMaxSeg, RFM_EINVAL, "internal: partition cover");
+            add_run_smooth(rbase + p0, p - p0, cur, pde ? 0 : c, pde ? K * J : J);
+            p0 = p;
+            cur.swap(nxt);
+          }
+        }
+      }
+    }
+  }
   for (const auto& g : P.groups) {
-    if (g.npts == 0) continue;
+    if (g.npts == 0 || smooth) continue;
     int nsel = g.comp < 0 ? K : 1;
     if (g.kind == RFM_PDE) {
       add_run(g.row0, g.nrows, g.owner * K * J, K * J, 0, 0);
@@ -239,8 +325,8 @@ static void finalize(Problem& P) {
   std::vector<std::vector<std::pair<int, int>>> contrib(nblk);
   for (int t = 0; t < P.ntiles; ++t) {
     const TileDesc& td = P.tiles_h[t];
-    for (int o = 0; o < td.wA; o += J) contrib[(td.colA + o) / J].push_back({t, o});
-    if (td.wB) contrib[td.colB / J].push_back({t, td.wA});
+    for (int sg = 0; sg < td.nseg; ++sg)
+      for (int o = 0; o < td.wseg; o += J) contrib[(td.seg_col[sg] + o) / J].push_back({t, sg * td.wseg + o});
   }
   P.cb_ptr_h.assign(nblk + 1, 0);
   P.cb_tile_h.clear();
@@ -466,6 +552,16 @@ rfm_status rfm_set_partition(rfm_problem* p, const double* lo, const double* hi,
     RFM_CHECK(nbox < (1 << 24), RFM_EINVAL, "rfm_set_partition: too many boxes");
     P.geom.nbox = (int)nbox;
     P.have_partition = true;
+  });
+}
+
+rfm_status rfm_set_partition_of_unity(rfm_problem* p, int32_t kind) {
+  return guarded([&] {
+    Problem& P = get(p);
+    RFM_CHECK(!P.finalized, RFM_EINVAL, "rfm_set_partition_of_unity: problem already finalized");
+    RFM_CHECK(kind == RFM_POU_INDICATOR || kind == RFM_POU_SMOOTH, RFM_EINVAL,
+              "rfm_set_partition_of_unity: unknown kind");
+    P.geom.pou = kind;
   });
 }
 

@@ -489,6 +489,387 @@ __global__ void __launch_bounds__(256) k_assemble_wide(RowsCtx C, const TileDesc
   }
 }
 
+// ---------------------------------------------------------------------------
+// smooth partition of unity: psi_e(x) = prod_a b(l_a(x)) with b = 1 on |y| <= 3/4,
+// (1 - sin(2 pi |y|)) / 2 on 3/4 <= |y| <= 5/4, 0 beyond, and b = 1 on the side of an axis where
+// the box touches the boundary of the domain.  A row's boxes are its tile's segments.
+// ---------------------------------------------------------------------------
+
+struct Pou {
+  double psi, g[kMaxDim], h, hs;  // value, gradient, sum of pure second derivatives (all axes; space)
+  double l[kMaxDim];              // the box's local coordinates of the point
+};
+
+__device__ __forceinline__ Pou pou_smooth(const GeomDesc& G, int e, const double* x) {
+  Pou P;
+  double f[kMaxDim], d1[kMaxDim], d2[kMaxDim];
+  int rem = e;
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) {
+    f[a] = 1.0;
+    d1[a] = 0.0;
+    d2[a] = 0.0;
+    P.l[a] = 0.0;
+    if (a < G.dim) {
+      const int i = rem % G.nsub[a];
+      rem /= G.nsub[a];
+      const double hw = (G.hi[a] - G.lo[a]) / G.nsub[a];
+      const double blo = G.lo[a] + i * hw, bhi = blo + hw;
+      const double mu = 0.5 * (blo + bhi), sig = 0.5 * (bhi - blo);
+      const double y = (x[a] - mu) / sig, ay = fabs(y);
+      P.l[a] = y;
+      const bool flat = (i == 0 && y < 0.0) || (i == G.nsub[a] - 1 && y > 0.0);
+      if (!flat && ay > 0.75) {
+        if (ay < 1.25) {
+          double sn, cs;
+          sincospi(2.0 * ay, &sn, &cs);
+          f[a] = 0.5 * (1.0 - sn);
+          d1[a] = -M_PI * cs * (y < 0.0 ? -1.0 : 1.0) / sig;
+          d2[a] = 2.0 * M_PI * M_PI * sn / (sig * sig);
+        } else {
+          f[a] = 0.0;
+        }
+      }
+    }
+  }
+  P.psi = 1.0;
+  P.h = 0.0;
+  P.hs = 0.0;
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) P.psi *= f[a];
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) {
+    double o = 1.0;
+#pragma unroll
+    for (int b2 = 0; b2 < kMaxDim; ++b2)
+      if (b2 != a) o *= f[b2];
+    P.g[a] = d1[a] * o;
+    P.h += d2[a] * o;
+    if (a < G.dim - 1) P.hs += d2[a] * o;
+  }
+  return P;
+}
+
+// the weight table of axis a (an unrolled select: no run-time index into the argument)
+__device__ __forceinline__ const double* ws_of(const RowsCtx& C, int a) {
+  const double* ws = C.f.WS[0];
+#pragma unroll
+  for (int k = 1; k < kMaxDim; ++k)
+    if (a == k) ws = C.f.WS[k];
+  return ws;
+}
+
+// derivative selector applied to psi phi_f (t = tanh of feature f) by the product rule
+__device__ __forceinline__ double smooth_deriv(const RowsCtx& C, int deriv, int64_t f, double t, const Pou& P) {
+  const double dt = 1.0 - t * t;
+  if (deriv == RFM_D_ID) return P.psi * t;
+  if (deriv >= RFM_D_X0 && deriv <= RFM_D_X3) {
+    const int a = deriv - RFM_D_X0;
+    double ga = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k)
+      if (k == a) ga = P.g[k];
+    return P.psi * dt * ws_of(C, a)[f] + t * ga;
+  }
+  const bool space = deriv == RFM_D_LAPLACE_SPACE;
+  const int na = space ? C.g.dim - 1 : C.g.dim;
+  double cross = 0.0;
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a)
+    if (a < na) cross += P.g[a] * C.f.WS[a][f];
+  const double s2 = space ? C.f.S2s[f] : C.f.S2[f];
+  return P.psi * (-2.0 * t * dt * s2) + 2.0 * dt * cross + t * (space ? P.hs : P.h);
+}
+
+__device__ __forceinline__ double smooth_normal(const RowsCtx& C, int64_t f, double t, const Pou& P,
+                                                const double* nrm) {
+  const double dt = 1.0 - t * t;
+  double sw = 0.0, sg = 0.0;
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a)
+    if (a < C.g.dim) {
+      sw += C.f.WS[a][f] * nrm[a];
+      sg += P.g[a] * nrm[a];
+    }
+  return P.psi * dt * sw + t * sg;
+}
+
+// one entry of a smooth-partition row without the nonlinear parts: the linear operator of equation q on
+// component c (PDE rows), or the boundary operator
+__device__ __forceinline__ double smooth_lin_entry(const RowsCtx& C, const RowDesc& rd, int c, int64_t f, double t,
+                                                   const Pou& P, const double* nrm) {
+  if (rd.kind == RFM_PDE) {
+    double Lv = 0.0;
+    for (int i = 0; i < C.op->nlin; ++i)
+      if (C.op->lin_eq[i] == rd.sel && C.op->lin_comp[i] == c)
+        Lv += C.op->lin_coeff[i] * smooth_deriv(C, C.op->lin_deriv[i], f, t, P);
+    return Lv;
+  }
+  return rd.kind == RFM_DIRICHLET ? P.psi * t : smooth_normal(C, f, t, P, nrm);
+}
+
+__device__ __forceinline__ double smooth_quantity_comb(const RowsCtx& C, int c, int64_t f, double t, const Pou& P,
+                                                       const double* w) {
+  double r = 0.0;
+#pragma unroll
+  for (int qq = 0; qq < kMaxQ; ++qq)
+    if (qq < C.op->nq && C.op->q_comp[qq] == c) r += w[qq] * smooth_deriv(C, C.op->q_deriv[qq], f, t, P);
+  return r;
+}
+
+__device__ __forceinline__ void smooth_quantity_acc(const RowsCtx& C, int c, int64_t f, double t, const Pou& P,
+                                                    double x, double* acc) {
+#pragma unroll
+  for (int qq = 0; qq < kMaxQ; ++qq)
+    if (qq < C.op->nq && C.op->q_comp[qq] == c) acc[qq] += smooth_deriv(C, C.op->q_deriv[qq], f, t, P) * x;
+}
+
+// Rows of the smooth partition (PDE, Dirichlet, Neumann), swept three times like k_assemble_wide:
+// sums, maximum, scaled store.  Segment sg of the tile is box seg_col[sg] / (K J); PDE rows hold all K
+// components of each box (position sg wseg + c J + j), boundary rows component sel (sg wseg + j).
+__global__ void __launch_bounds__(256) k_assemble_smooth(RowsCtx C, const TileDesc* __restrict__ tiles,
+                                                         const int32_t* __restrict__ rowtile, int64_t m,
+                                                         const double* __restrict__ u, double cscale,
+                                                         double* __restrict__ Jv, double* __restrict__ DF,
+                                                         double* __restrict__ Dout) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
+  if (r >= m) return;
+  const RowDesc rd = C.rows[r];
+  const TileDesc td = tiles[rowtile[r]];
+  const int K = C.g.ncomp, J = C.g.J, dim = C.g.dim;
+  const bool pde = rd.kind == RFM_PDE;
+  const int c0 = pde ? 0 : rd.sel, c1 = pde ? K : rd.sel + 1;
+  double x[kMaxDim], nrm[kMaxDim];
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) {
+    x[a] = a < dim ? C.px[(int64_t)rd.pt * dim + a] : 0.0;
+    nrm[a] = a < dim ? C.pn[(int64_t)rd.pt * dim + a] : 0.0;
+  }
+  const bool has_q = pde && C.op->nq > 0;
+  // sweep 1: sums
+  double accv[kMaxComp] = {0, 0, 0, 0};
+  double accq[kMaxQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double accL = 0.0;
+  for (int sg = 0; sg < td.nseg; ++sg) {
+    const int e = td.seg_col[sg] / (K * J);
+    const Pou P = pou_smooth(C.g, e, x);
+    for (int c = c0; c < c1; ++c) {
+      const int64_t fb = ((int64_t)e * K + c) * J;
+      double av = 0.0;
+      for (int j = lane; j < J; j += kWave) {
+        const int64_t f = fb + j;
+        const double t = feat_t(C, f, P.l);
+        const double uj = u[f];
+        accL += smooth_lin_entry(C, rd, c, f, t, P, nrm) * uj;
+        av += P.psi * t * uj;
+        if (has_q) smooth_quantity_acc(C, c, f, t, P, uj, accq);
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxComp; ++k)
+        if (k == c) accv[k] += av;
+    }
+  }
+  accL = wave_sum(accL);
+  double dp[kMaxComp] = {0, 0, 0, 0};
+  double dq[kMaxQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double F;
+  if (pde) {
+    double val[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) val[c] = c < K ? wave_sum(accv[c]) : 0.0;
+    double Fp;
+    nonlinear_terms(C, rd.sel, val, Fp, dp);
+    if (has_q) {
+      double vq[kMaxQ];
+#pragma unroll
+      for (int qq = 0; qq < kMaxQ; ++qq) vq[qq] = qq < C.op->nq ? wave_sum(accq[qq]) : 0.0;
+      prod_terms(C, rd.sel, vq, Fp, dq);
+    }
+    F = accL + Fp - C.rowdata[r];
+  } else {
+    F = accL - C.rowdata[r];
+  }
+  // the value of entry (box of segment sg, component c, feature f)
+  auto entry = [&](const Pou& P, int c, int64_t f, double t) -> double {
+    double v = smooth_lin_entry(C, rd, c, f, t, P, nrm);
+    if (pde) {
+      double dpc = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxComp; ++k)
+        if (k == c) dpc = dp[k];
+      v += dpc * P.psi * t;
+      if (has_q) v += smooth_quantity_comb(C, c, f, t, P, dq);
+    }
+    return v;
+  };
+  // sweep 2: row maximum
+  double mx = 0.0;
+  for (int sg = 0; sg < td.nseg; ++sg) {
+    const int e = td.seg_col[sg] / (K * J);
+    const Pou P = pou_smooth(C.g, e, x);
+    for (int c = c0; c < c1; ++c) {
+      const int64_t fb = ((int64_t)e * K + c) * J;
+      for (int j = lane; j < J; j += kWave) {
+        const int64_t f = fb + j;
+        mx = fmax(mx, fabs(entry(P, c, f, feat_t(C, f, P.l))));
+      }
+    }
+  }
+  mx = wave_max(mx);
+  const double D = mx > 0.0 ? cscale / mx : 1.0;
+  // sweep 3: scaled values
+  double* row = Jv + td.val_off + (int64_t)(r - td.row0) * td.wA;
+  for (int sg = 0; sg < td.nseg; ++sg) {
+    const int e = td.seg_col[sg] / (K * J);
+    const Pou P = pou_smooth(C.g, e, x);
+    for (int c = c0; c < c1; ++c) {
+      const int64_t fb = ((int64_t)e * K + c) * J;
+      double* rs = row + sg * td.wseg + (c - c0) * J;
+      for (int j = lane; j < J; j += kWave) {
+        const int64_t f = fb + j;
+        rs[j] = D * entry(P, c, f, feat_t(C, f, P.l));
+      }
+    }
+  }
+  if (lane == 0) {
+    DF[r] = D * F;
+    Dout[r] = D;
+  }
+}
+
+// the line search's per-row record (layout of k_row_eval) for smooth-partition rows
+__global__ void __launch_bounds__(256) k_row_eval_smooth(RowsCtx C, const TileDesc* __restrict__ tiles,
+                                                         const int32_t* __restrict__ rowtile, int64_t m,
+                                                         const double* __restrict__ u,
+                                                         const double* __restrict__ du, double* __restrict__ ab) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t r = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
+  if (r >= m) return;
+  const RowDesc rd = C.rows[r];
+  const TileDesc td = tiles[rowtile[r]];
+  const int K = C.g.ncomp, J = C.g.J, dim = C.g.dim;
+  const int nq = C.op->nq;
+  const int stride = 2 + 2 * K + 2 * nq;
+  const bool pde = rd.kind == RFM_PDE;
+  const int c0 = pde ? 0 : rd.sel, c1 = pde ? K : rd.sel + 1;
+  double x[kMaxDim], nrm[kMaxDim];
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) {
+    x[a] = a < dim ? C.px[(int64_t)rd.pt * dim + a] : 0.0;
+    nrm[a] = a < dim ? C.pn[(int64_t)rd.pt * dim + a] : 0.0;
+  }
+  double au = 0.0, ad = 0.0;
+  double vu[kMaxComp] = {0, 0, 0, 0}, vd[kMaxComp] = {0, 0, 0, 0};
+  double qu[kMaxQ] = {0, 0, 0, 0, 0, 0, 0, 0}, qd[kMaxQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int sg = 0; sg < td.nseg; ++sg) {
+    const int e = td.seg_col[sg] / (K * J);
+    const Pou P = pou_smooth(C.g, e, x);
+    for (int c = c0; c < c1; ++c) {
+      const int64_t fb = ((int64_t)e * K + c) * J;
+      double su = 0.0, sd = 0.0;
+      for (int j = lane; j < J; j += kWave) {
+        const int64_t f = fb + j;
+        const double t = feat_t(C, f, P.l);
+        const double a = u[f], d = du ? du[f] : 0.0;
+        const double Lv = smooth_lin_entry(C, rd, c, f, t, P, nrm);
+        au += Lv * a;
+        ad += Lv * d;
+        su += P.psi * t * a;
+        sd += P.psi * t * d;
+        if (pde && nq) {
+          smooth_quantity_acc(C, c, f, t, P, a, qu);
+          smooth_quantity_acc(C, c, f, t, P, d, qd);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxComp; ++k)
+        if (k == c) {
+          vu[k] += su;
+          vd[k] += sd;
+        }
+    }
+  }
+  au = wave_sum(au);
+  ad = wave_sum(ad);
+  for (int c = 0; c < K; ++c) {
+    vu[c] = wave_sum(vu[c]);
+    vd[c] = wave_sum(vd[c]);
+  }
+#pragma unroll
+  for (int qq = 0; qq < kMaxQ; ++qq)
+    if (qq < nq) {
+      qu[qq] = wave_sum(qu[qq]);
+      qd[qq] = wave_sum(qd[qq]);
+    }
+  if (lane == 0) {
+    double* o = ab + r * stride;
+    o[0] = au - C.rowdata[r];
+    o[1] = ad;
+    for (int c = 0; c < K; ++c) {
+      o[2 + c] = vu[c];
+      o[2 + K + c] = vd[c];
+    }
+#pragma unroll
+    for (int qq = 0; qq < kMaxQ; ++qq)
+      if (qq < nq) {
+        o[2 + 2 * K + qq] = qu[qq];
+        o[2 + 2 * K + nq + qq] = qd[qq];
+      }
+  }
+}
+
+// u_n(x) with the smooth partition: the owner's neighbours whose support holds x
+__global__ void __launch_bounds__(256) k_eval_points_smooth(RowsCtx C, int64_t npts, const double* __restrict__ x,
+                                                            const int32_t* __restrict__ owner,
+                                                            const double* __restrict__ u, double* __restrict__ out) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t p = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
+  if (p >= npts) return;
+  const int K = C.g.ncomp, J = C.g.J, dim = C.g.dim;
+  double xx[kMaxDim];
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) xx[a] = a < dim ? x[p * dim + a] : 0.0;
+  int idx[kMaxDim];
+  int rem = owner[p];
+#pragma unroll
+  for (int a = 0; a < kMaxDim; ++a) {
+    idx[a] = a < dim ? rem % C.g.nsub[a] : 0;
+    if (a < dim) rem /= C.g.nsub[a];
+  }
+  double acc[kMaxComp] = {0, 0, 0, 0};
+  int ncand = 1;
+  for (int a = 0; a < dim; ++a) ncand *= 3;
+  for (int k = 0; k < ncand; ++k) {
+    int kk = k, e = 0, stride = 1;
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < kMaxDim; ++a) {
+      if (a >= dim) continue;
+      const int ia = idx[a] + kk % 3 - 1;
+      kk /= 3;
+      if (ia < 0 || ia >= C.g.nsub[a]) ok = false;
+      e += ia * stride;
+      stride *= C.g.nsub[a];
+    }
+    if (!ok) continue;
+    const Pou P = pou_smooth(C.g, e, xx);
+    if (P.psi == 0.0) continue;
+    for (int c = 0; c < K; ++c) {
+      const int64_t fb = ((int64_t)e * K + c) * J;
+      double s = 0.0;
+      for (int j = lane; j < J; j += kWave) s += feat_t(C, fb + j, P.l) * u[fb + j];
+#pragma unroll
+      for (int q = 0; q < kMaxComp; ++q)
+        if (q == c) acc[q] += P.psi * s;
+    }
+  }
+  for (int c = 0; c < K; ++c) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) out[p * K + c] = v;
+  }
+}
+
 // Linear part and field values along u and du for the line search:
 //   ab[r] = {a_r, b_r, vu_0..vu_{K-1}, vd_0..vd_{K-1}, qu_0..qu_{nq-1}, qd_0..qd_{nq-1}}
 //   F_r(alpha) = a_r + alpha b_r + sum_poly coeff prod_c (vu_c + alpha vd_c)^p_c
@@ -704,9 +1085,10 @@ __global__ void __launch_bounds__(256) k_jmul(const TileDesc* __restrict__ tiles
   for (int rr = wv; rr < td.nrows; rr += kRowsPerBlock) {
     const T* row = Jv + td.val_off + (int64_t)rr * w;
     double acc = 0.0;
-    for (int p = lane; p < w; p += kWave) {
-      const int col = p < td.wA ? td.colA + p : td.colB + (p - td.wA);
-      acc += (double)row[p] * x[col];
+    for (int sg = 0; sg < td.nseg; ++sg) {
+      const T* rs = row + sg * td.wseg;
+      const double* xs = x + tiles[blockIdx.x].seg_col[sg];  // run-time index: read from memory
+      for (int p = lane; p < td.wseg; p += kWave) acc += (double)rs[p] * xs[p];
     }
     acc = wave_sum(acc);
     const int64_t r = td.row0 + rr;
@@ -772,7 +1154,7 @@ __global__ void k_jac_rows(const TileDesc* __restrict__ tiles, const int32_t* __
   __syncthreads();
   const double* row = Jv + td.val_off + (int64_t)(r - td.row0) * w;
   for (int p = threadIdx.x; p < w; p += blockDim.x) {
-    const int col = p < td.wA ? td.colA + p : td.colB + (p - td.wA);
+    const int col = td.seg_col[p / td.wseg] + p % td.wseg;
     o[col] = row[p];
   }
 }
@@ -797,6 +1179,12 @@ void launch_assemble(Problem& P, const double* u, double c) {
   ProfScope ps(P.prof, P.stream, "assemble", 0.0, 8.0 * ((double)P.nvals + 2.0 * P.m + P.n));
   RowsCtx C = make_ctx(P);
   dim3 grid((unsigned)((P.m + kRowsPerBlock - 1) / kRowsPerBlock));
+  if (P.geom.pou == RFM_POU_SMOOTH) {
+    hipLaunchKernelGGL(k_assemble_smooth, grid, dim3(256), 0, P.stream, C, P.d_tiles.p, P.d_rowtile.p, P.m, u, c,
+                       P.d_J.p, P.d_DF.p, P.d_D.p);
+    RFM_HIP(hipGetLastError());
+    return;
+  }
   switch (kper_of(P)) {
 #define RFM_CASE(KP)                                                                                    \
   case KP:                                                                                              \
@@ -816,7 +1204,11 @@ void launch_row_eval(Problem& P, const double* u, const double* du, double* out_
   ProfScope ps(P.prof, P.stream, "linesearch_products", 0.0, 8.0 * ((double)P.m * (2 + 2 * P.ncomp) + 2.0 * P.n));
   RowsCtx C = make_ctx(P);
   dim3 grid((unsigned)((P.m + kRowsPerBlock - 1) / kRowsPerBlock));
-  hipLaunchKernelGGL(k_row_eval<1>, grid, dim3(256), 0, P.stream, C, P.m, u, du, out_ab);
+  if (P.geom.pou == RFM_POU_SMOOTH)
+    hipLaunchKernelGGL(k_row_eval_smooth, grid, dim3(256), 0, P.stream, C, P.d_tiles.p, P.d_rowtile.p, P.m, u, du,
+                       out_ab);
+  else
+    hipLaunchKernelGGL(k_row_eval<1>, grid, dim3(256), 0, P.stream, C, P.m, u, du, out_ab);
   RFM_HIP(hipGetLastError());
 }
 
@@ -853,7 +1245,10 @@ void launch_eval_points(Problem& P, const double* u, int64_t npts, const double*
   if (npts == 0) return;
   RowsCtx C = make_ctx(P);
   dim3 grid((unsigned)((npts + kRowsPerBlock - 1) / kRowsPerBlock));
-  hipLaunchKernelGGL(k_eval_points, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
+  if (P.geom.pou == RFM_POU_SMOOTH)
+    hipLaunchKernelGGL(k_eval_points_smooth, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
+  else
+    hipLaunchKernelGGL(k_eval_points, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
   RFM_HIP(hipGetLastError());
 }
 

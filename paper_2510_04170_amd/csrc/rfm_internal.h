@@ -136,6 +136,7 @@ struct GeomDesc {
   int dim, ncomp, J, nbox;
   int nsub[kMaxDim];
   double lo[kMaxDim], hi[kMaxDim];
+  int pou;  // RFM_POU_INDICATOR or RFM_POU_SMOOTH
 };
 
 // one Jacobian row: which point, which box(es), which equation/component, which order
@@ -148,12 +149,16 @@ struct RowDesc {
 
 // consecutive rows with one column support: segment A (and B for continuity rows);
 // values are stored row-major, nrows x (wA + wB), starting at val_off
+constexpr int kMaxSeg = 8;  // column segments of a tile row (boxes touched by a smooth-partition row)
+
 struct TileDesc {
   int32_t row0, nrows;
-  int32_t colA, wA;
+  int32_t colA, wA;  // indicator partition: one or two segments; smooth partition: wA = row width
   int32_t colB, wB;
   int64_t val_off;
   int64_t part_off;  // start of this tile's slot in the J^T y partial buffer
+  int32_t nseg, wseg;         // segments of equal width: row value p is column seg_col[p / wseg] + p % wseg
+  int32_t seg_col[kMaxSeg];
 };
 
 // feature table, structure of arrays indexed by (e * ncomp + c) * J + j

@@ -40,6 +40,7 @@ void build_projection(Problem& P, const rfm_solve_opts& o) {
   int32_t nsub[kMaxDim];
   for (int a = 0; a < P.dim; ++a) nsub[a] = P.geom.nsub[a];
   check(rfm_set_partition(h, P.geom.lo, P.geom.hi, nsub));
+  check(rfm_set_partition_of_unity(h, P.geom.pou));
   check(rfm_set_features(h, P.J, P.W.data(), P.b.data()));
   for (const auto& g : P.groups) {
     if (g.kind != RFM_PDE || g.npts == 0) continue;

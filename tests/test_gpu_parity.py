@@ -78,6 +78,12 @@ CASES = {
     "ball_small": lambda: W.diffusion_reaction_ball(J=40, q=6, nbdy=600, test_per_dim=3),
     # Gray-Scott with solution-dependent diffusion: product terms in both components, J = 40
     "grayscott_nonlinear_small": lambda: W.gray_scott_nonlinear(nsub=(2, 1, 1), J=40, q=5, test_per_dim=3),
+    # the smooth partition of unity (rows touch up to 2^d boxes, no continuity rows): 2-D, J = 60
+    "poisson2d_smooth": lambda: W.config1(J=60, q=10, pou="b", test_per_dim=4),
+    # 3-D quasi-linear with the smooth partition and Neumann rows, J = 40
+    "quasilinear_smooth": lambda: _with_neumann(W.quasilinear(nsub=(2, 2, 1), J=40, q=6, pou="b", test_per_dim=3)),
+    # two components with the smooth partition, J = 30
+    "grayscott_smooth": lambda: W.config2(nsub=(2, 2, 1), J=30, q=4, pou="b", test_per_dim=3),
 }
 
 
@@ -725,4 +731,41 @@ def test_amipn_against_the_paper_gray_scott_table(qJ):
     assert e[0] < 3 * eu and e[1] < 3 * ev
     assert abs(st["outer_iters"] - it) <= 1
     assert 1 <= st["jac_evals"] <= nj + 1
+    lp.close()
+
+
+@pytest.mark.parametrize("method", ["ipn", "amipn"])
+def test_full_solve_smooth_partition(method):
+    """The 2-D workload with the smooth partition of unity (no continuity rows): the field against the
+    oracle's solve and u*."""
+    _announce(f"full solve smooth partition {method}")
+    prob = W.config1(J=200, q=20, pou="b", test_per_dim=10)
+    m = R.RFM_AMIPN if method == "amipn" else R.RFM_IPN
+    lp, ug, stg, rc, uo, sto = _solve_both(prob, m)
+    vg = lp.eval(ug, prob.test_x, prob.test_owner)
+    vo = O.eval_field(prob, uo, prob.test_x, prob.test_owner)
+    ex = prob.exact(prob.test_x)
+    print(f"smooth {method}: GPU IT {stg['outer_iters']} NJ {stg['jac_evals']} relL2 {_relerr(vg, ex):.3e}; "
+          f"oracle IT {sto.outer_iters} relL2 {_relerr(vo, ex):.3e}; fields {_relerr(vg, vo):.2e} apart")
+    assert rc in (R.RFM_OK, R.RFM_ESTALL)
+    assert _relerr(vg, vo) < 1e-6
+    assert _relerr(vg, ex) < 1e-6
+    lp.close()
+
+
+def test_smooth_partition_mixed_precision_solve():
+    """BF16 sketch and FP32 LSQR operator with the smooth partition reach the FP64 solve's field."""
+    _announce("smooth partition mixed precision")
+    prob = W.quasilinear(nsub=(2, 2, 2), J=150, q=10, pou="b", test_per_dim=3)
+    lp = R.from_description(prob)
+    o = dict(method=R.RFM_AMIPN, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5)
+    u1, st1, rc1 = lp.solve(None, R.default_opts(**o))
+    u2, st2, rc2 = lp.solve(None, R.default_opts(sketch_prec=R.RFM_PREC_BF16, lsqr_prec=R.RFM_PREC_F32, **o))
+    v1 = lp.eval(u1, prob.test_x, prob.test_owner)
+    v2 = lp.eval(u2, prob.test_x, prob.test_owner)
+    ex = prob.exact(prob.test_x)
+    print(f"smooth quasilinear: FP64 relL2 {_relerr(v1, ex):.3e}, mixed {_relerr(v2, ex):.3e}, "
+          f"fields {_relerr(v2, v1):.2e} apart")
+    assert rc1 in (R.RFM_OK, R.RFM_ESTALL) and rc2 in (R.RFM_OK, R.RFM_ESTALL)
+    assert _relerr(v2, v1) < 1e-6
     lp.close()
