@@ -931,6 +931,7 @@ class QrEngine {
     DR = Pp + 2 * (size_t)ncu * kPanel;
     part = DR + 4 * kPanel;
     W2 = part + tn;
+    part_cap = tn;
     int32_t zero3[3] = {0, 0, 0};
     RFM_HIP(hipMemcpyAsync(P.d_sync.p, zero3, sizeof(zero3), hipMemcpyHostToDevice, P.stream));
   }
@@ -978,6 +979,7 @@ class QrEngine {
   const int ncu;
   static constexpr int max_split = 16;
   double *Vw, *T64, *T128, *G128, *X128, *Y128, *T256, *G256, *X256, *Y256, *T512, *G64, *Pp, *DR, *part, *W2;
+  size_t part_cap = 0;  // doubles of split partials
 
   void zero_block(double* V, int64_t ldv, int c0, int ncols, int nrows) {
     const int64_t cnt = (int64_t)ncols * nrows;
@@ -995,16 +997,18 @@ class QrEngine {
   // split-row Gram V_a^T V_b of two w-wide (128 or 256) column blocks over K rows into G (w x w)
   void gram_wide(const double* Va, const double* Vbk, int64_t ldv, int K, int w, double* G) {
     int nsplit, krange;
-    tn_split(K, (w / kBig) * (w / kBig), ncu, max_split, &nsplit, &krange);
+    // up to 64 row splits: the Gram is short and wide, and 16 splits leave most CUs idle
+    tn_split(K, (w / kBig) * (w / kBig), ncu, 64, &nsplit, &krange);
     krange = (krange + kKC - 1) / kKC * kKC;
     nsplit = (K + krange - 1) / krange;
+    RFM_CHECK((size_t)nsplit * w * w <= part_cap, RFM_EINVAL, "QR: Gram partials exceed the workspace");
     hipLaunchKernelGGL((k_gemm_tn128<true, true>), dim3((w / kBig) * (w / kBig) * nsplit), dim3(256), 0, P.stream, Va,
                        ldv, Vbk, ldv, K, w, krange, part, w);
     hipLaunchKernelGGL(k_gsum, dim3((unsigned)((w * w + 255) / 256)), dim3(256), 0, P.stream, part, nsplit, w, G);
   }
   void gram_t(const double* V, int64_t ldv, int K, int nb, const double* tau, double* Tout) {
     int nsplit, krange;
-    tn_split(K, 1, std::max(1, ncu / 16), 64, &nsplit, &krange);
+    tn_split(K, 1, ncu, 256, &nsplit, &krange);
     hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit), dim3(256), 0, P.stream, V, ldv, V, ldv, K, nb, krange, part);
     hipLaunchKernelGGL(k_gsum64, dim3((unsigned)((nb * kPanel + 255) / 256)), dim3(256), 0, P.stream, part, nsplit,
                        nb, G64);
@@ -1068,7 +1072,7 @@ class QrEngine {
         // apply this block's reflectors to the rest of the 256 columns
         double* Cr = A + (c_sp + kPanel) * lda + c_sp;
         int nsplit, krange;
-        tn_split(Msp, (Nr + 63) / 64, ncu, 64, &nsplit, &krange);
+        tn_split(Msp, (Nr + 63) / 64, ncu, 256, &nsplit, &krange);
         hipLaunchKernelGGL(k_gemm_tn, dim3((unsigned)((Nr + 63) / 64), nsplit), dim3(256), 0, P.stream, Vsp, Mv, Cr,
                            lda, Msp, Nr, krange, part);
         hipLaunchKernelGGL(k_reduce_w, dim3((unsigned)((Nr + 3) / 4)), dim3(256), 0, P.stream, part, nsplit, Nr,
@@ -1083,7 +1087,7 @@ class QrEngine {
       int nsplit_ab = 1, krange;
       const int Kab = Mh - b * kPanel;
       if (nbs[b] > 0) {
-        tn_split(Kab, 1, ncu, 64, &nsplit_ab, &krange);
+        tn_split(Kab, 1, ncu, 256, &nsplit_ab, &krange);
         hipLaunchKernelGGL(k_gemm_tn, dim3(1, nsplit_ab), dim3(256), 0, P.stream, Vh + (int64_t)a * kPanel * Mv + b * kPanel,
                            Mv, Vh + (int64_t)b * kPanel * Mv + b * kPanel, Mv, Kab, nbs[b], krange, part);
         hipLaunchKernelGGL(k_gsum64, dim3((unsigned)((nbs[b] * kPanel + 255) / 256)), dim3(256), 0, P.stream, part,
