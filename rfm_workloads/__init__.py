@@ -558,6 +558,64 @@ def config4(nsub=(4, 4, 8), J=400, q=12, seed=0, R=1.0, n_t=96, n_theta=48, test
                   dirichlet_faces=faces, test_per_dim=test_per_dim, inside=inside, extra_groups=hole)
 
 
+def jet_ac_paper(x: np.ndarray) -> Jet:
+    """u* = 2 sin(x(1 - x)) sin(y(1 - y)) e^(t + 1) (time the last coordinate): value, gradient in
+    (x, y, t), Laplacian in (x, y, t) and in (x, y)."""
+    X, Y, T = x[:, 0], x[:, 1], x[:, 2]
+
+    def a(s):
+        w = s * (1.0 - s)
+        return np.sin(w), np.cos(w) * (1.0 - 2.0 * s), -np.sin(w) * (1.0 - 2.0 * s) ** 2 - 2.0 * np.cos(w)
+
+    ax, dax, d2ax = a(X)
+    ay, day, d2ay = a(Y)
+    et = 2.0 * np.exp(T + 1.0)
+    val = ax * ay * et
+    grad = np.stack([dax * ay * et, ax * day * et, val], 1)
+    lap_space = (d2ax * ay + ax * d2ay) * et
+    return val[:, None], grad[:, None, :], (lap_space + val)[:, None], lap_space[:, None]
+
+
+AC2_HOLE_R = 0.1
+
+
+def ac2_hole_centre(t):
+    t = np.asarray(t, float)
+    return np.stack([0.5 + 0.2 * np.cos(np.pi * t), 0.5 + 0.2 * np.sin(np.pi * t)], axis=-1)
+
+
+def allen_cahn_moving_hole(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, n_t=None, n_theta=None,
+                           test_per_dim=None) -> Problem:
+    """The paper's space-time Allen-Cahn problem on a domain with a moving hole (Sec. 5):
+    u_t - Lap u + u^3 - u = f on ([0,1]^2 minus a disc of radius 0.1 centred at
+    (0.5 + 0.2 cos(pi t), 0.5 + 0.2 sin(pi t))) x (0, 1], u* = 2 sin(x(1 - x)) sin(y(1 - y)) e^(t+1);
+    Dirichlet u* on the x, y faces, at t = 0 and on the hole's boundary (n_t cell-centred t levels x
+    n_theta angles, by default q per box along t and 4 q around)."""
+    lin = [(0, 0, 1.0, D_X2), (0, 0, -1.0, D_LAPLACE_SPACE), (0, 0, -1.0, D_ID)]
+    poly = [(0, 1.0, (3,))]
+    faces = [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0)]
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    n_t = n_t if n_t is not None else q * int(nsub[2])
+    n_theta = n_theta if n_theta is not None else 4 * q
+
+    def inside(p):
+        return np.linalg.norm(p[:, :2] - ac2_hole_centre(p[:, 2]), axis=1) > AC2_HOLE_R
+
+    def hole(lo_, hi_, nsub_, jet_fn):
+        t = (np.arange(n_t) + 0.5) / n_t
+        th = 2 * np.pi * np.arange(n_theta) / n_theta
+        tt, aa = np.meshgrid(t, th, indexing="ij")
+        tt, aa = tt.ravel(), aa.ravel()
+        x = np.concatenate([ac2_hole_centre(tt) + AC2_HOLE_R * np.stack([np.cos(aa), np.sin(aa)], 1), tt[:, None]],
+                           axis=1)
+        owner = box_of(x, lo_, hi_, nsub_)
+        return [PointGroup(KIND_DIRICHLET, x[owner == e], int(e), comp=-1, data=jet_fn(x[owner == e])[0])
+                for e in np.unique(owner)]
+
+    return _build("allen_cahn_moving_hole_paper", 3, 1, lo, hi, nsub, J, R, q, q, jet_ac_paper, lin, poly,
+                  seed=seed, dirichlet_faces=faces, test_per_dim=test_per_dim, inside=inside, extra_groups=hole)
+
+
 def make_config(i: int, **kw) -> Problem:
     return [config1, config2, config3_nohole, config4_nohole][i](**kw)
 
@@ -703,6 +761,8 @@ def gray_scott_nonlinear(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, F=GS2_F, k=
 def jet_of(problem: Problem):
     """Closed-form jet of the problem's manufactured solution."""
     name = problem.name
+    if name == "allen_cahn_moving_hole_paper":
+        return jet_ac_paper
     if name == "gray_scott_nonlinear_3d":
         return jet_gray_scott_nonlinear
     if name == "diffusion_reaction_ball":

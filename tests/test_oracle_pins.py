@@ -800,3 +800,24 @@ def test_smooth_pou_problem_by_manufactured_solution():
     u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
     assert st.status == "ok"
     assert np.all(O.rel_l2(prob, u) < 1e-6)
+
+
+def test_paper_allen_cahn_moving_hole_data_and_geometry():
+    """The paper's space-time Allen-Cahn problem with a moving hole (Sec. 5): data against central
+    differences of u* (u_t - Lap_xy u + u^3 - u), no collocation point inside the hole, the hole's
+    Dirichlet points on its moving circle, and the jet."""
+    prob = W.allen_cahn_moving_hole(J=4, q=8)
+    for g in prob.groups:
+        d = np.linalg.norm(g.x[:, :2] - W.ac2_hole_centre(g.x[:, 2]), axis=1)
+        if g.kind == W.KIND_DIRICHLET and np.allclose(d, W.AC2_HOLE_R, atol=1e-12):
+            np.testing.assert_allclose(g.data[:, 0], prob.exact(g.x)[:, 0], rtol=0, atol=1e-14)
+        else:
+            assert np.all(d > W.AC2_HOLE_R)
+    g = next(g for g in prob.groups if g.kind == W.KIND_PDE)
+    val, grad, sec = _fd_jet(prob.exact, g.x)
+    u = val[:, 0]
+    f = grad[:, 0, 2] - sec[:, 0, 0] - sec[:, 0, 1] + u ** 3 - u
+    assert np.abs(f - g.data[:, 0]).max() < 2e-5 * max(1.0, np.abs(g.data).max())
+    jv, jg, jl, jls = W.jet_ac_paper(g.x)
+    assert np.abs(jg - grad).max() < 1e-6
+    assert np.abs(jls[:, 0] - sec[:, 0, :2].sum(-1)).max() < 1e-4
