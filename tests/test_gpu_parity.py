@@ -769,3 +769,38 @@ def test_smooth_partition_mixed_precision_solve():
     assert rc1 in (R.RFM_OK, R.RFM_ESTALL) and rc2 in (R.RFM_OK, R.RFM_ESTALL)
     assert _relerr(v2, v1) < 1e-6
     lp.close()
+
+
+def _paper_allen_cahn_rows():
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_allen_cahn.txt")
+    rows = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            solver, q, J, it, nj, _s, err, _ux, _uy, _ut = line.split()
+            rows[(int(q), int(J))] = (int(it), int(nj), float(err))
+    return rows
+
+
+PAPER_AC = _paper_allen_cahn_rows()
+
+
+@pytest.mark.parametrize("qJ", sorted(PAPER_AC), ids=lambda qJ: f"q{qJ[0]}_J{qJ[1]}")
+def test_amipn_against_the_paper_allen_cahn_table(qJ):
+    """AMIPN on the paper's space-time Allen-Cahn problem with a moving hole ((2,2,2) space-time boxes,
+    q^3 points and J features per box; m_max = 5, eta = 1e-10, gamma = 2): the printed error within a
+    factor of 3 (another draw of the features and of the hole's boundary points), outer steps within 2
+    and Jacobians at most 1 more than printed."""
+    q, J = qJ
+    it, nj, err = PAPER_AC[qJ]
+    _announce(f"paper Allen-Cahn table q={q} J={J}")
+    prob = W.allen_cahn_moving_hole(J=J, q=q)
+    lp = R.from_description(prob)
+    u, st, rc = lp.solve(None, R.default_opts(method=R.RFM_AMIPN, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5))
+    e = _relerr(lp.eval(u, prob.test_x, prob.test_owner), prob.exact(prob.test_x))
+    print(f"q {q} J {J} amipn: IT {st['outer_iters']} NJ {st['jac_evals']} relL2 {e:.3e} ({st['t_total']:.2f} s; "
+          f"paper IT {it} NJ {nj} error {err:.2e})")
+    assert rc in (R.RFM_OK, R.RFM_ESTALL)
+    assert e < 3 * err
+    assert abs(st["outer_iters"] - it) <= 2
+    assert 1 <= st["jac_evals"] <= nj + 1
+    lp.close()
