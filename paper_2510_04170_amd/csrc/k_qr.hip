@@ -3,14 +3,16 @@
 // the trailing columns as it is built and then dropped.
 //
 // Blocked right-looking algorithm with panels of ib <= 64 columns:
-//  1. k_panel: one cooperative launch factors the panel column by column.  Each
+//  1. k_panel_df: one cooperative launch factors the panel column by column.  Each
 //     workgroup keeps a contiguous chunk of the panel's rows in registers
 //     (thread (rg, c) holds rows rg, rg+8, ... of column c).  Per column the
 //     per-workgroup partial sums (sigma = ||x||^2 below the diagonal and
-//     g_c = x^T a_c) are published at a grid barrier and reduced in a fixed
-//     order; every workgroup then applies the reflector to its rows.  The reflector
-//     follows the usual convention H = I - tau v v^T, v_0 = 1,
-//     beta = -sign(alpha) ||(alpha, x)||.
+//     g_c = x^T a_c) are published in write-once slots, one owner workgroup per
+//     column reduces them in a fixed order and publishes the total, and every
+//     workgroup then applies the reflector to its rows (no grid barrier: readers
+//     poll the slots; k_panel, with barriers, remains for panels with fewer rows
+//     than columns).  The reflector follows the usual convention
+//     H = I - tau v v^T, v_0 = 1, beta = -sign(alpha) ||(alpha, x)||.
 //  2. The Gram V^T V (k_gemm_tn) and the compact-WY factor T (k_build_t), with
 //     H_1 ... H_ib = I - V T V^T (Schreiber and Van Loan, 1989).
 //  3. Inside a 256-column block, each 64-column block updates the rest of the
@@ -242,6 +244,147 @@ __global__ void __launch_bounds__(512) k_panel(double* __restrict__ A, int64_t l
     __syncthreads();
   }
   // write back and emit the explicit V
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    if (i < nrow) {
+      const int pr = r0 + rg + NRG * i;
+      if (c < nb) A[(int64_t)c * ld + pr] = a[i];
+      double v = 0.0;
+      if (c < nb) v = pr > c ? a[i] : (pr == c ? 1.0 : 0.0);
+      Vb[(int64_t)c * ldv + pr] = v;
+    }
+  }
+}
+
+// Slots of the dataflow panel start every launch holding kEmpty, a signalling-NaN pattern: IEEE
+// arithmetic only ever returns quiet NaNs, and every value published below is an arithmetic result
+// (the diagonal row is canonicalised first), so a slot that differs from kEmpty holds its value.
+constexpr unsigned long long kEmpty = 0xFFF4A5A5A5A5A5A5ull;
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// the value of a published slot, polled until it is there (bounded: a time-out raises the error flag,
+// and a raised flag ends every wait)
+__device__ __forceinline__ double wait_slot(const double* p, int32_t* sync) {
+  double v = ld_dev(p);
+  int spins = 0;
+  while ((unsigned long long)__double_as_longlong(v) == kEmpty) {
+    __builtin_amdgcn_s_sleep(1);
+    if ((++spins & 1023) == 0 &&
+        __hip_atomic_load(&sync[kSyncError], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      break;
+    if (spins > kSpinLimit) {
+      __hip_atomic_store(&sync[kSyncError], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    v = ld_dev(p);
+  }
+  return v;
+}
+
+// Panel factorisation with the same arithmetic per column as k_panel and no grid barrier: every value
+// that crosses workgroups sits in a slot of its own, written once per launch, and the readers poll it.
+// Per column j: workgroup g publishes its partial sums x^T a_c (c >= j) in P[j][g][c] and, if it holds
+// row j, the diagonal row in DR[j][c]; workgroup (c - j) mod G owns column c and sums the G partials
+// of it in a fixed order into TOT[j][c]; every workgroup then reads TOT[j][c] and DR[j][c] and applies
+// the reflector.  A reader depends only on writes that every workgroup makes before its first wait in
+// the column, so all-resident workgroups cannot deadlock.  P: [64][G][64], DR: [64][64], TOT: [64][64],
+// all kEmpty at launch.  Requires M >= nb (some workgroup holds every diagonal row).
+template <int RPT>
+__global__ void __launch_bounds__(512) k_panel_df(double* __restrict__ A, int64_t ld, int M, int nb, int chunk,
+                                                  double* __restrict__ tau, double* __restrict__ P,
+                                                  double* __restrict__ DR, double* __restrict__ TOT,
+                                                  double* __restrict__ Vb, int64_t ldv, int32_t* __restrict__ sync) {
+  constexpr int NRG = 8;
+  __shared__ double red[NRG][kPanel];
+  __shared__ double ored[NRG];
+  __shared__ double tot_sh[kPanel], dr_sh[kPanel];
+  __shared__ double scal_sh[3];
+  const int G = gridDim.x, g = blockIdx.x;
+  const int c = threadIdx.x % kPanel, rg = __builtin_amdgcn_readfirstlane(threadIdx.x / kPanel);  // uniform
+  const int r0 = g * chunk;
+  const int rend = min(M, r0 + chunk);
+  const int nrow = max(0, min(RPT, (rend - r0 - rg + NRG - 1) / NRG));
+  double a[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) a[i] = (c < nb && i < nrow) ? A[(int64_t)c * ld + r0 + rg + NRG * i] : 0.0;
+
+  for (int j = 0; j < nb; ++j) {
+    const int dj = j - r0 - rg;
+    const int ilo = dj < 0 ? 0 : dj / NRG + 1;
+    const int idiag = (dj >= 0 && dj % NRG == 0 && dj / NRG < nrow) ? dj / NRG : -1;
+    if (idiag >= 0 && c >= j && c < nb) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        if (i == idiag) st_dev(&DR[j * kPanel + c], __builtin_canonicalize(a[i]));
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (i >= ilo) part += bcast_lane(a[i], j) * a[i];
+    red[rg][c] = part;
+    __syncthreads();
+    if (rg == 0 && c >= j && c < nb)
+      st_dev(&P[((size_t)j * G + g) * kPanel + c], ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) +
+                                                       ((red[4][c] + red[5][c]) + (red[6][c] + red[7][c])));
+    // the columns this workgroup owns: partials of workgroups 0 .. G-1 in thread order
+    for (int cc = g; cc < nb - j; cc += G) {
+      const int col = j + cc;
+      double v = (int)threadIdx.x < G ? wait_slot(&P[((size_t)j * G + threadIdx.x) * kPanel + col], sync) : 0.0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if ((threadIdx.x & 63) == 0) ored[threadIdx.x >> 6] = v;
+      __syncthreads();
+      if (threadIdx.x == 0)
+        st_dev(&TOT[j * kPanel + col], ((ored[0] + ored[1]) + (ored[2] + ored[3])) + ((ored[4] + ored[5]) + (ored[6] + ored[7])));
+      __syncthreads();
+    }
+    if (rg == 0 && c >= j && c < nb) {
+      tot_sh[c] = wait_slot(&TOT[j * kPanel + c], sync);
+      dr_sh[c] = wait_slot(&DR[j * kPanel + c], sync);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double sigma = tot_sh[j];
+      const double alpha = dr_sh[j];
+      double beta, t, sc;
+      if (sigma == 0.0) {
+        beta = alpha;
+        t = 0.0;
+        sc = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+        t = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+      }
+      scal_sh[0] = beta;
+      scal_sh[1] = t;
+      scal_sh[2] = sc;
+      if (g == 0) tau[j] = t;
+    }
+    __syncthreads();
+    const double beta = scal_sh[0], t = scal_sh[1], sc = scal_sh[2];
+    const double gc = (c >= j && c < nb) ? tot_sh[c] : 0.0;
+    const double ajc = (c >= j && c < nb) ? dr_sh[c] : 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) asm volatile("" : "+v"(a[i]));
+    const double tw = t * (ajc + gc * sc);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      if (i >= ilo) {
+        const double v = bcast_lane(a[i], j) * sc;
+        if (c == j) a[i] = v;
+        else if (c > j) a[i] -= tw * v;
+      } else if (i == idiag) {
+        if (c == j) a[i] = beta;
+        else if (c > j) a[i] -= tw;
+      }
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     if (i < nrow) {
@@ -863,8 +1006,23 @@ template <int RPT>
 void launch_panel_t(Problem& P, dim3 grid, double* A, int64_t ld, int M, int nb, int chunk, double* tau, double* Pp,
                     double* DR, double* Vb, int64_t ldv) {
   int32_t* sync = P.d_sync.p;
-  void* args[] = {&A, &ld, &M, &nb, &chunk, &tau, &Pp, &DR, &Vb, &ldv, &sync};
-  const void* fn = reinterpret_cast<const void*>(&k_panel<RPT, kPanelOneBarrier>);
+  const void* fn;
+  if (M >= nb) {
+    // dataflow form: P [64][G][64], then DR [64][64] and TOT [64][64], all set to kEmpty
+    const int64_t cnt = (int64_t)kPanel * grid.x * kPanel;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, P.stream,
+                       reinterpret_cast<unsigned long long*>(Pp), cnt, kEmpty);
+    hipLaunchKernelGGL(k_fill_u64, dim3(2 * kPanel * kPanel / 256), dim3(256), 0, P.stream,
+                       reinterpret_cast<unsigned long long*>(DR), (int64_t)2 * kPanel * kPanel, kEmpty);
+    fn = reinterpret_cast<const void*>(&k_panel_df<RPT>);
+  } else {
+    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(256), 0, P.stream, P.d_sync.p);
+    fn = reinterpret_cast<const void*>(&k_panel<RPT, kPanelOneBarrier>);
+  }
+  double* TOT = DR + kPanel * kPanel;
+  void* args_df[] = {&A, &ld, &M, &nb, &chunk, &tau, &Pp, &DR, &TOT, &Vb, &ldv, &sync};
+  void* args_bar[] = {&A, &ld, &M, &nb, &chunk, &tau, &Pp, &DR, &Vb, &ldv, &sync};
+  void** args = M >= nb ? args_df : args_bar;
   int maxb = 0;
   RFM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxb, fn, 512, 0));
   RFM_CHECK((int64_t)maxb * num_cus(P.device) >= (int64_t)grid.x, RFM_EDEVICE,
@@ -878,7 +1036,6 @@ void launch_panel(Problem& P, double* A, int64_t ld, int M, int nb, double* tau,
   int G = std::max(1, std::min(std::min(ncu, 256), (M + 63) / 64));
   int chunk = (M + G - 1) / G;
   const int need = (chunk + 7) / 8;
-  hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(256), 0, P.stream, P.d_sync.p);
   ProfScope ps(P.prof, P.stream, "qr_panel", 4.0 * M * (double)nb * nb, 16.0 * M * (double)nb);
   dim3 grid(G);
   if (need <= 8) launch_panel_t<8>(P, grid, A, ld, M, nb, chunk, tau, Pp, DR, Vb, ldv);
@@ -913,7 +1070,7 @@ class QrEngine {
     const size_t vb = (size_t)(Mmax + 1) * kWide;  // V of a 512-column outer panel, leading dimension M rounded up to even
     const size_t tn = (size_t)max_split * std::max<int64_t>(nmax, kWide) * kWide;
     const size_t small = 5 * kPanel * kPanel + 5 * kBig * kBig + 5 * kOuter * kOuter + kWide * kWide;
-    const size_t need = vb + small + 2 * (size_t)ncu * kPanel + 4 * kPanel + tn + (size_t)nmax * kWide + 256;
+    const size_t need = vb + small + (size_t)kPanel * ncu * kPanel + 2 * kPanel * kPanel + tn + (size_t)nmax * kWide + 256;
     P.d_ws.resize(need);
     Vw = P.d_ws.p;
     T64 = Vw + vb;                     // 4 blocks of 64 x 64
@@ -928,8 +1085,8 @@ class QrEngine {
     T512 = Y256 + kOuter * kOuter;
     G64 = T512 + kWide * kWide;        // summed 64-wide Gram blocks
     Pp = G64 + kPanel * kPanel;
-    DR = Pp + 2 * (size_t)ncu * kPanel;
-    part = DR + 4 * kPanel;
+    DR = Pp + (size_t)kPanel * ncu * kPanel;  // panel partials [64][G][64] (G <= ncu)
+    part = DR + 2 * kPanel * kPanel;         // panel diagonal rows and column totals
     W2 = part + tn;
     part_cap = tn;
     int32_t zero3[3] = {0, 0, 0};
