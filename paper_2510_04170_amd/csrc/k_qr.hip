@@ -560,19 +560,28 @@ __global__ void __launch_bounds__(256) k_gemm_nn(double* __restrict__ C, int64_t
 // the XCD-aware workgroup order are in mfma_f64.h.
 // ---------------------------------------------------------------------------
 
-// C[M x N] += A[M x K] B, A column-major (lda even, 16-byte aligned), B[k][n] = Bt[n * ldb + k] (ldb even,
-// aligned); K a multiple of 16.  Loaders: A as row pairs (m = 2 (tid % 64), k = tid / 64 + 4 i), B as k pairs
-// (k = 2 (tid % 8), n = tid / 8 + 32 i); tiles wholly inside M x N take unguarded 16-byte loads.
+// C[M x N] += A[M x K] B, A column-major (lda even, base 16-byte aligned, lda >= M), B k-major
+// (B[k][n] = Bk[k * ldbk + n], ldbk even, base aligned, ldbk >= N); K a multiple of 32.
+// Operands move from global memory straight into LDS (global_load_lds_dwordx4): per 16-deep chunk each
+// wavefront issues 4 k-rows of A and 4 of B, one 16-byte piece per lane, into tiles with rows of 130
+// doubles; two tile pairs in separate LDS arrays, so the reads of one are not made to wait for the
+// loads into the other, and one barrier per chunk.  Rows past M and columns past N load clamped
+// (in-bounds) addresses and are never stored.
 // 1-D grid over the tiles: each XCD takes a contiguous range of the tiles ordered in groups of 4 row
 // tiles (row tile fastest), so the 4 x 4 tiles it runs at a time share 4 tiles of A and 4 of B in its L2
 // (against a fresh A tile per workgroup in row-major launch order; 8% faster at K = 512).
+typedef __attribute__((address_space(3))) void* lds_ptr;
+constexpr int kLdsRow = kBig + 2;  // 16-byte aligned rows
+
 __global__ void __launch_bounds__(256, 2) k_gemm_nn128(double* __restrict__ C, int64_t ldc,
                                                       const double* __restrict__ A, int64_t lda,
-                                                      const double* __restrict__ Bt, int64_t ldb, int M, int N,
+                                                      const double* __restrict__ Bk, int64_t ldbk, int M, int N,
                                                       int K) {
-  __shared__ double As[2][kKC][kBig + 1];
-  __shared__ double Bs[2][kKC][kBig + 1];
-  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  __shared__ __attribute__((aligned(16))) double As0[kKC][kLdsRow];
+  __shared__ __attribute__((aligned(16))) double Bs0[kKC][kLdsRow];
+  __shared__ __attribute__((aligned(16))) double As1[kKC][kLdsRow];
+  __shared__ __attribute__((aligned(16))) double Bs1[kKC][kLdsRow];
+  const int tid = threadIdx.x, lane = tid % 64, wv = __builtin_amdgcn_readfirstlane(tid / 64);
   const int wr = wv / 2, wc = wv % 2;
   int r0, n0;
   {
@@ -584,55 +593,32 @@ __global__ void __launch_bounds__(256, 2) k_gemm_nn128(double* __restrict__ C, i
     r0 = (gi * kGroup + gl % gh) * kBig;
     n0 = (gl / gh) * kBig;
   }
-  const bool full = (r0 + kBig <= M) && (n0 + kBig <= N);
   double acc[4][16];
 #pragma unroll
   for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
     for (int cg = 0; cg < 16; ++cg) acc[rg][cg] = 0.0;
-  const int am = 2 * (tid % 64), ak = tid / 64;
-  const int bk = 2 * (tid % 8), bn = tid / 8;
-  v2d ra[4], rb[4];
-  auto load = [&](int k0) {
-    if (full) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ra[i] = *reinterpret_cast<const v2d*>(A + (int64_t)(k0 + ak + 4 * i) * lda + r0 + am);
-        rb[i] = *reinterpret_cast<const v2d*>(Bt + (int64_t)(n0 + bn + 32 * i) * ldb + k0 + bk);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double* ap = A + (int64_t)(k0 + ak + 4 * i) * lda + r0 + am;
-        ra[i].x = (r0 + am < M) ? ap[0] : 0.0;
-        ra[i].y = (r0 + am + 1 < M) ? ap[1] : 0.0;
-        const int n = n0 + bn + 32 * i;
-        const double* bp = Bt + (int64_t)n * ldb + k0 + bk;
-        rb[i].x = (n < N) ? bp[0] : 0.0;
-        rb[i].y = (n < N) ? bp[1] : 0.0;
-      }
-    }
-  };
-  auto stash = [&](int buf) {
+  const int64_t ra = min<int64_t>(r0 + 2 * lane, lda - 2);
+  const int64_t nbk = min<int64_t>(n0 + 2 * lane, ldbk - 2);
+  auto issue = [&](int k0, double (*Xs)[kLdsRow], double (*Ys)[kLdsRow]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      As[buf][ak + 4 * i][am] = ra[i].x;
-      As[buf][ak + 4 * i][am + 1] = ra[i].y;
-      Bs[buf][bk][bn + 32 * i] = rb[i].x;
-      Bs[buf][bk + 1][bn + 32 * i] = rb[i].y;
+      const int kk = wv * 4 + i;
+      __builtin_amdgcn_global_load_lds((const void*)(A + (int64_t)(k0 + kk) * lda + ra), (lds_ptr)&Xs[kk][0], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(Bk + (int64_t)(k0 + kk) * ldbk + nbk), (lds_ptr)&Ys[kk][0], 16, 0,
+                                       0);
     }
   };
-  load(0);
-  stash(0);
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += kKC) {
-    const bool more = k0 + kKC < K;
-    if (more) load(k0 + kKC);
-    mfma4_chunk(As[buf], Bs[buf], lane, wr, wc, acc);
-    if (more) stash(buf ^ 1);
+  issue(0, As0, Bs0);
+  for (int k0 = 0; k0 < K; k0 += 2 * kKC) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wavefront's pieces of the chunk have landed
+    __syncthreads();                // everyone's have, and nobody still reads the other pair
+    issue(k0 + kKC, As1, Bs1);
+    mfma4_chunk(As0, Bs0, lane, wr, wc, acc);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    buf ^= 1;
+    if (k0 + 2 * kKC < K) issue(k0 + 2 * kKC, As0, Bs0);
+    mfma4_chunk(As1, Bs1, lane, wr, wc, acc);
   }
   const int row_l = lane % 16, col_l = lane / 16;
 #pragma unroll
@@ -653,18 +639,59 @@ __global__ void __launch_bounds__(256, 2) k_gemm_nn128(double* __restrict__ C, i
   }
 }
 
+// Tiles of 128 (p or n) x 16 (k) for the TN product, staged as 16-byte pairs (k, k + 1): the pair of
+// k-pair c of index p sits in slot p * 8 + (c ^ ((p / 2) % 8)).  Loading a column's 16 k is then one
+// contiguous 128-byte piece spread over its 8 slots, and the 16 lanes of a wavefront that read one k of
+// 16 consecutive p hit distinct LDS banks.
+__device__ __forceinline__ int pair_slot(int p, int c) { return p * 8 + (c ^ ((p / 2) % 8)); }
+
+// One 16-deep k-chunk on pair tiles Xp (output rows p) and Yp (output columns n); the same products, in
+// the same order, as mfma4_chunk on plain tiles.
+__device__ __forceinline__ void mfma4_chunk_pairs(const double* Xp, const double* Yp, int lane, int wr, int wc,
+                                                  double (&acc)[4][16]) {
+  const int h = lane / 32, odd = (lane / 16) % 2;  // k = 4 ks + lane / 16: pair 2 ks + h, element odd
+  const int m = (lane % 16) / 2;
+#pragma unroll
+  for (int ks = 0; ks < kKC / 4; ++ks) {
+    const int xoff = (lane % 16) * 16 + 2 * ((2 * ks) ^ (h ^ m)) + odd;
+    double x[4];
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) x[rg] = Xp[(wr * 64 + rg * 16) * 16 + xoff];
+    const int yl = (lane % 4) * 16 + 2 * (h ^ ((lane % 4) / 2)) + odd;
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      double y[8];
+#pragma unroll
+      for (int cg = 0; cg < 8; ++cg) {
+        const int cq = hh * 8 + cg;
+        y[cg] = Yp[(wc * 64 + cq * 4) * 16 + 4 * (ks ^ (cq % 4)) + yl];
+      }
+#pragma unroll
+      for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+        for (int cg = 0; cg < 8; ++cg)
+          acc[rg][hh * 8 + cg] = __builtin_amdgcn_mfma_f64_4x4x4f64(y[cg], x[rg], acc[rg][hh * 8 + cg], 0, 0, 0);
+    }
+  }
+}
+
 // part[split][n][p] = sum_{k in split} A[k][p] B[k][n]; A: K x pstride (lda), B: K x N (ldb), both
 // column-major; rows of a split: [split * krange, ...), krange a multiple of 16.  Grid: 1-D,
-// (pstride / 128 halves) x (column tiles) x (row splits) workgroups.  VEC: lda, ldb even and both bases 16-byte aligned,
-// so k pairs load as 16 bytes.  GRAM only tells the Gram products of the T merges apart from the
-// trailing updates in a profile (same code).
+// (pstride / 128 halves) x (column tiles) x (row splits) workgroups.  Whole 16-row chunks move from
+// global memory straight into the pair tiles (global_load_lds_dwordx4, one 16-byte pair per lane,
+// columns past N clamped to N - 1 and never stored); a split's last, partial chunk, and every chunk
+// when VEC is false, go through registers with guarded loads.  VEC: lda, ldb even and both bases 16-byte
+// aligned.  GRAM only tells the Gram products of the T merges apart from the trailing updates in a
+// profile (same code).
 template <bool VEC, bool GRAM = false>
 __global__ void __launch_bounds__(256, 2) k_gemm_tn128(const double* __restrict__ A, int64_t lda,
                                                      const double* __restrict__ B, int64_t ldb, int K, int N,
                                                      int krange, double* __restrict__ part, int pstride) {
-  __shared__ double As[2][kKC][kBig + 1];
-  __shared__ double Bs[2][kKC][kBig + 1];
-  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  __shared__ __attribute__((aligned(16))) double Xp0[kBig * kKC];
+  __shared__ __attribute__((aligned(16))) double Yp0[kBig * kKC];
+  __shared__ __attribute__((aligned(16))) double Xp1[kBig * kKC];
+  __shared__ __attribute__((aligned(16))) double Yp1[kBig * kKC];
+  const int tid = threadIdx.x, lane = tid % 64, wv = __builtin_amdgcn_readfirstlane(tid / 64);
   const int wr = wv / 2, wc = wv % 2;
   // 1-D grid of halves x column tiles x splits: on each XCD the halves of one (column tile, split)
   // run next to each other and share that C tile in its L2
@@ -675,58 +702,66 @@ __global__ void __launch_bounds__(256, 2) k_gemm_tn128(const double* __restrict_
   const int split = L / halves / ntile;
   A += (int64_t)half * kBig * lda;
   const int kb = split * krange, ke = min(K, kb + krange);
-  const bool ncols_full = n0 + kBig <= N;
   double acc[4][16];
 #pragma unroll
   for (int rg = 0; rg < 4; ++rg)
 #pragma unroll
     for (int cg = 0; cg < 16; ++cg) acc[rg][cg] = 0.0;
-  const int lk = 2 * (tid % 8), lc = tid / 8;  // k pair lk, lk + 1; column lc + 32 i
-  v2d ra[4], rb[4];
-  auto load = [&](int k0) {
-    const int k = k0 + lk;
-    if (VEC && ncols_full && k0 + kKC <= ke) {
+  // direct loads: instruction b of a tile covers indices 8 b .. 8 b + 7, lane l index 8 b + l / 8, slot
+  // l % 8; per-lane byte offsets from the tile's first column at the chunk's first row (32-bit: the host
+  // keeps 128 ld 8 < 2^32)
+  uint32_t ao[4], bo[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int c = lc + 32 * i;
-        ra[i] = *reinterpret_cast<const v2d*>(A + (int64_t)c * lda + k);
-        rb[i] = *reinterpret_cast<const v2d*>(B + (int64_t)(n0 + c) * ldb + k);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int c = lc + 32 * i;
-        const bool cv = n0 + c < N;
-        ra[i].x = k < ke ? A[(int64_t)c * lda + k] : 0.0;
-        ra[i].y = k + 1 < ke ? A[(int64_t)c * lda + k + 1] : 0.0;
-        rb[i].x = (k < ke && cv) ? B[(int64_t)(n0 + c) * ldb + k] : 0.0;
-        rb[i].y = (k + 1 < ke && cv) ? B[(int64_t)(n0 + c) * ldb + k + 1] : 0.0;
-      }
-    }
-  };
-  auto stash = [&](int buf) {
+  for (int i = 0; i < 4; ++i) {
+    const int p = (wv * 4 + i) * 8 + lane / 8;
+    const int c = (lane % 8) ^ ((p / 2) % 8);
+    ao[i] = (uint32_t)(((int64_t)p * lda + 2 * c) * 8);
+    bo[i] = (uint32_t)(((int64_t)min(p, N - 1 - n0) * ldb + 2 * c) * 8);  // relative to column n0
+  }
+  auto issue = [&](int k0, double* Xs, double* Ys) {
+    const char* ab = reinterpret_cast<const char*>(A + k0);
+    const char* bb = reinterpret_cast<const char*>(B + (int64_t)n0 * ldb + k0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int c = lc + 32 * i;
-      As[buf][lk][c] = ra[i].x;
-      As[buf][lk + 1][c] = ra[i].y;
-      Bs[buf][lk][c] = rb[i].x;
-      Bs[buf][lk + 1][c] = rb[i].y;
+      const int blk = wv * 4 + i;
+      __builtin_amdgcn_global_load_lds((const void*)(ab + ao[i]), (lds_ptr)(Xs + blk * 128), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(bb + bo[i]), (lds_ptr)(Ys + blk * 128), 16, 0, 0);
     }
   };
-  if (kb < ke) {
-    load(kb);
-    stash(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = kb; k0 < ke; k0 += kKC) {
-    const bool more = k0 + kKC < ke;
-    if (more) load(k0 + kKC);
-    mfma4_chunk(As[buf], Bs[buf], lane, wr, wc, acc);
-    if (more) stash(buf ^ 1);
+  // whole chunks by direct loads, two tile pairs, one barrier per chunk
+  const int nfull = VEC && ke > kb ? (ke - kb) / kKC : 0;
+  if (nfull > 0) issue(kb, Xp0, Yp0);
+  for (int ch = 0; ch < nfull; ch += 2) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wavefront's pieces of the chunk have landed
+    __syncthreads();                // everyone's have, and nobody still reads the other pair
+    if (ch + 1 < nfull) issue(kb + (ch + 1) * kKC, Xp1, Yp1);
+    mfma4_chunk_pairs(Xp0, Yp0, lane, wr, wc, acc);
+    if (ch + 1 >= nfull) break;
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    buf ^= 1;
+    if (ch + 2 < nfull) issue(kb + (ch + 2) * kKC, Xp0, Yp0);
+    mfma4_chunk_pairs(Xp1, Yp1, lane, wr, wc, acc);
+  }
+  // the rest (a split's partial last chunk; every chunk when VEC is false) through registers with
+  // guarded loads: thread t fills slots t + 256 i of both tiles
+  for (int k0 = kb + nfull * kKC; k0 < ke; k0 += kKC) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int sl = tid + 256 * i;
+      const int p = sl / 8;
+      const int c = (sl % 8) ^ ((p / 2) % 8);
+      const int k = k0 + 2 * c;
+      const bool nv = n0 + p < N;
+      const double* ap = A + (int64_t)p * lda + k;
+      const double* bp = B + (int64_t)(n0 + p) * ldb + k;
+      Xp0[2 * sl] = k < ke ? ap[0] : 0.0;
+      Xp0[2 * sl + 1] = k + 1 < ke ? ap[1] : 0.0;
+      Yp0[2 * sl] = (nv && k < ke) ? bp[0] : 0.0;
+      Yp0[2 * sl + 1] = (nv && k + 1 < ke) ? bp[1] : 0.0;
+    }
+    __syncthreads();
+    mfma4_chunk_pairs(Xp0, Yp0, lane, wr, wc, acc);
   }
   double* o = part + (size_t)split * N * pstride + (size_t)half * kBig;
   const int row_l = lane % 16, col_l = lane / 16;
@@ -867,11 +902,13 @@ __global__ void k_assemble_t(const double* __restrict__ T1, const double* __rest
   T[e] = v;
 }
 
-// W2[n][p] = -sum_{q <= p} T[q][p] W[n][q] for WID (256 or 512) reflectors, W = sum over splits
-// (pstride WID); one thread per p, 8 columns per block
+// W2[p][n] = W2k[p * ldw + n] = -sum_{q <= p} T[q][p] W[n][q] for WID (256 or 512) reflectors, W = sum
+// over splits (pstride WID); one thread per p, 8 columns per block.  W2 is k-major for the product
+// C += V W2 (its rows are the k-rows that product loads).
 template <int WID>
 __global__ void __launch_bounds__(WID) k_reduce_wide(const double* __restrict__ part, int nsplit, int N,
-                                                     const double* __restrict__ T, double* __restrict__ W2) {
+                                                     const double* __restrict__ T, double* __restrict__ W2,
+                                                     int64_t ldw) {
   __shared__ double Wsh[8][WID];
   const int p = threadIdx.x;
   const int n0 = blockIdx.x * 8;
@@ -891,7 +928,7 @@ __global__ void __launch_bounds__(WID) k_reduce_wide(const double* __restrict__ 
   }
 #pragma unroll
   for (int c = 0; c < 8; ++c)
-    if (n0 + c < N) W2[(int64_t)(n0 + c) * WID + p] = -v[c];
+    if (n0 + c < N) W2[(int64_t)p * ldw + n0 + c] = -v[c];
 }
 
 // R (upper n x n of B) into tiled storage: tile (bi, bj), bi <= bj, at
@@ -1070,7 +1107,7 @@ class QrEngine {
     const size_t vb = (size_t)(Mmax + 1) * kWide;  // V of a 512-column outer panel, leading dimension M rounded up to even
     const size_t tn = (size_t)max_split * std::max<int64_t>(nmax, kWide) * kWide;
     const size_t small = 5 * kPanel * kPanel + 5 * kBig * kBig + 5 * kOuter * kOuter + kWide * kWide;
-    const size_t need = vb + small + (size_t)kPanel * ncu * kPanel + 2 * kPanel * kPanel + tn + (size_t)nmax * kWide + 256;
+    const size_t need = vb + small + (size_t)kPanel * ncu * kPanel + 2 * kPanel * kPanel + tn + (size_t)(nmax + 1) * kWide + 256;
     P.d_ws.resize(need);
     Vw = P.d_ws.p;
     T64 = Vw + vb;                     // 4 blocks of 64 x 64
@@ -1159,6 +1196,7 @@ class QrEngine {
     krange = (krange + kKC - 1) / kKC * kKC;
     nsplit = (K + krange - 1) / krange;
     RFM_CHECK((size_t)nsplit * w * w <= part_cap, RFM_EINVAL, "QR: Gram partials exceed the workspace");
+    RFM_CHECK((int64_t)kBig * ldv * 8 < (int64_t(1) << 32), RFM_EINVAL, "QR: sketch too tall for 32-bit tile offsets");
     hipLaunchKernelGGL((k_gemm_tn128<true, true>), dim3((w / kBig) * (w / kBig) * nsplit), dim3(256), 0, P.stream, Va,
                        ldv, Vbk, ldv, K, w, krange, part, w);
     hipLaunchKernelGGL(k_gsum, dim3((unsigned)((w * w + 255) / 256)), dim3(256), 0, P.stream, part, nsplit, w, G);
@@ -1185,6 +1223,8 @@ class QrEngine {
                    8.0 * (2.0 * M * N + (double)M * K + (double)nsplit * N * K));
       // 16-byte loads of C need an even leading dimension and an aligned first column
       const bool vec = (ldc % 2 == 0) && (reinterpret_cast<uintptr_t>(Cp) % 16 == 0);
+      RFM_CHECK((int64_t)kBig * std::max<int64_t>(Mv, ldc) * 8 < (int64_t(1) << 32), RFM_EINVAL,
+                "QR: sketch too tall for 32-bit tile offsets");
       if (vec)
         hipLaunchKernelGGL(k_gemm_tn128<true>, dim3(halves * ntile * nsplit), dim3(256), 0, P.stream, V, Mv, Cp, ldc,
                            M, (int)N, krange, part, K);
@@ -1192,17 +1232,21 @@ class QrEngine {
         hipLaunchKernelGGL(k_gemm_tn128<false>, dim3(halves * ntile * nsplit), dim3(256), 0, P.stream, V, Mv, Cp, ldc,
                            M, (int)N, krange, part, K);
     }
+    const int64_t ldw = (N + 1) & ~(int64_t)1;  // even, so that column pairs load as 16 bytes
     if (K == kWide)
       hipLaunchKernelGGL(k_reduce_wide<kWide>, dim3((unsigned)((N + 7) / 8)), dim3(kWide), 0, P.stream, part, nsplit,
-                         (int)N, T, W2);
+                         (int)N, T, W2, ldw);
     else
       hipLaunchKernelGGL(k_reduce_wide<kOuter>, dim3((unsigned)((N + 7) / 8)), dim3(kOuter), 0, P.stream, part,
-                         nsplit, (int)N, T, W2);
+                         nsplit, (int)N, T, W2, ldw);
     {
       ProfScope ps(P.prof, P.stream, "qr_gemm_nn", 2.0 * M * (double)N * K,
                    8.0 * (2.0 * M * N + (double)M * K + (double)N * K));
+      RFM_CHECK(Mv % 2 == 0 && Mv >= M && K % (2 * kKC) == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0 &&
+                    reinterpret_cast<uintptr_t>(W2) % 16 == 0,
+                RFM_EINVAL, "QR: trailing-update operands not laid out for 16-byte loads");
       hipLaunchKernelGGL(k_gemm_nn128, dim3((unsigned)((M + kBig - 1) / kBig * ntile)), dim3(256), 0, P.stream, Cp,
-                         ldc, V, Mv, W2, (int64_t)K, M, (int)N, K);
+                         ldc, V, Mv, W2, ldw, M, (int)N, K);
     }
   }
   // Factor columns c0 .. c0 + nbh - 1 (nbh <= 256) of the M-row matrix A (diagonal at A[0]) in four

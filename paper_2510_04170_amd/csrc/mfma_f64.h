@@ -21,15 +21,15 @@ __device__ __forceinline__ int xcd_order(int id, int total) {
   return q < per ? x * per + q : 8 * per + x;
 }
 
-// One 16-deep k-chunk on LDS tiles Xs[k][row], Ys[k][col] (row and column of the output; LDY is the
-// padded width of the column tile).
+// One 16-deep k-chunk on LDS tiles Xs[k][row], Ys[k][col] (row and column of the output; LDX and LDY
+// are the padded widths of the two tiles).
 // v_mfma_f64_4x4x4_4b_f64 holds, for block b, A(i,k) in lane 16k+4b+i, B(k,j) in lane 16k+4b+j
 // and D(i,j) in lane 16i+4b+j.  With the A operand carrying 4 output columns (the same in every
 // block) and the B operand 16 output rows, acc[rg][cg] in lane l is output row rg*16 + l%16 and
 // column cg*4 + l/16 of the wavefront's 64 x 64 block: 16 consecutive rows of one column per
 // 16 lanes, which suits column-major stores.
-template <int LDY>
-__device__ __forceinline__ void mfma4_chunk(const double (*Xs)[kBig + 1], const double (*Ys)[LDY], int lane, int wr,
+template <int LDX, int LDY>
+__device__ __forceinline__ void mfma4_chunk(const double (*Xs)[LDX], const double (*Ys)[LDY], int lane, int wr,
                                             int wc, double (&acc)[4][16]) {
 #pragma unroll
   for (int ks = 0; ks < kKC / 4; ++ks) {
