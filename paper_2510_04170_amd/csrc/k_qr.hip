@@ -1096,6 +1096,28 @@ static void tn_split(int M, int ntile, int ncu, int cap, int* nsplit, int* krang
   *nsplit = (M + kr - 1) / kr;
 }
 
+// split-row count for the 128 x 128-tile TN products: the workgroups of one launch run in rounds of
+// `slots` (the resident count), each split's workgroups taking 1/ns of the rows, so the launch lasts
+// about ceil(tiles ns / slots) / ns full-height rounds.  Take the ns <= cap with the fewest (a small
+// charge per split for its partials and their reduction breaks near-ties towards fewer splits), at
+// least 256 rows per split, krange a multiple of 32.
+static void tn_split_rounds(int M, int tiles, int slots, int cap, int* nsplit, int* krange) {
+  int best = 1;
+  double best_cost = 1e300;
+  const int max_ns = std::max(1, std::min(cap, M / 256));
+  for (int ns = 1; ns <= max_ns; ++ns) {
+    const double rounds = std::ceil((double)tiles * ns / slots) / ns;
+    const double cost = rounds + 0.004 * ns;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = ns;
+    }
+  }
+  const int kr = ((M + best - 1) / best + 31) / 32 * 32;
+  *krange = kr;
+  *nsplit = (M + kr - 1) / kr;
+}
+
 namespace {
 
 // The blocked Householder QR on one column-major matrix A (leading dimension lda): workspace and the
@@ -1154,6 +1176,17 @@ class QrEngine {
     RFM_HIP(hipGetLastError());
   }
 
+  // resident workgroups of k_gemm_tn128 on the device (queried once)
+  int tn128_slots() {
+    if (tn_slots == 0) {
+      int per_cu = 0;
+      RFM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(&k_gemm_tn128<true>), 256, 0));
+      tn_slots = std::max(1, per_cu) * ncu;
+    }
+    return tn_slots;
+  }
+
   // the singular / time-out flags raised by the panels and by k_extract_r or k_r_signs
   void check_flags() {
     int32_t flags[3];
@@ -1171,6 +1204,7 @@ class QrEngine {
  private:
   Problem& P;
   const int ncu;
+  int tn_slots = 0;
   static constexpr int max_split = 16;
   double *Vw, *T64, *T128, *G128, *X128, *Y128, *T256, *G256, *X256, *Y256, *T512, *G64, *Pp, *DR, *part, *W2;
   size_t part_cap = 0;  // doubles of split partials
@@ -1215,7 +1249,7 @@ class QrEngine {
     const int ntile = (int)((N + kBig - 1) / kBig);
     const int halves = K / kBig;
     int nsplit, krange;
-    tn_split(M, halves * ntile, ncu, max_split, &nsplit, &krange);
+    tn_split_rounds(M, halves * ntile, tn128_slots(), max_split, &nsplit, &krange);
     krange = (krange + kKC - 1) / kKC * kKC;
     nsplit = (M + krange - 1) / krange;
     {
