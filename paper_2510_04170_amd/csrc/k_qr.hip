@@ -452,6 +452,7 @@ __global__ void __launch_bounds__(256) k_build_t(const double* __restrict__ part
                                                  const double* __restrict__ tau, double* __restrict__ T) {
   __shared__ double Ts[kPanel][kPanel + 1];
   __shared__ double Gs[kPanel][kPanel + 1];  // Gs[j][i] = G[i][j]
+  __shared__ double taus[kPanel];
   const int tid = threadIdx.x;
   for (int e = tid; e < kPanel * kPanel; e += 256) {
     const int j = e / kPanel, i = e % kPanel;
@@ -461,11 +462,14 @@ __global__ void __launch_bounds__(256) k_build_t(const double* __restrict__ part
     Gs[j][i] = g;
     Ts[i][j] = 0.0;
   }
+  if (tid < kPanel) taus[tid] = tid < nb ? tau[tid] : 0.0;
   __syncthreads();
   if (tid < kPanel) {
+    // column j: T[i][j] = -tau_j sum_{i <= k < j} T[i][k] G[k][j], T[j][j] = tau_j (tau from LDS: one
+    // global load per column would put a memory round trip on every step of this chain)
     const int i = tid;
     for (int j = 0; j < nb; ++j) {
-      const double tj = tau[j];
+      const double tj = taus[j];
       double v = 0.0;
       if (i < j) {
         for (int k = i; k < j; ++k) v += Ts[i][k] * Gs[j][k];
@@ -473,7 +477,7 @@ __global__ void __launch_bounds__(256) k_build_t(const double* __restrict__ part
       } else if (i == j) {
         v = tj;
       }
-      // every lane reads column j < current only; the write goes to column j
+      // every lane reads columns < j only; the write goes to column j
       if (i <= j) Ts[i][j] = v;
       __builtin_amdgcn_wave_barrier();
     }
@@ -620,21 +624,28 @@ __global__ void __launch_bounds__(256, 2) k_gemm_nn128(double* __restrict__ C, i
     if (k0 + 2 * kKC < K) issue(k0 + 2 * kKC, As0, Bs0);
     mfma4_chunk(As1, Bs1, lane, wr, wc, acc);
   }
+  // C += acc, two row groups (32 loads per lane) at a time
   const int row_l = lane % 16, col_l = lane / 16;
 #pragma unroll
-  for (int rg = 0; rg < 4; ++rg) {
-    const int r = r0 + wr * 64 + rg * 16 + row_l;
-    if (r >= M) continue;
-    double cv[16];
+  for (int rp = 0; rp < 4; rp += 2) {
+    double cv[2][16];
 #pragma unroll
-    for (int cg = 0; cg < 16; ++cg) {
-      const int col = n0 + wc * 64 + cg * 4 + col_l;
-      cv[cg] = col < N ? C[(int64_t)col * ldc + r] : 0.0;
+    for (int q = 0; q < 2; ++q) {
+      const int r = r0 + wr * 64 + (rp + q) * 16 + row_l;
+#pragma unroll
+      for (int cg = 0; cg < 16; ++cg) {
+        const int col = n0 + wc * 64 + cg * 4 + col_l;
+        cv[q][cg] = (col < N && r < M) ? C[(int64_t)col * ldc + r] : 0.0;
+      }
     }
 #pragma unroll
-    for (int cg = 0; cg < 16; ++cg) {
-      const int col = n0 + wc * 64 + cg * 4 + col_l;
-      if (col < N) C[(int64_t)col * ldc + r] = cv[cg] + acc[rg][cg];
+    for (int q = 0; q < 2; ++q) {
+      const int r = r0 + wr * 64 + (rp + q) * 16 + row_l;
+#pragma unroll
+      for (int cg = 0; cg < 16; ++cg) {
+        const int col = n0 + wc * 64 + cg * 4 + col_l;
+        if (col < N && r < M) C[(int64_t)col * ldc + r] = cv[q][cg] + acc[rp + q][cg];
+      }
     }
   }
 }
@@ -799,6 +810,8 @@ __global__ void __launch_bounds__(256) k_combine_t(const double* __restrict__ Ta
                                                    double* __restrict__ T) {
   __shared__ double Xs[kPanel][kPanel + 1];
   __shared__ double Gs[kPanel][kPanel + 1];
+  __shared__ double Tas[kPanel][kPanel + 1];
+  __shared__ double Tbs[kPanel][kPanel + 1];
   const int tid = threadIdx.x;
   for (int e = tid; e < kPanel * kPanel; e += 256) {
     const int a = e / kPanel, b = e % kPanel;
@@ -806,14 +819,16 @@ __global__ void __launch_bounds__(256) k_combine_t(const double* __restrict__ Ta
     if (b < nbb)
       for (int sp = 0; sp < nsplit; ++sp) g += part[((size_t)sp * nbb + b) * kPanel + a];
     Gs[a][b] = g;
+    Tas[a][b] = Ta[e];
+    Tbs[a][b] = Tb[e];
   }
   __syncthreads();
-  // X = Gab Tb
+  // X = Gab Tb (Tb upper triangular)
   for (int e = tid; e < kPanel * kPanel; e += 256) {
     const int a = e / kPanel, b = e % kPanel;
     double v = 0.0;
     if (nbb > 0)
-      for (int k = 0; k <= b; ++k) v += Gs[a][k] * Tb[k * kPanel + b];
+      for (int k = 0; k <= b; ++k) v += Gs[a][k] * Tbs[k][b];
     Xs[a][b] = v;
   }
   __syncthreads();
@@ -821,12 +836,12 @@ __global__ void __launch_bounds__(256) k_combine_t(const double* __restrict__ Ta
     const int qq = e / kBig, p = e % kBig;
     double v = 0.0;
     if (qq < kPanel && p < kPanel) {
-      v = Ta[qq * kPanel + p];
+      v = Tas[qq][p];
     } else if (qq >= kPanel && p >= kPanel) {
-      v = Tb[(qq - kPanel) * kPanel + (p - kPanel)];
+      v = Tbs[qq - kPanel][p - kPanel];
     } else if (qq < kPanel && p >= kPanel) {
       const int b = p - kPanel;
-      for (int k = qq; k < kPanel; ++k) v += Ta[qq * kPanel + k] * Xs[k][b];
+      for (int k = qq; k < kPanel; ++k) v += Tas[qq][k] * Xs[k][b];
       v = -v;
     }
     T[e] = v;
@@ -860,11 +875,22 @@ __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
 
 // G[b][a] = sum over splits of part[split][b][a] for b < nb (64-wide rows), splits in order; the
 // single-workgroup T builders then read G as a one-split partial
-__global__ void k_gsum64(const double* __restrict__ part, int nsplit, int nb, double* __restrict__ G) {
+// G[e] = sum over splits of part[split][e] in split order, e < nb * 64; the loads go out 8 at a time
+__global__ void __launch_bounds__(256) k_gsum64(const double* __restrict__ part, int nsplit, int nb,
+                                                double* __restrict__ G) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nb * kPanel) return;
+  const int ne = nb * kPanel;
+  if (e >= ne) return;
   double g = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) g += part[(size_t)sp * nb * kPanel + e];
+  int sp = 0;
+  for (; sp + 8 <= nsplit; sp += 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = part[(size_t)(sp + q) * ne + e];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) g += v[q];
+  }
+  for (; sp < nsplit; ++sp) g += part[(size_t)sp * ne + e];
   G[e] = g;
 }
 
