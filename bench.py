@@ -51,8 +51,8 @@ PREC = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
 # same counters read for an elementwise copy of 1 GiB); valid only while the kernels are unchanged,
 # so a kernel without counters taken on its current code reports null
 TRAFFIC_BYTES = {
-    "qr_gemm_tn": (8338539.7 * 2.0 + 85947.3 * 1.0) * 1024.0,
-    "qr_gemm_nn": (6335101.8 * 2.0 + 4851457.7 * 1.0) * 1024.0,
+    "qr_gemm_tn": (6439910.3 * 2.0 + 276686.2 * 1.0) * 1024.0,
+    "qr_gemm_nn": (6164443.1 * 2.0 + 4851457.7 * 1.0) * 1024.0,
 }
 
 METRIC = "Newton solves/s at relL2<=1e-6; sketch-GEMM TFLOP/s; LSQR SpMV HBM GB/s"
