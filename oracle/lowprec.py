@@ -174,11 +174,28 @@ def chunk_rows(groups: np.ndarray, h: int, m: int) -> np.ndarray:
     return rows[rows < m]
 
 
+def split_chunk(X: np.ndarray, fmt: str, npieces: int = 0):
+    """One chunk (rows x columns) of D J cut into integer pieces per column: returns (pieces, E) with
+    pieces[p] = q_p 2^(E - b(p+1)) (q_p integer, nearest with ties to even, taken from what the earlier
+    pieces leave) and E = floor(log2 max |X|) + 1 per column (0 for an all-zero column)."""
+    npieces = npieces or DEFAULT_PIECES[fmt]
+    b = BITS[fmt]
+    X = np.array(X, np.float64, copy=True)
+    M = np.abs(X).max(axis=0) if X.shape[0] else np.zeros(X.shape[1])
+    E = np.where(M > 0, np.frexp(M)[1], 0)          # M = f 2^e, f in [0.5, 1): floor(log2 M) + 1 = e
+    out = []
+    for p in range(npieces):
+        unit = np.ldexp(1.0, E - b * (p + 1))
+        piece = np.round(X / unit) * unit
+        out.append(piece)
+        X = X - piece
+    return out, E
+
+
 def pieces(prob, DJ: np.ndarray, fmt: str, npieces: int = 0):
     """Returns (pieces, exps): pieces[p] is m x n (values q_p 2^(E - b(p+1))),
     exps[e*K + c] is [nchunks, J] (the exponent E of each chunk and column)."""
     npieces = npieces or DEFAULT_PIECES[fmt]
-    b = BITS[fmt]
     m, n = DJ.shape
     J = prob.J
     out = [np.zeros_like(DJ) for _ in range(npieces)]
@@ -189,16 +206,9 @@ def pieces(prob, DJ: np.ndarray, fmt: str, npieces: int = 0):
         E = np.zeros((nch, J), np.int64)
         for h in range(nch):
             rows = chunk_rows(groups, h, m)
-            X = DJ[rows, cols].copy()
-            M = np.abs(X).max(axis=0) if len(rows) else np.zeros(J)
-            Eh = np.where(M > 0, np.frexp(M)[1], 0)   # M = f 2^e, f in [0.5, 1): floor(log2 M) + 1 = e
-            E[h] = Eh
+            got, E[h] = split_chunk(DJ[rows, cols], fmt, npieces)
             for p in range(npieces):
-                unit = np.ldexp(1.0, Eh - b * (p + 1))
-                q = np.round(X / unit)
-                piece = q * unit
-                out[p][rows, cols] = piece
-                X = X - piece
+                out[p][rows, cols] = got[p]
         exps.append(E)
     return out, exps
 
