@@ -91,7 +91,7 @@ def cpu_baseline(quick: bool) -> dict:
         threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    nsub, J, q = ((2, 1, 1), 30, 4) if quick else ((2, 2, 2), 110, 6)
+    nsub, J, q = ((2, 1, 1), 30, 4) if quick else ((2, 2, 2), 200, 7)
     prob = W.config2(nsub=nsub, J=J, q=q, test_per_dim=2)
     t0 = time.perf_counter()
     u, st = O.ipn(prob, opts=O.Opts(gamma=2.0, lsqr_tol=1e-10))
