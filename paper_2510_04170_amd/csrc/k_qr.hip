@@ -67,6 +67,22 @@ __device__ __forceinline__ double bcast_lane(double v, int k) {
   return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
+// sum over sp < cnt of p[sp * stride], added in split order (the loads go out 8 at a time; the sum is
+// the same as one load and one add per split)
+__device__ __forceinline__ double sum_splits(const double* __restrict__ p, size_t stride, int cnt) {
+  double g = 0.0;
+  int sp = 0;
+  for (; sp + 8 <= cnt; sp += 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = p[(size_t)(sp + q) * stride];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) g += v[q];
+  }
+  for (; sp < cnt; ++sp) g += p[(size_t)sp * stride];
+  return g;
+}
+
 // Grid barrier without atomics: workgroup g publishes its phase in its own word
 // (after its data stores are acknowledged); thread t < G polls word t.  Arrival
 // words start at 0 for every launch (k_reset_sync).
@@ -472,7 +488,19 @@ __global__ void __launch_bounds__(256) k_build_t(const double* __restrict__ part
       const double tj = taus[j];
       double v = 0.0;
       if (i < j) {
-        for (int k = i; k < j; ++k) v += Ts[i][k] * Gs[j][k];
+        // in order of k, the LDS reads 8 at a time
+        int k = i;
+        for (; k + 8 <= j; k += 8) {
+          double a[8], g[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            a[q] = Ts[i][k + q];
+            g[q] = Gs[j][k + q];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v += a[q] * g[q];
+        }
+        for (; k < j; ++k) v += Ts[i][k] * Gs[j][k];
         v = -tj * v;
       } else if (i == j) {
         v = tj;
@@ -496,8 +524,7 @@ __global__ void __launch_bounds__(256) k_reduce_w(const double* __restrict__ par
   const int p = tid % kPanel, sub = tid / kPanel;
   const int col = blockIdx.x * 4 + sub;
   double w = 0.0;
-  if (col < N)
-    for (int sp = 0; sp < nsplit; ++sp) w += part[((size_t)sp * N + col) * kPanel + p];
+  if (col < N) w = sum_splits(part + (size_t)col * kPanel + p, (size_t)N * kPanel, nsplit);
   Wsh[sub][p] = w;
   __syncthreads();
   if (col < N) {
@@ -881,17 +908,7 @@ __global__ void __launch_bounds__(256) k_gsum64(const double* __restrict__ part,
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int ne = nb * kPanel;
   if (e >= ne) return;
-  double g = 0.0;
-  int sp = 0;
-  for (; sp + 8 <= nsplit; sp += 8) {
-    double v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = part[(size_t)(sp + q) * ne + e];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) g += v[q];
-  }
-  for (; sp < nsplit; ++sp) g += part[(size_t)sp * ne + e];
-  G[e] = g;
+  G[e] = sum_splits(part + e, (size_t)ne, nsplit);
 }
 
 // G[a][b] (row-major w x w) = sum over splits of part[split][b][a] (pstride w), splits in order
@@ -941,8 +958,7 @@ __global__ void __launch_bounds__(WID) k_reduce_wide(const double* __restrict__ 
   for (int c = 0; c < 8; ++c) {
     const int n = n0 + c;
     double w = 0.0;
-    if (n < N)
-      for (int sp = 0; sp < nsplit; ++sp) w += part[((size_t)sp * N + n) * WID + p];
+    if (n < N) w = sum_splits(part + (size_t)n * WID + p, (size_t)N * WID, nsplit);
     Wsh[c][p] = w;
   }
   __syncthreads();
