@@ -854,8 +854,20 @@ __global__ void __launch_bounds__(256) k_combine_t(const double* __restrict__ Ta
   for (int e = tid; e < kPanel * kPanel; e += 256) {
     const int a = e / kPanel, b = e % kPanel;
     double v = 0.0;
-    if (nbb > 0)
-      for (int k = 0; k <= b; ++k) v += Gs[a][k] * Tbs[k][b];
+    if (nbb > 0) {
+      int k = 0;
+      for (; k + 8 <= b + 1; k += 8) {
+        double x[8], y[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          x[q] = Gs[a][k + q];
+          y[q] = Tbs[k + q][b];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v += x[q] * y[q];
+      }
+      for (; k <= b; ++k) v += Gs[a][k] * Tbs[k][b];
+    }
     Xs[a][b] = v;
   }
   __syncthreads();
@@ -868,7 +880,18 @@ __global__ void __launch_bounds__(256) k_combine_t(const double* __restrict__ Ta
       v = Tbs[qq - kPanel][p - kPanel];
     } else if (qq < kPanel && p >= kPanel) {
       const int b = p - kPanel;
-      for (int k = qq; k < kPanel; ++k) v += Tas[qq][k] * Xs[k][b];
+      int k = qq;
+      for (; k + 8 <= kPanel; k += 8) {
+        double x[8], y[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          x[q] = Tas[qq][k + q];
+          y[q] = Xs[k + q][b];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v += x[q] * y[q];
+      }
+      for (; k < kPanel; ++k) v += Tas[qq][k] * Xs[k][b];
       v = -v;
     }
     T[e] = v;
@@ -916,9 +939,7 @@ __global__ void k_gsum(const double* __restrict__ part, int nsplit, int w, doubl
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= w * w) return;
   const int a = e / w, b = e % w;
-  double g = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) g += part[((size_t)sp * w + b) * w + a];
-  G[e] = g;
+  G[e] = sum_splits(part + (size_t)b * w + a, (size_t)w * w, nsplit);
 }
 
 // C = alpha * A B for row-major w x w matrices, one thread per entry
@@ -928,7 +949,18 @@ __global__ void k_sq_gemm(const double* __restrict__ A, const double* __restrict
   if (e >= w * w) return;
   const int i = e / w, j = e % w;
   double v = 0.0;
-  for (int k = 0; k < w; ++k) v += A[i * w + k] * B[k * w + j];
+  int k = 0;
+  for (; k + 8 <= w; k += 8) {  // loads 8 at a time, the sum in order of k
+    double a[8], b[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      a[q] = A[i * w + k + q];
+      b[q] = B[(k + q) * w + j];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += a[q] * b[q];
+  }
+  for (; k < w; ++k) v += A[i * w + k] * B[k * w + j];
   C[e] = alpha * v;
 }
 
@@ -963,7 +995,17 @@ __global__ void __launch_bounds__(WID) k_reduce_wide(const double* __restrict__ 
   }
   __syncthreads();
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int qq = 0; qq <= p; ++qq) {
+  int qq = 0;
+  for (; qq + 8 <= p + 1; qq += 8) {  // T loads 8 at a time, the sums in order of qq
+    double t[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t[q] = T[(qq + q) * WID + p];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[c] += t[q] * Wsh[c][qq + q];
+  }
+  for (; qq <= p; ++qq) {
     const double t = T[qq * WID + p];
 #pragma unroll
     for (int c = 0; c < 8; ++c) v[c] += t * Wsh[c][qq];
