@@ -359,8 +359,13 @@ __global__ void __launch_bounds__(512) k_panel_df(double* __restrict__ A, int64_
       __syncthreads();
     }
     if (rg == 0 && c >= j && c < nb) {
-      tot_sh[c] = wait_slot(&TOT[j * kPanel + c], sync);
-      dr_sh[c] = wait_slot(&DR[j * kPanel + c], sync);
+      // both loads in flight at once (the diagonal row is usually there long before the total)
+      double t = ld_dev(&TOT[j * kPanel + c]);
+      double d = ld_dev(&DR[j * kPanel + c]);
+      if ((unsigned long long)__double_as_longlong(t) == kEmpty) t = wait_slot(&TOT[j * kPanel + c], sync);
+      if ((unsigned long long)__double_as_longlong(d) == kEmpty) d = wait_slot(&DR[j * kPanel + c], sync);
+      tot_sh[c] = t;
+      dr_sh[c] = d;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
