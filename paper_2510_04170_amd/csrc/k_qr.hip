@@ -1281,7 +1281,7 @@ class QrEngine {
     int32_t flags[3];
     RFM_HIP(hipMemcpyAsync(flags, P.d_sync.p, sizeof(flags), hipMemcpyDeviceToHost, P.stream));
     RFM_HIP(hipStreamSynchronize(P.stream));
-    RFM_CHECK(flags[kSyncError] == 0, RFM_EDEVICE, "QR panel: grid barrier timed out");
+    RFM_CHECK(flags[kSyncError] == 0, RFM_EDEVICE, "QR panel: a cross-workgroup wait timed out");
     RFM_CHECK(flags[kSyncSingular] == 0, RFM_ESINGULAR, "R has a zero or non-finite diagonal entry");
   }
 
