@@ -420,7 +420,8 @@ __global__ void __launch_bounds__(512) k_panel_df(double* __restrict__ A, int64_
 
 // Split-row TN product: part[split][col][p] = sum_{k in split} V[k][p] C[k][col]
 // V: K x 64 (ldv), C: K x N (ldc).  Workgroup tile 64 (p) x 64 (col); wavefront w
-// owns p-tile w and the 4 col-tiles.  Rows are staged through LDS 32 at a time.
+// owns p-tile w and the 4 col-tiles.  Rows are staged through LDS 32 at a time; the next 32 rows
+// are loaded into registers while the current ones are multiplied.
 __global__ void __launch_bounds__(256) k_gemm_tn(const double* __restrict__ V, int64_t ldv,
                                                  const double* __restrict__ C, int64_t ldc, int K, int N,
                                                  int krange, double* __restrict__ part) {
@@ -435,15 +436,25 @@ __global__ void __launch_bounds__(256) k_gemm_tn(const double* __restrict__ V, i
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0, 0, 0, 0};
   const int lk = tid % KC, lc = tid / KC;  // loader: row lk, columns lc + 8 i
-  for (int k0 = kb; k0 < ke; k0 += KC) {
+  double rv[8], rcv[8];
+  auto load = [&](int k0) {
     const int kr = k0 + lk;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int col = lc + 8 * i;
-      Vs[lk][col] = kr < ke ? V[(int64_t)col * ldv + kr] : 0.0;
-      Cs[lk][col] = (kr < ke && n0 + col < N) ? C[(int64_t)(n0 + col) * ldc + kr] : 0.0;
+      rv[i] = kr < ke ? V[(int64_t)col * ldv + kr] : 0.0;
+      rcv[i] = (kr < ke && n0 + col < N) ? C[(int64_t)(n0 + col) * ldc + kr] : 0.0;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += KC) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      Vs[lk][lc + 8 * i] = rv[i];
+      Cs[lk][lc + 8 * i] = rcv[i];
     }
     __syncthreads();
+    if (k0 + KC < ke) load(k0 + KC);
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       const int kk = ks * 4 + lane / 16;
@@ -563,15 +574,24 @@ __global__ void __launch_bounds__(256) k_gemm_nn(double* __restrict__ C, int64_t
       acc[ct][t] = (r < M && col < N) ? C[(int64_t)col * ldc + r] : 0.0;
     }
   }
+  // all of this lane's V values first (one memory round trip), then the products in order of p
   const int nks = (nb + 3) / 4;
-  for (int ks = 0; ks < nks; ++ks) {
-    const int p = ks * 4 + lane / 16;
-    const int r = rbase + lane % 16;
-    const double av = (r < M && p < nb) ? V[(int64_t)p * ldv + r] : 0.0;
+  const int r = rbase + lane % 16;
+  double avs[kPanel / 4];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const double bv = Ws[ct * 16 + lane % 16][p];
-      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+  for (int ks = 0; ks < kPanel / 4; ++ks) {
+    const int p = ks * 4 + lane / 16;
+    avs[ks] = (ks < nks && r < M && p < nb) ? V[(int64_t)p * ldv + r] : 0.0;
+  }
+#pragma unroll
+  for (int ks = 0; ks < kPanel / 4; ++ks) {
+    if (ks < nks) {  // uniform
+      const int p = ks * 4 + lane / 16;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const double bv = Ws[ct * 16 + lane % 16][p];
+        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(avs[ks], bv, acc[ct], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
