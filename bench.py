@@ -143,8 +143,8 @@ def main() -> None:
         print(summarize_rocpd(a.summarize_rocpd))
         return
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
-              f"(a multi-GPU layout is described in DESIGN.md but not built)", file=sys.stderr)
+        print(f"bench.py: a solve runs on one GPU; --gpus {a.gpus} is not supported "
+              f"(independent solves, one process per GPU, are how more GPUs are used)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -9,7 +9,7 @@ Everything is dense numpy in float64, written for a reader to check against
 the paper by eye; there is no blocking, fusion or reordering beyond what each
 formula states.  Inputs come from ``rfm_workloads`` (problem description only).
 
-Readings taken where the paper is silent (each is also listed in the design doc):
+Readings taken where the paper is silent:
  * rows: each point group expands to rows ordered (equation or component,
    continuity order, point); groups keep their listed order, which is
    [PDE; continuity; boundary] as in Alg. 3 step 4;
