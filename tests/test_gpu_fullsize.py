@@ -260,7 +260,7 @@ def test_other_workloads_at_full_size(name):
     """The two other full-size workloads: sampled rows of D F and D J from every row kind (hole surfaces,
     the moving disc's Neumann rows and the space-time continuity rows included) against the oracle
     (1e-13 per row); for the Allen-Cahn workload, whose sketch fits (s n 8 = 41.9 GB), sampled entries
-    of its BF16 sketch too (1e-12 of sum |S||DJ|).  The Helmholtz workload's sketch (262 GB) only exists
+    of its BF16 and FP8 sketches too (1e-12 of sum |S||DJ|).  The Helmholtz workload's sketch (262 GB) only exists
     streamed; its QR is covered by the streamed-QR parity cases."""
     prob = W.config4() if name.startswith("allen") else W.config3()
     _announce(f"full size: {name} (n = {prob.n})")
@@ -280,28 +280,29 @@ def test_other_workloads_at_full_size(name):
             assert abs(DFg[k] - DF[k]) <= 1e-13 * abs(DF[k]) + 1e-13 * np.abs(DJ[k]) @ np.abs(u), int(r)
         msg = f"{name}: {rows.size} rows, worst D J row difference {worst:.2e}"
         if name.startswith("allen"):
-            lp.stage_sketch(2.0, 1, 0, R.RFM_PREC_BF16, 0)
-            s = lp.s
-            rng = np.random.default_rng(31)
-            isamp = np.unique(np.concatenate([[0, s - 1], rng.integers(s, size=14)]))
-            _, m = O.row_table(prob)
-            for c in np.unique(np.concatenate([[prob.n - 1], rng.integers(prob.n, size=2)])):
-                rows_c = column_support(prob, int(c))
-                x = oracle_rows(prob, u, rows_c, cols=[int(c)])[2][:, 0]
-                groups = L.block_groups(prob)[int(c) // prob.J]
-                xt = np.zeros_like(x)
-                at = 0
-                for h in range(len(groups) // 4):
-                    nr = L.chunk_rows(groups, h, m).size
-                    got, _ = L.split_chunk(x[at:at + nr, None], L.FMT_BF16)
-                    xt[at:at + nr] = np.sum(got, axis=0)[:, 0]
-                    at += nr
-                S = L.code_table(L.FMT_BF16)[L.sample_bytes(1, 0, isamp[:, None], rows_c[None, :])]
-                S = S / L.CODE_SCALE[L.FMT_BF16] / math.sqrt(s)
-                ref = S @ xt
-                gotb = lp.get_sketch_cols(int(c), 1)[isamp, 0]
-                assert np.all(np.abs(gotb - ref) <= 1e-12 * (np.abs(S) @ np.abs(xt))), int(c)
-            msg += "; BF16 sketch entries agree"
+            for code, fmt in ((R.RFM_PREC_BF16, L.FMT_BF16), (R.RFM_PREC_FP8, L.FMT_E4M3)):
+                lp.stage_sketch(2.0, 1, 0, code, 0)
+                s = lp.s
+                rng = np.random.default_rng(31)
+                isamp = np.unique(np.concatenate([[0, s - 1], rng.integers(s, size=14)]))
+                _, m = O.row_table(prob)
+                for c in np.unique(np.concatenate([[prob.n - 1], rng.integers(prob.n, size=2)])):
+                    rows_c = column_support(prob, int(c))
+                    x = oracle_rows(prob, u, rows_c, cols=[int(c)])[2][:, 0]
+                    groups = L.block_groups(prob)[int(c) // prob.J]
+                    xt = np.zeros_like(x)
+                    at = 0
+                    for h in range(len(groups) // 4):
+                        nr = L.chunk_rows(groups, h, m).size
+                        got, _ = L.split_chunk(x[at:at + nr, None], fmt)
+                        xt[at:at + nr] = np.sum(got, axis=0)[:, 0]
+                        at += nr
+                    S = L.code_table(fmt)[L.sample_bytes(1, 0, isamp[:, None], rows_c[None, :])]
+                    S = S / L.CODE_SCALE[fmt] / math.sqrt(s)
+                    ref = S @ xt
+                    gotb = lp.get_sketch_cols(int(c), 1)[isamp, 0]
+                    assert np.all(np.abs(gotb - ref) <= 1e-12 * (np.abs(S) @ np.abs(xt))), (fmt, int(c))
+            msg += "; BF16 and FP8 sketch entries agree"
         print(msg)
     finally:
         lp.close()
