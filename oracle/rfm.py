@@ -586,6 +586,7 @@ class Opts:
     sketch_prec: str = "f64"       # "f64" | "bf16" | "fp8"  (oracle.lowprec)
     sketch_pieces: int = 0         # pieces of D J in the low-precision sketch (0: format default)
     lsqr_prec: str = "f64"         # "f64" | "f32": D J copy used by the LSQR products
+    jac_index0: int = 0            # index of the first Jacobian evaluation (the sketch's key word 1)
 
 
 @dataclass
@@ -596,6 +597,8 @@ class Stats:
     alphas: List[float] = field(default_factory=list)
     resnorms: List[float] = field(default_factory=list)
     status: str = "ok"             # ok | maxit | stall | singular
+    inner_steps: List[int] = field(default_factory=list)   # directions computed in each outer step
+    flags: List[bool] = field(default_factory=list)        # Alg. 2's Flag after each outer step
 
 
 @dataclass
@@ -650,7 +653,7 @@ def ipn(prob: Problem, u0: Optional[np.ndarray] = None, opts: Optional[Opts] = N
     st = Stats()
     for k in range(opts.max_outer):
         try:
-            pc = make_precond(prob, u, opts, st.jac_evals)
+            pc = make_precond(prob, u, opts, opts.jac_index0 + st.jac_evals)
         except SingularPreconditioner:
             st.status = "singular"
             return u, st
@@ -662,6 +665,8 @@ def ipn(prob: Problem, u0: Optional[np.ndarray] = None, opts: Optional[Opts] = N
         du = newton_direction(pc, DF, opts, st)
         alpha, phi1, _ = golden_section(lambda a: scaled_norm(prob, pc.D, u + a * du), phi0, opts.gs_iters)
         st.outer_iters += 1
+        st.inner_steps.append(1)
+        st.flags.append(True)
         st.alphas.append(alpha)
         if alpha == 0.0:
             st.status = "stall"
@@ -686,7 +691,7 @@ def amipn(prob: Problem, u0: Optional[np.ndarray] = None, opts: Optional[Opts] =
     u = np.zeros(prob.n) if u0 is None else np.array(u0, float)
     st = Stats()
     try:
-        pc = make_precond(prob, u, opts, 0)
+        pc = make_precond(prob, u, opts, opts.jac_index0)
     except SingularPreconditioner:
         st.status = "singular"
         return u, st
@@ -717,12 +722,15 @@ def amipn(prob: Problem, u0: Optional[np.ndarray] = None, opts: Optional[Opts] =
                 break
             Fz = Fn
         st.outer_iters += 1
+        st.inner_steps.append(i + 1)
         if stalled and i == 0 and fresh:
+            st.flags.append(True)
             st.status = "stall"
             st.resnorms.append(phi_u)
             return u, st
         if stalled:
             flag = True
+        st.flags.append(flag)
         u_new = z
         phi_new = float(np.linalg.norm(pc.D * residual(prob, u_new)))
         st.resnorms.append(phi_new)
@@ -732,7 +740,7 @@ def amipn(prob: Problem, u0: Optional[np.ndarray] = None, opts: Optional[Opts] =
             return u, st
         if flag:
             try:
-                pc = make_precond(prob, u, opts, st.jac_evals)
+                pc = make_precond(prob, u, opts, opts.jac_index0 + st.jac_evals)
             except SingularPreconditioner:
                 st.status = "singular"
                 return u, st
