@@ -159,7 +159,7 @@ def col_slice(prob: Problem, e: int, c: int) -> slice:
 # ---------------------------------------------------------------------------
 
 
-# f and f' of the pointwise terms coeff * f(u_c) (the paper's cosh nonlinearity, Sec. 5)
+# f and f' of the pointwise terms coeff * f(u_c) (the paper's cosh nonlinearity, Sec. 6.2)
 _FN = {"cosh": (np.cosh, np.sinh), "sinh": (np.sinh, np.cosh), "exp": (np.exp, np.exp)}
 
 
@@ -599,6 +599,7 @@ class Stats:
     status: str = "ok"             # ok | maxit | stall | singular
     inner_steps: List[int] = field(default_factory=list)   # directions computed in each outer step
     flags: List[bool] = field(default_factory=list)        # Alg. 2's Flag after each outer step
+    iterates: List[np.ndarray] = field(default_factory=list)  # u after each outer step
 
 
 @dataclass
@@ -671,9 +672,11 @@ def ipn(prob: Problem, u0: Optional[np.ndarray] = None, opts: Optional[Opts] = N
         if alpha == 0.0:
             st.status = "stall"
             st.resnorms.append(phi0)
+            st.iterates.append(u.copy())
             return u, st
         u = u + alpha * du
         st.resnorms.append(phi1)
+        st.iterates.append(u.copy())
         if abs(phi1 - phi0) < opts.outer_tol or phi1 == 0.0:
             return u, st
     st.status = "maxit"
@@ -727,6 +730,7 @@ def amipn(prob: Problem, u0: Optional[np.ndarray] = None, opts: Optional[Opts] =
             st.flags.append(True)
             st.status = "stall"
             st.resnorms.append(phi_u)
+            st.iterates.append(u.copy())
             return u, st
         if stalled:
             flag = True
@@ -734,6 +738,7 @@ def amipn(prob: Problem, u0: Optional[np.ndarray] = None, opts: Optional[Opts] =
         u_new = z
         phi_new = float(np.linalg.norm(pc.D * residual(prob, u_new)))
         st.resnorms.append(phi_new)
+        st.iterates.append(u_new.copy())
         done = abs(phi_new - phi_u) < opts.outer_tol or phi_new == 0.0
         u = u_new
         if done and not stalled:
@@ -778,6 +783,38 @@ def eval_field(prob: Problem, u: np.ndarray, x: np.ndarray, owner: np.ndarray) -
             phi = feature_jet(prob, int(e), c, x[sel])[0]
             out[sel, c] = phi @ u[col_slice(prob, int(e), c)]
     return out
+
+
+def eval_grad(prob: Problem, u: np.ndarray, x: np.ndarray, owner: np.ndarray) -> np.ndarray:
+    """grad u_n(x) [npts, ncomp, d]: the feature gradients (1 - t^2) w_a / sigma_a of the owner box (indicator
+    partition), or by the product rule psi_e grad phi + phi grad psi_e summed over the covering boxes."""
+    d = prob.dim
+    out = np.zeros((x.shape[0], prob.ncomp, d))
+    if getattr(prob, "pou", "a") == "b":
+        for e in covering_boxes(prob, x):
+            for c in range(prob.ncomp):
+                dv = blended_jet(prob, e, c, x)[1]                  # [n, J, d]
+                out[:, c, :] += np.einsum("njd,j->nd", dv, u[col_slice(prob, e, c)])
+        return out
+    for e in np.unique(owner):
+        sel = np.nonzero(owner == e)[0]
+        for c in range(prob.ncomp):
+            dphi = feature_jet(prob, int(e), c, x[sel])[1]          # [n, J, d]
+            out[sel, c, :] = np.einsum("njd,j->nd", dphi, u[col_slice(prob, int(e), c)])
+    return out
+
+
+def rel_h1(prob: Problem, u: np.ndarray) -> np.ndarray:
+    """Per-component relative H1 error on the test points:
+    sqrt(sum |u_n - u*|^2 + |grad(u_n - u*)|^2) / sqrt(sum |u*|^2 + |grad u*|^2)."""
+    un = eval_field(prob, u, prob.test_x, prob.test_owner)
+    gn = eval_grad(prob, u, prob.test_x, prob.test_owner)
+    from rfm_workloads import jet_of
+    jet = jet_of(prob)(prob.test_x)
+    us, gs = jet[0], jet[1]
+    num = np.sum((un - us) ** 2, axis=0) + np.sum((gn - gs) ** 2, axis=(0, 2))
+    den = np.sum(us ** 2, axis=0) + np.sum(gs ** 2, axis=(0, 2))
+    return np.sqrt(num / den)
 
 
 def rel_l2(prob: Problem, u: np.ndarray) -> np.ndarray:

@@ -586,7 +586,7 @@ def ac2_hole_centre(t):
 
 def allen_cahn_moving_hole(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, n_t=None, n_theta=None,
                            test_per_dim=None) -> Problem:
-    """The paper's space-time Allen-Cahn problem on a domain with a moving hole (Sec. 5):
+    """The paper's space-time Allen-Cahn problem on a domain with a moving hole (Sec. 6.3):
     u_t - Lap u + u^3 - u = f on ([0,1]^2 minus a disc of radius 0.1 centred at
     (0.5 + 0.2 cos(pi t), 0.5 + 0.2 sin(pi t))) x (0, 1], u* = 2 sin(x(1 - x)) sin(y(1 - y)) e^(t+1);
     Dirichlet u* on the x, y faces, at t = 0 and on the hole's boundary (n_t cell-centred t levels x
@@ -636,7 +636,7 @@ def jet_helmholtz_cosh(x: np.ndarray) -> Jet:
 
 def helmholtz_cosh(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, test_per_dim=None, pou="a") -> Problem:
     """3-D nonlinear Helmholtz with a cosh term on the unit cube (the paper's IPN / AMIPN comparison,
-    Sec. 5): Lap u - 100 u + 10 cosh(u) = f, u* = (2 + |x|^2) sin(pi x) sin(pi y) sin(pi z),
+    Sec. 6.2): Lap u - 100 u + 10 cosh(u) = f, u* = (2 + |x|^2) sin(pi x) sin(pi y) sin(pi z),
     Dirichlet u* on the boundary; q^3 collocation points per box, q x q face and interface grids."""
     lin = [(0, 0, 1.0, D_LAPLACE), (0, 0, -100.0, D_ID)]
     fn = [(0, 0, 10.0, FN_COSH)]
@@ -667,7 +667,7 @@ def quasilinear_terms():
 
 
 def quasilinear(nsub=(2, 2, 2), J=800, q=20, seed=0, R=1.0, test_per_dim=None, pou="a") -> Problem:
-    """3-D quasi-linear elliptic benchmark of the paper (Sec. 3.4 and the AMIPN table of Sec. 5):
+    """3-D quasi-linear elliptic benchmark of the paper (Sec. 3.2 and the AMIPN table of Sec. 6.2):
     -div((1 + u^2) grad u) = f on the unit cube, u* = (x + y + z) sin(pi x) sin(pi y) cos(pi z),
     Dirichlet u* on the boundary; q^3 collocation points per box, q x q face and interface grids."""
     lin, prod = quasilinear_terms()
@@ -690,7 +690,7 @@ def jet_ball(x: np.ndarray) -> Jet:
 
 
 def diffusion_reaction_ball(nsub=(2, 2, 2), J=400, q=30, nbdy=30000, seed=0, R=1.0, test_per_dim=None) -> Problem:
-    """3-D steady diffusion-reaction on the unit ball (the paper's AMIPN example of Sec. 5):
+    """3-D steady diffusion-reaction on the unit ball (the paper's AMIPN example of Sec. 6.2):
     -div((1 + u^2) grad u) + (u^3 - u) + e^u = f, u* = (x^2 + y^2 + z^2) sin(pi x) sin(pi y) sin(pi z).
     The ball sits in [-1, 1]^3, split into nsub boxes; the q^3 grid points of each box and the q x q
     interface grids are kept where x^2 + y^2 + z^2 < 1; Dirichlet u* at nbdy Fibonacci points of the
@@ -746,7 +746,7 @@ GS2_F, GS2_K = 0.060, 0.062
 
 
 def gray_scott_nonlinear(nsub=(2, 2, 2), J=400, q=20, seed=0, R=1.0, F=GS2_F, k=GS2_K, test_per_dim=None) -> Problem:
-    """The paper's steady Gray-Scott system with solution-dependent diffusion (Sec. 5):
+    """The paper's steady Gray-Scott system with solution-dependent diffusion (Sec. 6.2):
     (1 + u^2) Lap u - u v^2 + F (1 - u) = f1, (1 + v^2) Lap v + u v^2 - (F + k) v = f2 on the unit cube,
     u* = sin(x(1 - x)) sin(y(1 - y)) e^z, v* = sin(pi x) sin(pi y) sin(pi z), Dirichlet u*, v*; the
     constant F of the first equation is carried by the data."""

@@ -86,3 +86,28 @@ def test_gray_scott_collocation_floor_on_one_box(lo, q):
     print(f"one box at {lo}, q = {q}: exact Newton IT {st.outer_iters}, relL2 {e}")
     assert st.status == "ok"
     assert np.all(e > 5e-5) and np.all(e < 2e-3)
+
+
+def test_floor_trajectories_are_rounding_sensitive():
+    """The oracle against itself on the coarse unit-ball case: AMIPN restarted from its second iterate and
+    from the same iterate perturbed by 1e-13 (relative, entrywise) takes a different number of steps and
+    ends 1e-3 apart -- the merit is flat at the floor (||D F|| unchanged to 7 digits from the second step
+    on).  Whole-solve trajectories are therefore compared only loosely; the parity bar is per step."""
+    prob = W.diffusion_reaction_ball(J=80, q=8, nbdy=600, test_per_dim=3)
+    oo = O.Opts(method="amipn", gamma=2.0, lsqr_tol=1e-10, m_max=3)
+    u, st = O.amipn(prob, opts=oo)
+    assert st.status == "ok"
+    r = np.array(st.resnorms[1:])
+    assert np.all(np.abs(r - r[0]) < 1e-6 * r[0])
+    k = 1
+    jac = 1 + sum(st.flags[:k + 1])
+    u1 = st.iterates[k]
+    up = u1 * (1 + 1e-13 * np.random.default_rng(5).normal(size=u1.size))
+    o2 = O.Opts(method="amipn", gamma=2.0, lsqr_tol=1e-10, m_max=3, jac_index0=jac)
+    ua, sa = O.amipn(prob, up, o2)
+    ub, sb = O.amipn(prob, u1, o2)
+    fa = O.eval_field(prob, ua, prob.test_x, prob.test_owner)
+    fb = O.eval_field(prob, ub, prob.test_x, prob.test_owner)
+    d = np.linalg.norm(fa - fb) / np.linalg.norm(fb)
+    print(f"restart from iterate {k + 1}: IT {sa.outer_iters} vs {sb.outer_iters}, fields {d:.2e} apart")
+    assert d > 1e-5

@@ -529,7 +529,7 @@ def test_count_sketch_preconditions():
 
 
 # ---------------------------------------------------------------------------
-# pointwise transcendental terms: Lap u - 100 u + 10 cosh(u) = f (Sec. 5, IPN vs AMIPN)
+# pointwise transcendental terms: Lap u - 100 u + 10 cosh(u) = f (Sec. 6.2, IPN vs AMIPN)
 # ---------------------------------------------------------------------------
 
 def test_cosh_data_matches_finite_differences():
@@ -590,7 +590,7 @@ def _flux_divergence(u, x, h=1e-3):
 
 
 def test_quasilinear_data_matches_the_flux_form():
-    """The data of the quasi-linear benchmark (Sec. 3.4): f = -div((1 + u*^2) grad u*), written out as
+    """The data of the quasi-linear benchmark (Sec. 3.2): f = -div((1 + u*^2) grad u*), written out as
     product terms, against central differences of the flux itself; also the jet of u* against central
     differences of u*."""
     prob = W.quasilinear(nsub=(2, 2, 2), J=4, q=5)
@@ -649,7 +649,7 @@ def test_quasilinear_problem_by_manufactured_solution():
 
 
 def test_ball_problem_data_and_geometry():
-    """The diffusion-reaction problem on the unit ball (Sec. 5): its data against central differences of
+    """The diffusion-reaction problem on the unit ball (Sec. 6.2): its data against central differences of
     the flux (1 + u*^2) grad u* plus u*^3 - u* + e^u*, every collocation and interface point inside the
     ball, the Dirichlet points on the unit sphere and owned by the box that holds them, no rows on the
     cube's faces, and the jet of u* against central differences."""
@@ -684,7 +684,7 @@ def test_ball_problem_by_manufactured_solution():
 
 
 def test_gray_scott_nonlinear_data_matches_finite_differences():
-    """The paper's Gray-Scott system with D = 1 + u^2, 1 + v^2 (Sec. 5): its data (the constant F of
+    """The paper's Gray-Scott system with D = 1 + u^2, 1 + v^2 (Sec. 6.2): its data (the constant F of
     the first equation carried by the data) against central differences of (u*, v*), and the jet."""
     prob = W.gray_scott_nonlinear(nsub=(2, 2, 2), J=4, q=5)
     g = prob.groups[2]
@@ -803,7 +803,7 @@ def test_smooth_pou_problem_by_manufactured_solution():
 
 
 def test_paper_allen_cahn_moving_hole_data_and_geometry():
-    """The paper's space-time Allen-Cahn problem with a moving hole (Sec. 5): data against central
+    """The paper's space-time Allen-Cahn problem with a moving hole (Sec. 6.3): data against central
     differences of u* (u_t - Lap_xy u + u^3 - u), no collocation point inside the hole, the hole's
     Dirichlet points on its moving circle, and the jet."""
     prob = W.allen_cahn_moving_hole(J=4, q=8)
