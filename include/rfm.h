@@ -70,7 +70,7 @@ typedef struct { int32_t eq; double coeff; int32_t pow[4]; } rfm_poly_term;
 
 /* One term coeff * f(u_comp) of equation eq with f one of the functions below:
  * the nonlinear part mu*N(u) for pointwise transcendental nonlinearities (the
- * cosh term of the 3-D Helmholtz problem of Sec. 5, e^u of the diffusion-reaction
+ * cosh term of the 3-D Helmholtz problem of Sec. 6.2, e^u of the diffusion-reaction
  * problems).  Its Jacobian contribution is coeff * f'(u_comp) phi. */
 typedef struct { int32_t eq, comp; double coeff; int32_t fn; } rfm_fn_term;
 enum { RFM_FN_COSH = 0, RFM_FN_SINH = 1, RFM_FN_EXP = 2 };
@@ -78,7 +78,7 @@ enum { RFM_FN_COSH = 0, RFM_FN_SINH = 1, RFM_FN_EXP = 2 };
 /* Product term coeff * prod_k (D_k u_{comp_k})^{pow_k} of equation eq, with D_k
  * a derivative selector RFM_D_* of the field: the quasi-linear operators of the
  * paper's benchmarks written out, e.g. -div((1 + u^2) grad u) = -Lap u
- * - u^2 Lap u - 2 u |grad u|^2 (Sec. 3.4, Sec. 5).  Its Jacobian contribution
+ * - u^2 Lap u - 2 u |grad u|^2 (Sec. 3.2, Sec. 6.2).  Its Jacobian contribution
  * is, by the product rule, sum_k coeff pow_k (D_k u)^{pow_k - 1} (the other
  * factors) D_k phi. */
 typedef struct { int32_t comp, deriv, pow; } rfm_factor;
@@ -144,7 +144,7 @@ rfm_status rfm_add_points(rfm_problem* p, int32_t kind, int64_t npts, const doub
 rfm_status rfm_set_operator(rfm_problem* p, const rfm_lin_term* lin, int32_t nlin,
                             const rfm_poly_term* nl, int32_t nnl);
 
-/* Pointwise terms coeff * f(u_comp) added to the operator (Sec. 2.1, Sec. 5):
+/* Pointwise terms coeff * f(u_comp) added to the operator (Sec. 2.1, Sec. 6.2):
  * replaces any earlier ones; at most 8 (n = 0 removes them).  eq and comp in
  * [0, ncomp), fn one of RFM_FN_*, finite coeff, else RFM_EINVAL / RFM_ENUMERIC.
  * Like rfm_set_operator it may be called again after rfm_finalize. */
@@ -171,6 +171,10 @@ rfm_status rfm_finalize(rfm_problem* p);
 
 int64_t rfm_num_unknowns(const rfm_problem* p);  /* n, or -1 before features are set */
 int64_t rfm_num_rows(const rfm_problem* p);      /* m (after rfm_finalize), else -1 */
+/* nnz(J): the values the block-sparse Jacobian stores, each row over the columns of the
+ * box (or boxes) its point touches (after rfm_finalize), else -1.  The algorithmic work
+ * of the sketch is 2 s nnz(J) flops and of one product J x or J^T y nnz(J) values read. */
+int64_t rfm_num_jacobian_values(const rfm_problem* p);
 
 /* ------------------------------------------------------------------------
  * Solver (Alg. 1 IPN, Alg. 2 AMIPN)
@@ -206,6 +210,9 @@ typedef struct {
                               of 128, at most 98,304), B is produced that many rows at a time and
                               each block folded into R (rfm_stage_sketch_qr_streamed).  Gaussian
                               sketches only. */
+  int32_t jac_index0;      /* index of the solve's first Jacobian evaluation (key word 1 of the
+                              sketch generator; later evaluations count up from it), so that a
+                              solve can be resumed from an iterate of another one; default 0 */
 } rfm_solve_opts;
 
 #define RFM_MAX_STEPS 64
@@ -218,10 +225,14 @@ typedef struct {
   double alphas[RFM_MAX_STEPS];
   double resnorms[RFM_MAX_STEPS];    /* ||D F|| after each step */
   double final_resnorm;
-  /* wall time per stage in seconds (HIP events on the problem's stream) */
+  /* wall time per stage in seconds: host clock around the stage, which ends by waiting for
+     the problem's stream (so each figure includes the launch overhead of its kernels) */
   double t_assemble, t_sketch, t_qr, t_lsqr, t_linesearch, t_total;
   int32_t status_detail;
   int32_t lsqr_fp64_fallback;        /* 1: lsqr_prec F32 was abandoned for FP64 during the solve */
+  int32_t inner_steps[RFM_MAX_STEPS]; /* Newton directions computed in each outer step (IPN: 1) */
+  int32_t flags[RFM_MAX_STEPS];      /* Alg. 2's Flag after each outer step: 1 = a fresh Jacobian and
+                                        preconditioner for the next one (IPN: always 1) */
 } rfm_solve_stats;
 
 /* Paper values: gamma 3, eta 1e-6, epsilon 1e-10, tau 1e-3, m_max 3, c 100 (Sec. 6). */
@@ -234,9 +245,19 @@ rfm_status rfm_solve(rfm_problem* p, const rfm_solve_opts* opts, double* u_inout
 /* Unscaled residual F(u) (F may be NULL) and ||F||_2. */
 rfm_status rfm_residual(rfm_problem* p, const double* u, double* F, double* norm);
 
-/* Field u_n(x) at npts points of given owner boxes: out [npts][ncomp]. */
+/* The random-feature field of coefficients u (Sec. 2.2) at npts points x [npts][dim]
+ * with their owner boxes owner [npts] (indicator partition: the box whose features
+ * represent the field there; smooth partition: any box whose support holds the
+ * point, the call sums over the boxes whose bump is non-zero at it).
+ *   what RFM_EVAL_VALUE: out [npts][ncomp] = u_n(x);
+ *   what RFM_EVAL_GRAD:  out [npts][ncomp][dim] = grad u_n(x), from
+ *                        d_a phi = (1 - t^2) w_a / sigma_a (and the product rule with
+ *                        the bump under the smooth partition); with the manufactured
+ *                        gradient this gives the H1 errors the experiments report.
+ * RFM_EINVAL for an owner outside [0, nbox) or another `what`, before device work. */
+enum { RFM_EVAL_VALUE = 0, RFM_EVAL_GRAD = 1 };
 rfm_status rfm_eval(rfm_problem* p, const double* u, int64_t npts, const double* x, const int32_t* owner,
-                    double* out);
+                    int32_t what, double* out);
 
 /* ------------------------------------------------------------------------
  * Stage calls.  Each runs one step of the per-Newton-step pipeline on the
@@ -408,24 +429,35 @@ rfm_status rfm_get_pde_points(rfm_problem* p, double* x, int32_t* owner);
 rfm_status rfm_project(rfm_problem* p, const rfm_solve_opts* opts, const double* values, double* u_out,
                        double* resnorm);
 
+/* The network inputs of one parameter draw at the problem's PDE points, in row
+ * order: X [npde][nparam + dim] (host or device) with row k = (encoded params, x_k).
+ * With param_lo and param_hi (each [nparam]) parameter j is encoded as
+ * 2 (params[j] - lo_j) / (hi_j - lo_j) - 1, so that a family's ranges map onto
+ * [-1, 1]; with both NULL the parameters are used as given.  RFM_EINVAL for only
+ * one of them, or a range with lo_j >= hi_j; RFM_ENUMERIC for a non-finite
+ * parameter.  Training sets and rfm_warm_start use the same encoding. */
+rfm_status rfm_warm_inputs(rfm_problem* p, const double* params, const double* param_lo, const double* param_hi,
+                           int32_t nparam, float* X);
+
 /* Initial coefficients from a network with in_dim = nparam + dim: its inputs
- * at PDE point x are (params[0..nparam), x), its outputs the ncomp field
- * values; they are projected by rfm_project.  u_out [n] gets the projected
- * coefficients if the solver's merit ||D0 F(u)|| is smaller there than at the
- * zero vector, else zeros (D0: the row scale of the Jacobian at u = 0, the
- * same for both).  info (or NULL) gets {||D0 F(projected)||, ||D0 F(0)||,
- * 1 if the projection was kept}.  Leaves the Jacobian at u = 0 as the
- * problem's current one. */
+ * at PDE point x are those of rfm_warm_inputs (encoded params, x), its outputs
+ * the ncomp field values; they are projected by rfm_project.  u_out [n] gets
+ * the projected coefficients if the solver's merit ||D0 F(u)|| is smaller there
+ * than at the zero vector, else zeros (D0: the row scale of the Jacobian at
+ * u = 0, the same for both).  info (or NULL) gets {||D0 F(projected)||,
+ * ||D0 F(0)||, 1 if the projection was kept}.  Leaves the Jacobian at u = 0 as
+ * the problem's current one. */
 rfm_status rfm_warm_start(rfm_problem* p, rfm_mlp* net, const rfm_solve_opts* opts, const double* params,
-                          int32_t nparam, double* u_out, double* info);
+                          const double* param_lo, const double* param_hi, int32_t nparam, double* u_out,
+                          double* info);
 
 /* ------------------------------------------------------------------------
  * Kernel timing.  While enabled, the main kernels are bracketed by HIP events
  * on the problem's stream; each record accumulates launches, seconds, and the
  * algorithmic floating-point operations and HBM bytes of those launches
- * (flops: 2 s nnz(J) for the sketch, 2 M N K for the QR products; bytes: the
- * stored Jacobian plus the vectors for J x and J^T y, the packed triangle of R
- * for a triangular solve).
+ * (flops: 2 s nnz(J) for every sketch, whatever the matrix cores issue for it,
+ * 2 M N K for the QR products; bytes: the stored Jacobian plus the vectors for
+ * J x and J^T y, the packed triangle of R for a triangular solve).
  * ---------------------------------------------------------------------- */
 typedef struct {
   char name[32];

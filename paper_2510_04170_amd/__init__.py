@@ -25,6 +25,7 @@ RFM_PREC_F64, RFM_PREC_F32, RFM_PREC_BF16, RFM_PREC_FP8 = 0, 1, 2, 3
 RFM_SKETCH_GAUSSIAN, RFM_SKETCH_COUNT = 0, 1
 RFM_FN_COSH, RFM_FN_SINH, RFM_FN_EXP = 0, 1, 2
 RFM_POU_INDICATOR, RFM_POU_SMOOTH = 0, 1
+RFM_EVAL_VALUE, RFM_EVAL_GRAD = 0, 1
 _FN_CODE = {"cosh": RFM_FN_COSH, "sinh": RFM_FN_SINH, "exp": RFM_FN_EXP}
 RFM_MAX_STEPS = 64
 
@@ -55,7 +56,7 @@ class rfm_solve_opts(C.Structure):
                 ("max_outer", C.c_int32), ("m_max", C.c_int32), ("tau_rel", C.c_double),
                 ("row_scale_c", C.c_double), ("gs_iters", C.c_int32), ("sketch_prec", C.c_int32),
                 ("lsqr_prec", C.c_int32), ("sketch_pieces", C.c_int32), ("sketch_kind", C.c_int32),
-                ("verbose", C.c_int32), ("sketch_rows_per_pass", C.c_int32)]
+                ("verbose", C.c_int32), ("sketch_rows_per_pass", C.c_int32), ("jac_index0", C.c_int32)]
 
 
 class rfm_solve_stats(C.Structure):
@@ -64,16 +65,19 @@ class rfm_solve_stats(C.Structure):
                 ("alphas", C.c_double * RFM_MAX_STEPS), ("resnorms", C.c_double * RFM_MAX_STEPS),
                 ("final_resnorm", C.c_double), ("t_assemble", C.c_double), ("t_sketch", C.c_double),
                 ("t_qr", C.c_double), ("t_lsqr", C.c_double), ("t_linesearch", C.c_double),
-                ("t_total", C.c_double), ("status_detail", C.c_int32), ("lsqr_fp64_fallback", C.c_int32)]
+                ("t_total", C.c_double), ("status_detail", C.c_int32), ("lsqr_fp64_fallback", C.c_int32),
+                ("inner_steps", C.c_int32 * RFM_MAX_STEPS), ("flags", C.c_int32 * RFM_MAX_STEPS)]
 
     def as_dict(self) -> dict:
         k = min(self.nsteps, RFM_MAX_STEPS)
+        ko = min(self.outer_iters, RFM_MAX_STEPS)
         return dict(outer_iters=self.outer_iters, jac_evals=self.jac_evals, lsqr_iters_total=self.lsqr_iters_total,
                     nsteps=self.nsteps, lsqr_iters=list(self.lsqr_iters[:k]), alphas=list(self.alphas[:k]),
                     resnorms=list(self.resnorms[:k]), final_resnorm=self.final_resnorm,
                     t_assemble=self.t_assemble, t_sketch=self.t_sketch, t_qr=self.t_qr, t_lsqr=self.t_lsqr,
                     t_linesearch=self.t_linesearch, t_total=self.t_total, status=self.status_detail,
-                    lsqr_fp64_fallback=self.lsqr_fp64_fallback)
+                    lsqr_fp64_fallback=self.lsqr_fp64_fallback, inner_steps=list(self.inner_steps[:ko]),
+                    flags=[bool(f) for f in self.flags[:ko]])
 
 
 class rfm_kernel_stat(C.Structure):
@@ -111,10 +115,11 @@ _SIGS = {
     "rfm_set_group_data": (C.c_int, [_P, C.c_int32, _D]),
     "rfm_num_unknowns": (C.c_int64, [_P]),
     "rfm_num_rows": (C.c_int64, [_P]),
+    "rfm_num_jacobian_values": (C.c_int64, [_P]),
     "rfm_solve_opts_default": (None, [C.POINTER(rfm_solve_opts)]),
     "rfm_solve": (C.c_int, [_P, C.POINTER(rfm_solve_opts), _D, C.POINTER(rfm_solve_stats)]),
     "rfm_residual": (C.c_int, [_P, _D, _D, C.POINTER(C.c_double)]),
-    "rfm_eval": (C.c_int, [_P, _D, C.c_int64, _D, _D, _D]),
+    "rfm_eval": (C.c_int, [_P, _D, C.c_int64, _D, _D, C.c_int32, _D]),
     "rfm_stage_assemble": (C.c_int, [_P, _D, C.c_double]),
     "rfm_get_scaled_residual": (C.c_int, [_P, _D]),
     "rfm_get_row_scale": (C.c_int, [_P, _D]),
@@ -152,7 +157,8 @@ _SIGS = {
     "rfm_num_pde_points": (C.c_int64, [_P]),
     "rfm_get_pde_points": (C.c_int, [_P, _D, C.c_void_p]),
     "rfm_project": (C.c_int, [_P, C.POINTER(rfm_solve_opts), _D, _D, C.POINTER(C.c_double)]),
-    "rfm_warm_start": (C.c_int, [_P, _P, C.POINTER(rfm_solve_opts), _D, C.c_int32, _D, _D]),
+    "rfm_warm_inputs": (C.c_int, [_P, _D, _D, _D, C.c_int32, C.c_void_p]),
+    "rfm_warm_start": (C.c_int, [_P, _P, C.POINTER(rfm_solve_opts), _D, _D, _D, C.c_int32, _D, _D]),
     "rfm_profile_enable": (C.c_int, [_P, C.c_int32]),
     "rfm_profile_read": (C.c_int32, [_P, C.POINTER(rfm_kernel_stat), C.c_int32]),
 }
@@ -380,6 +386,11 @@ class RfmProblem:
     def m(self) -> int:
         return int(lib().rfm_num_rows(self.h))
 
+    @property
+    def nnz(self) -> int:
+        """Values the block-sparse Jacobian stores (nnz(J))."""
+        return int(lib().rfm_num_jacobian_values(self.h))
+
     # -- solver ------------------------------------------------------------------
     def solve(self, u0=None, opts: Optional[rfm_solve_opts] = None):
         """Returns (u, stats dict, status).  u0 may be a numpy array or a device tensor
@@ -398,11 +409,23 @@ class RfmProblem:
         return F, nrm.value
 
     def eval(self, u, x, owner) -> np.ndarray:
+        """Field values [npts, ncomp]."""
         x = _f64(x)
         ow = np.ascontiguousarray(owner, dtype=np.int32)
         out = np.zeros((x.shape[0], self.ncomp))
         uu = u if hasattr(u, "data_ptr") else _f64(u)
-        _check(lib().rfm_eval(self.h, _ptr(uu)[0], x.shape[0], x.ctypes.data, ow.ctypes.data, out.ctypes.data))
+        _check(lib().rfm_eval(self.h, _ptr(uu)[0], x.shape[0], x.ctypes.data, ow.ctypes.data, RFM_EVAL_VALUE,
+                              out.ctypes.data))
+        return out
+
+    def eval_grad(self, u, x, owner) -> np.ndarray:
+        """Field gradients [npts, ncomp, dim]."""
+        x = _f64(x)
+        ow = np.ascontiguousarray(owner, dtype=np.int32)
+        out = np.zeros((x.shape[0], self.ncomp, self.dim))
+        uu = u if hasattr(u, "data_ptr") else _f64(u)
+        _check(lib().rfm_eval(self.h, _ptr(uu)[0], x.shape[0], x.ctypes.data, ow.ctypes.data, RFM_EVAL_GRAD,
+                              out.ctypes.data))
         return out
 
     # -- stages ------------------------------------------------------------------
@@ -515,14 +538,29 @@ class RfmProblem:
         _check(lib().rfm_project(self.h, C.byref(opts), values.ctypes.data, u.ctypes.data, C.byref(rn)))
         return u, rn.value
 
-    def warm_start(self, net: "RfmMLP", params, opts=None):
+    def warm_inputs(self, params, lo=None, hi=None) -> np.ndarray:
+        """Network inputs [npde, nparam + dim] of one parameter draw (params encoded onto [-1, 1] over
+        [lo, hi] when the ranges are given)."""
+        params = _f64(params)
+        lo = None if lo is None else _f64(lo)
+        hi = None if hi is None else _f64(hi)
+        k = int(lib().rfm_num_pde_points(self.h))
+        X = np.zeros((k, params.size + self.dim), np.float32)
+        _check(lib().rfm_warm_inputs(self.h, params.ctypes.data, None if lo is None else lo.ctypes.data,
+                                     None if hi is None else hi.ctypes.data, params.size, X.ctypes.data))
+        return X
+
+    def warm_start(self, net: "RfmMLP", params, opts=None, lo=None, hi=None):
         """(u0, info): info = (||F(projection)||, ||F(0)||, kept)."""
         params = _f64(params)
+        lo = None if lo is None else _f64(lo)
+        hi = None if hi is None else _f64(hi)
         opts = opts or default_opts()
         u = np.zeros(self.n)
         info = np.zeros(3)
-        _check(lib().rfm_warm_start(self.h, net.h, C.byref(opts), params.ctypes.data, params.size, u.ctypes.data,
-                                    info.ctypes.data))
+        _check(lib().rfm_warm_start(self.h, net.h, C.byref(opts), params.ctypes.data,
+                                    None if lo is None else lo.ctypes.data, None if hi is None else hi.ctypes.data,
+                                    params.size, u.ctypes.data, info.ctypes.data))
         return u, info
 
     def profile_enable(self, on: bool = True):

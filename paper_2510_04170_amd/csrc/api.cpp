@@ -790,6 +790,12 @@ int64_t rfm_num_rows(const rfm_problem* p) {
   return P.finalized ? P.m : -1;
 }
 
+int64_t rfm_num_jacobian_values(const rfm_problem* p) {
+  if (!p) return -1;
+  const Problem& P = *reinterpret_cast<const Problem*>(p);
+  return P.finalized ? P.nvals : -1;
+}
+
 rfm_status rfm_stage_count_sketch(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index) {
   return guarded([&] {
     Problem& P = ready(p);
@@ -1062,10 +1068,10 @@ rfm_status rfm_residual(rfm_problem* p, const double* u, double* F, double* norm
 }
 
 rfm_status rfm_eval(rfm_problem* p, const double* u, int64_t npts, const double* x, const int32_t* owner,
-                    double* out) {
+                    int32_t what, double* out) {
   return guarded_rc([&] {
     RFM_CHECK(u != nullptr, RFM_EINVAL, "rfm_eval: u is NULL");
-    return api_eval(ready(p), u, npts, x, owner, out);
+    return api_eval(ready(p), u, npts, x, owner, what, out);
   });
 }
 

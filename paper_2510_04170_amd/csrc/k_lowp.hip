@@ -434,8 +434,9 @@ void launch_sketch_lowp_rows(Problem& P, uint64_t seed, uint64_t jac_index, int 
   const double ks = prec == RFM_PREC_BF16 ? 32.0 : 4.0;
   const double inv_scale = 1.0 / (ks * std::sqrt((double)P.s));
   const int64_t per_piece = P.nslots * (int64_t)P.J * 32;
-  // algorithmic work: every piece against S on the padded row chunks; bytes: pieces once, B once
-  const double flops = 2.0 * (double)nr * (double)per_piece * npc;
+  // algorithmic work 2 s nnz(J) (the matrix cores issue every piece on the padded row chunks on top of it);
+  // bytes: pieces once, B once
+  const double flops = 2.0 * (double)nr * (double)P.nvals;
   const double bytes = (prec == RFM_PREC_BF16 ? 2.0 : 1.0) * npc * (double)per_piece + 8.0 * (double)nr * P.n;
   if (prec == RFM_PREC_BF16) {
     ProfScope ps(P.prof, P.stream, "sketch_bf16", flops, bytes);

@@ -6,6 +6,7 @@
 // (feature j on lane j mod 64), so every value of the row is produced and
 // written by consecutive lanes and the row's reductions (field values, the
 // maximum for the scale, the dot products) are wavefront reductions.
+
 #include "rfm_internal.h"
 
 namespace rfm {
@@ -819,7 +820,9 @@ __global__ void __launch_bounds__(256) k_row_eval_smooth(RowsCtx C, const TileDe
   }
 }
 
-// u_n(x) with the smooth partition: the owner's neighbours whose support holds x
+// u_n(x) (GRAD: its gradient, out [npts][ncomp][dim]) with the smooth partition: the owner's neighbours
+// whose support holds x; d_a (psi phi) = psi d_a phi + phi d_a psi
+template <bool GRAD>
 __global__ void __launch_bounds__(256) k_eval_points_smooth(RowsCtx C, int64_t npts, const double* __restrict__ x,
                                                             const int32_t* __restrict__ owner,
                                                             const double* __restrict__ u, double* __restrict__ out) {
@@ -838,6 +841,7 @@ __global__ void __launch_bounds__(256) k_eval_points_smooth(RowsCtx C, int64_t n
     if (a < dim) rem /= C.g.nsub[a];
   }
   double acc[kMaxComp] = {0, 0, 0, 0};
+  double accg[kMaxComp][kMaxDim] = {};
   int ncand = 1;
   for (int a = 0; a < dim; ++a) ncand *= 3;
   for (int k = 0; k < ncand; ++k) {
@@ -857,16 +861,42 @@ __global__ void __launch_bounds__(256) k_eval_points_smooth(RowsCtx C, int64_t n
     if (P.psi == 0.0) continue;
     for (int c = 0; c < K; ++c) {
       const int64_t fb = ((int64_t)e * K + c) * J;
-      double s = 0.0;
-      for (int j = lane; j < J; j += kWave) s += feat_t(C, fb + j, P.l) * u[fb + j];
+      double s = 0.0, sg[kMaxDim] = {};
+      for (int j = lane; j < J; j += kWave) {
+        const double t = feat_t(C, fb + j, P.l);
+        s += t * u[fb + j];
+        if (GRAD) {
+          const double w = (1.0 - t * t) * u[fb + j];
+#pragma unroll
+          for (int a = 0; a < kMaxDim; ++a)
+            if (a < dim) sg[a] += C.f.WS[a][fb + j] * w;
+        }
+      }
 #pragma unroll
       for (int q = 0; q < kMaxComp; ++q)
-        if (q == c) acc[q] += P.psi * s;
+        if (q == c) {
+          acc[q] += P.psi * s;
+          if (GRAD) {
+#pragma unroll
+            for (int a = 0; a < kMaxDim; ++a) accg[q][a] += P.psi * sg[a] + P.g[a] * s;
+          }
+        }
     }
   }
-  for (int c = 0; c < K; ++c) {
-    const double v = wave_sum(acc[c]);
-    if (lane == 0) out[p * K + c] = v;
+#pragma unroll
+  for (int c = 0; c < kMaxComp; ++c) {
+    if (c >= K) continue;
+    if (GRAD) {
+#pragma unroll
+      for (int a = 0; a < kMaxDim; ++a) {
+        if (a >= dim) continue;
+        const double v = wave_sum(accg[c][a]);
+        if (lane == 0) out[(p * K + c) * dim + a] = v;
+      }
+    } else {
+      const double v = wave_sum(acc[c]);
+      if (lane == 0) out[p * K + c] = v;
+    }
   }
 }
 
@@ -1042,7 +1072,9 @@ __global__ void __launch_bounds__(kRedBlock) k_reduce_sum(const double* __restri
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
-// u_n(x) at arbitrary points, one wavefront per point
+// u_n(x) at arbitrary points, one wavefront per point (GRAD: the gradient, out [npts][ncomp][dim], from
+// d_a phi = (1 - t^2) w_a / sigma_a)
+template <bool GRAD>
 __global__ void __launch_bounds__(256) k_eval_points(RowsCtx C, int64_t npts, const double* __restrict__ x,
                                                      const int32_t* __restrict__ owner,
                                                      const double* __restrict__ u, double* __restrict__ out) {
@@ -1057,10 +1089,27 @@ __global__ void __launch_bounds__(256) k_eval_points(RowsCtx C, int64_t npts, co
   norm_coords(C.g, e, xx, l);
   for (int c = 0; c < K; ++c) {
     const int64_t fb = ((int64_t)e * K + c) * J;
-    double acc = 0.0;
-    for (int j = lane; j < J; j += kWave) acc += feat_t(C, fb + j, l) * u[fb + j];
-    acc = wave_sum(acc);
-    if (lane == 0) out[p * K + c] = acc;
+    if (GRAD) {
+      double g[kMaxDim] = {};
+      for (int j = lane; j < J; j += kWave) {
+        const double t = feat_t(C, fb + j, l);
+        const double w = (1.0 - t * t) * u[fb + j];
+#pragma unroll
+        for (int a = 0; a < kMaxDim; ++a)
+          if (a < dim) g[a] += C.f.WS[a][fb + j] * w;
+      }
+#pragma unroll
+      for (int a = 0; a < kMaxDim; ++a) {
+        if (a >= dim) continue;
+        const double v = wave_sum(g[a]);
+        if (lane == 0) out[(p * K + c) * dim + a] = v;
+      }
+    } else {
+      double acc = 0.0;
+      for (int j = lane; j < J; j += kWave) acc += feat_t(C, fb + j, l) * u[fb + j];
+      acc = wave_sum(acc);
+      if (lane == 0) out[p * K + c] = acc;
+    }
   }
 }
 
@@ -1068,33 +1117,121 @@ __global__ void __launch_bounds__(256) k_eval_points(RowsCtx C, int64_t npts, co
 // block-sparse products on the stored (scaled) Jacobian
 // ---------------------------------------------------------------------------
 
+// Block-sparse products, one 64-row tile per workgroup (four wavefronts).  A tile's values are one
+// contiguous row-major block (nrows x w).  When w and the tile's offset are multiples of the 16-byte
+// vector (4 FP32 or 2 FP64 values) and w <= 1024, every lane owns fixed 16-byte
+// column slices of the row (vector k of lane l starts at value (64 k + l) VEC): it reads its slices
+// of each row with one 16-byte load per slice, keeps the matching x values (J x) or partial column
+// sums (J^T y) in registers across the tile's rows, and the cross-lane work is done once per tile
+// through LDS.  Other tiles (odd widths, rows wider than the register budget) take the plain loops.
+constexpr int kVecWidth = 1024;  // widest row on the vector path
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  static constexpr int N = 4;
+  static constexpr int K = kVecWidth / (64 * 4);  // 16-byte slices per lane and row
+  __device__ static void load(const float* p, double* o) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
+template <>
+struct Vec16<double> {
+  static constexpr int N = 2;
+  static constexpr int K = kVecWidth / (64 * 2);
+  __device__ static void load(const double* p, double* o) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ bool tile_vector_path(const TileDesc& td, int w) {
+  constexpr int V = Vec16<T>::N;
+  return w % V == 0 && td.val_off % V == 0 && w <= kVecWidth;
+}
+
 // y[r] = sum_p J[r,p] x[col(p)] - ucoef * uprev[r];  optional ||y||^2 partial per tile;
-// ucoef = alpha/beta is read from the LSQR state when st != null
+// ucoef = alpha/beta is read from the LSQR state when st != null.  Wavefront wv of the tile's
+// workgroup takes rows wv, wv + 4, ...: every lane reads its 16-byte slices of those rows (the loads
+// of all of them can be in flight together), and the row sums are wavefront reductions at the end.
 template <typename T>
 __global__ void __launch_bounds__(256) k_jmul(const TileDesc* __restrict__ tiles, const T* __restrict__ Jv,
                                               const double* __restrict__ x, double* __restrict__ y,
                                               const double* __restrict__ uprev, const LsqrState* __restrict__ st,
                                               double* __restrict__ partial) {
   if (st && st->done) return;
+  constexpr int V = Vec16<T>::N, NK = Vec16<T>::K;
+  constexpr int RPW = kTileRows / kRowsPerBlock;  // rows per wavefront
   __shared__ double sh[kRowsPerBlock];
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const TileDesc td = tiles[blockIdx.x];
   const int w = td.wA + td.wB;
+  const int32_t* seg_col = tiles[blockIdx.x].seg_col;  // run-time index: read from memory
   const double uc = st ? st->alpha * st->inv_beta : 0.0;  // x arrives already scaled by 1/alpha
-  double nrm = 0.0;
-  for (int rr = wv; rr < td.nrows; rr += kRowsPerBlock) {
-    const T* row = Jv + td.val_off + (int64_t)rr * w;
-    double acc = 0.0;
-    for (int sg = 0; sg < td.nseg; ++sg) {
-      const T* rs = row + sg * td.wseg;
-      const double* xs = x + tiles[blockIdx.x].seg_col[sg];  // run-time index: read from memory
-      for (int p = lane; p < td.wseg; p += kWave) acc += (double)rs[p] * xs[p];
+  const T* tile = Jv + td.val_off;
+  double acc[RPW];
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) acc[j] = 0.0;
+  if (tile_vector_path<T>(td, w)) {
+    // this lane's x values: column slices k = 0 .. NK - 1
+    double xv[NK][V];
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int pos = (k * kWave + lane) * V + v;
+        xv[k][v] = pos < w ? x[seg_col[pos / td.wseg] + pos % td.wseg] : 0.0;
+      }
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+      const int rr = wv + kRowsPerBlock * j;
+      if (rr < td.nrows) {
+        const T* row = tile + (int64_t)rr * w;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          const int pos = (k * kWave + lane) * V;
+          if (pos < w) {
+            double val[V];
+            Vec16<T>::load(row + pos, val);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[j] += val[v] * xv[k][v];
+          }
+        }
+      }
     }
-    acc = wave_sum(acc);
-    const int64_t r = td.row0 + rr;
-    if (uprev) acc -= uc * uprev[r];
-    if (lane == 0) y[r] = acc;
-    nrm += acc * acc;
+  } else {
+    for (int j = 0; j < RPW; ++j) {
+      const int rr = wv + kRowsPerBlock * j;
+      if (rr < td.nrows) {
+        const T* row = tile + (int64_t)rr * w;
+        double a = 0.0;
+        for (int sg = 0; sg < td.nseg; ++sg) {
+          const T* rs = row + sg * td.wseg;
+          const double* xs = x + seg_col[sg];
+          for (int p = lane; p < td.wseg; p += kWave) a += (double)rs[p] * xs[p];
+        }
+        acc[j] = a;
+      }
+    }
+  }
+  double nrm = 0.0;
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) {
+    const int rr = wv + kRowsPerBlock * j;
+    double v = wave_sum(acc[j]);
+    if (rr < td.nrows) {
+      const int64_t r = td.row0 + rr;
+      if (uprev) v -= uc * uprev[r];
+      if (lane == 0) y[r] = v;
+      nrm += v * v;
+    }
   }
   if (partial) {
     if (lane == 0) sh[wv] = nrm;
@@ -1103,23 +1240,56 @@ __global__ void __launch_bounds__(256) k_jmul(const TileDesc* __restrict__ tiles
   }
 }
 
-// part[tile slot + p] = sum_{rows} J[r,p] y[r] * yscale
+// part[tile slot + p] = sum_{rows} J[r,p] y[r] * yscale.  One wavefront per (tile, 16-byte column
+// slice of 64 lanes): each lane sums its slice over the tile's rows, reading one 16-byte piece per row,
+// with y of row r broadcast from lane r; no cross-lane work.  Tiles off the vector path are done by the
+// first wavefront of the tile with the plain loop.
 template <typename T>
-__global__ void __launch_bounds__(256) k_jtmul_tiles(const TileDesc* __restrict__ tiles,
-                                                     const T* __restrict__ Jv, const double* __restrict__ y,
-                                                     const LsqrState* __restrict__ st, double* __restrict__ part) {
+__global__ void __launch_bounds__(kWave) k_jtmul_tiles(const TileDesc* __restrict__ tiles,
+                                                       const T* __restrict__ Jv, const double* __restrict__ y,
+                                                       const LsqrState* __restrict__ st, double* __restrict__ part) {
   if (st && st->done) return;
-  __shared__ double ys[kTileRows];
-  const TileDesc td = tiles[blockIdx.x];
+  constexpr int V = Vec16<T>::N, NK = Vec16<T>::K;
+  const int t = blockIdx.x / NK, k = blockIdx.x % NK;
+  const int lane = threadIdx.x;
+  const TileDesc td = tiles[t];
   const int w = td.wA + td.wB;
   const double ysc = st ? st->inv_beta : 1.0;
-  if (threadIdx.x < td.nrows) ys[threadIdx.x] = y[td.row0 + threadIdx.x] * ysc;
-  __syncthreads();
-  for (int p = threadIdx.x; p < w; p += blockDim.x) {
-    double acc = 0.0;
-    const T* col = Jv + td.val_off + p;
-    for (int rr = 0; rr < td.nrows; ++rr) acc += (double)col[(int64_t)rr * w] * ys[rr];
-    part[td.part_off + p] = acc;
+  const T* tile = Jv + td.val_off;
+  const double yl = lane < td.nrows ? y[td.row0 + lane] * ysc : 0.0;  // lane r holds row r's y
+  if (tile_vector_path<T>(td, w)) {
+    const int pos = (k * kWave + lane) * V;
+    if (k * kWave * V >= w) return;  // this slice lies past the row
+    double acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = 0.0;
+    const bool in = pos < w;
+#pragma unroll 16
+    for (int rr = 0; rr < td.nrows; ++rr) {
+      const double yr = __shfl(yl, rr, kWave);
+      if (in) {
+        double val[V];
+        Vec16<T>::load(tile + (int64_t)rr * w + pos, val);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] += val[v] * yr;
+      }
+    }
+    if (in) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) part[td.part_off + pos + v] = acc[v];
+    }
+  } else {
+    if (k != 0) return;
+    // lanes leave the column loop at different times: y goes through LDS, not through lane exchanges
+    __shared__ double ys[kTileRows];
+    ys[lane] = yl;
+    __syncthreads();
+    for (int p = lane; p < w; p += kWave) {
+      double acc = 0.0;
+      const T* col = tile + p;
+      for (int rr = 0; rr < td.nrows; ++rr) acc += (double)col[(int64_t)rr * w] * ys[rr];
+      part[td.part_off + p] = acc;
+    }
   }
 }
 
@@ -1241,14 +1411,21 @@ void launch_reduce_sum(Problem& P, const double* partials, int nparts, double* o
 }
 
 void launch_eval_points(Problem& P, const double* u, int64_t npts, const double* x, const int32_t* owner,
-                        double* out) {
+                        double* out, bool grad) {
   if (npts == 0) return;
   RowsCtx C = make_ctx(P);
   dim3 grid((unsigned)((npts + kRowsPerBlock - 1) / kRowsPerBlock));
-  if (P.geom.pou == RFM_POU_SMOOTH)
-    hipLaunchKernelGGL(k_eval_points_smooth, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
-  else
-    hipLaunchKernelGGL(k_eval_points, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
+  if (P.geom.pou == RFM_POU_SMOOTH) {
+    if (grad)
+      hipLaunchKernelGGL(k_eval_points_smooth<true>, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
+    else
+      hipLaunchKernelGGL(k_eval_points_smooth<false>, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
+  } else {
+    if (grad)
+      hipLaunchKernelGGL(k_eval_points<true>, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
+    else
+      hipLaunchKernelGGL(k_eval_points<false>, grid, dim3(256), 0, P.stream, C, npts, x, owner, u, out);
+  }
   RFM_HIP(hipGetLastError());
 }
 
@@ -1276,7 +1453,8 @@ template <typename T>
 static void jtmul_impl(Problem& P, const T* J, const double* y, double* x, const LsqrState* st) {
   ProfScope ps(P.prof, P.stream, sizeof(T) == 8 ? "jtmul" : "jtmul_f32", 2.0 * P.nvals,
                sizeof(T) * (double)P.nvals + 8.0 * (P.m + P.n));
-  hipLaunchKernelGGL(k_jtmul_tiles<T>, dim3(P.ntiles), dim3(256), 0, P.stream, P.d_tiles.p, J, y, st, P.d_part.p);
+  hipLaunchKernelGGL(k_jtmul_tiles<T>, dim3((unsigned)(P.ntiles * Vec16<T>::K)), dim3(kWave), 0, P.stream,
+                     P.d_tiles.p, J, y, st, P.d_part.p);
   hipLaunchKernelGGL(k_jtmul_reduce, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, P.stream, P.d_tiles.p,
                      P.d_cb_ptr.p, P.d_cb_tile.p, P.d_cb_off.p, P.J, P.n, P.d_part.p, st, x);
   RFM_HIP(hipGetLastError());

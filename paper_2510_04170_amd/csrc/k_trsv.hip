@@ -9,28 +9,33 @@
 //    solved in LDS, so no step of the chain waits for another workgroup's
 //    stores: per block it applies the kLook = 2 tiles next to the diagonal,
 //    subtracts the helpers' partial sum for the block, solves the 64 x 64
-//    diagonal tile by substitution in LDS and publishes the block (data, then a
-//    flag).  Its eight wavefronts: 0 solves and publishes, with its row of the
+//    diagonal tile by substitution in LDS and publishes the block.  Its eight wavefronts: 0 solves and publishes, with its row of the
 //    diagonal tile in registers (the substitution is the chain's longest part);
 //    1-3 and 4-6 are two sets that hold the two off-diagonal tiles and the
 //    diagonal tile of even and odd steps in registers, each set loading its next
 //    step two steps ahead.  Only the product with the block solved last is left
 //    between two substitutions: the product with the block before it and the
 //    diagonal tile's copy to LDS are done a step early.  Wavefront 7 fetches the
-//    helper partial of the next step (alone, so that its polls do not wait
+//    helper partial of the next step (alone, so that its reads do not wait
 //    behind tile loads).
 //  * Ticket t >= 1 is the helper of block t-th in chain order: it streams the
 //    rest of that block's row (R) or column (R^T) of tiles as the solver
 //    publishes the blocks they multiply, and publishes the partial sum.  It
 //    needs blocks up to kLook + 1 steps behind the one it serves, so the solver
 //    finds the partial ready.
-// Published data and flags are written and read with device-scope relaxed
-// atomics (coherent across the XCDs' L2s); a writer waits for its data stores
-// to be acknowledged before it stores the flag, and flags hold the epoch of
-// the launch.  Workgroups only wait for work of smaller tickets (the solver
-// waits for helpers of blocks whose dependencies it has already published,
-// and helpers start in the order the solver needs them), so the launch always
-// drains; a spin limit turns a lost flag into an error instead of a hang.
+// Published data are written and read with device-scope relaxed atomics
+// (coherent across the XCDs' L2s), and every published value carries its own
+// ready state: a fill kernel sets every slot of the blocks of x and of the
+// helpers' partial sums to a signalling-NaN pattern that no result has (a NaN
+// result is stored as the canonical quiet NaN) before the launch; a writer
+// stores its values and moves on -- no wait for the stores to be acknowledged,
+// no flag -- and a reader takes a block once none of its 64 slots holds the
+// pattern.  The solver reads the next step's partial a phase before it needs
+// it, so one round trip to memory per step is hidden behind the substitution.
+// Workgroups only wait for work of smaller tickets (the solver waits for
+// helpers of blocks whose dependencies it has already published, and helpers
+// start in the order the solver needs them), so the launch always drains; a
+// spin limit turns a lost value into an error instead of a hang.
 //
 // Optional fusion for LSQR: out = yscale-scaled solve minus coef * sub, and a
 // per-block partial of ||out||^2.
@@ -43,10 +48,9 @@ namespace {
 constexpr int kTB = 64;
 constexpr int kSpinLimit = 1 << 26;
 constexpr int kLook = 2;   // off-diagonal tiles next to the diagonal applied by the solver
-constexpr int kBatch = 8;  // helper: flags polled per round trip
-// sync words used here: [8] ticket counter, [9] error flag, [kXFlags + b] block b of x published,
-// [kXFlags + nb + b] helper partial of block b published (past the QR's grid-barrier words)
-enum { kTicket = 8, kTrsvErr = 9, kXFlags = 2048 };
+constexpr int kBatch = 8;  // helper: upcoming blocks read per round trip
+// sync words used here: [8] ticket counter, [9] error flag
+enum { kTicket = 8, kTrsvErr = 9 };
 
 __device__ __forceinline__ const double* tile_ptr(const double* Rt, int bi, int bj) {
   return Rt + ((size_t)bj * (bj + 1) / 2 + bi) * kTB * kTB;
@@ -61,31 +65,23 @@ __device__ __forceinline__ void st_dev(double* p, double v) {
 __device__ __forceinline__ int ld_flag(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void stores_done() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+// an empty slot of a published block of x: a signalling-NaN bit pattern no result takes
+constexpr uint64_t kEmpty = 0x7FF4F00DDEADBEEFull;
+__device__ __forceinline__ double canon(double v) {  // a NaN result becomes the canonical quiet NaN
+  return v != v ? __longlong_as_double(0x7FF8000000000000ll) : v;
 }
+__device__ __forceinline__ bool filled(double v) { return (uint64_t)__double_as_longlong(v) != kEmpty; }
+
+__global__ void __launch_bounds__(256) k_trsv_clear(double* __restrict__ z, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) z[i] = __longlong_as_double((long long)kEmpty);
+}
+
 __device__ __forceinline__ double bcast(double v, int k) {
   const unsigned long long b = __double_as_longlong(v);
   const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, k);
   const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), k);
   return __longlong_as_double(((unsigned long long)hi << 32) | lo);
-}
-
-// Wait (one wavefront) until flag == epoch; false when the spin limit or another
-// workgroup's error ends the wait.
-__device__ bool wait_flag(const int32_t* flag, int32_t* sync, int32_t epoch) {
-  int spins = 0;
-  while (ld_flag(flag) != epoch) {
-    __builtin_amdgcn_s_sleep(1);
-    if ((++spins & 1023) == 0 && ld_flag(&sync[kTrsvErr]) != 0) return false;
-    if (spins > kSpinLimit) {
-      __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-  }
-  return true;
 }
 
 // mode 0: R x = y   (chain from the last block up)
@@ -96,7 +92,7 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
                                               double* __restrict__ pz, double* __restrict__ out,
                                               const double* __restrict__ sub, const LsqrState* __restrict__ st,
                                               int yscale_sel, int sub_sel, double* __restrict__ partial,
-                                              int32_t* __restrict__ sync, int32_t epoch) {
+                                              int32_t* __restrict__ sync) {
   if (st && st->done) return;
   __shared__ int tk_sh;
   __shared__ double Dt[2][kTB][kTB + 1];  // solver: diagonal tiles of even and odd steps, [row][col], diagonal zeroed
@@ -117,8 +113,6 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
   const int ticket = tk_sh;
   constexpr int d = MODE == 0 ? 1 : -1;  // step from a block to the one solved just before it
   auto blk = [&](int step) { return MODE == 0 ? nbk - 1 - step : step; };
-  int32_t* xflag = sync + kXFlags;
-  int32_t* pflag = sync + kXFlags + nbk;
 
   if (ticket == 0) {
     // ------------------------------------------------------------------ solver
@@ -154,11 +148,23 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
         for (int c = 0; c < kTB; ++c) tv[c] = T[c * kTB + lane];
       }
     };
-    auto fetch_partial = [&](int step) {  // wavefront 7
-      const int i = blk(step);
-      wait_flag(&pflag[i], sync, epoch);
-      pzs[step & 1][lane] = ld_dev(&pz[(size_t)i * kTB + lane]);
+    // wavefront 7: the helper partial of `step`, a value that is its own ready state; pv holds the
+    // first read (issued a phase earlier), re-read until all 64 slots are filled
+    auto finish_partial = [&](int step, double pv) {
+      const double* src = &pz[(size_t)blk(step) * kTB + lane];
+      int spins = 0;
+      while (__ballot(filled(pv)) != ~0ull) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 1023) == 0 && ld_flag(&sync[kTrsvErr]) != 0) break;
+        if (spins > kSpinLimit) {
+          __hip_atomic_store(&sync[kTrsvErr], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        pv = ld_dev(src);
+      }
+      pzs[step & 1][lane] = pv;
     };
+    double pnext = 0.0;  // wavefront 7: the next step's partial, in flight
     // tile (registers) times a block of x (LDS, read by every lane): the block is read 16 values
     // at a time into registers of their own so that the reads overlap
     auto tile_times = [&](const double* xv) {
@@ -190,45 +196,77 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
       }
       dg[step & 1][lane] = d;
     };
-    double yv = 0.0, sv = 0.0;
+    // wavefront 0: y (and sub) of the next kYAhead blocks in a register queue, each read kYAhead steps
+    // before its block is solved (the helpers keep the memory system busy, so one step is not always
+    // enough for a read to return)
+    constexpr int kYAhead = 4;
+    double yq[kYAhead], sq[kYAhead];
+    auto read_y = [&](int step, double& yv, double& sv) {
+      const int row = step < nbk ? blk(step) * kTB + lane : n;
+      yv = row < n ? y[row] : 0.0;
+      sv = (sub && row < n) ? sub[row] : 0.0;
+    };
+    // wavefront 0: the row (mode 0) or column (mode 1) `lane` of a step's diagonal tile from LDS into
+    // registers, divided by its diagonal entry, the entry itself dropped: each unknown is then final
+    // when its turn comes, and one FMA per step updates every lane (lanes already solved, and the
+    // pivot lane, multiply a zero)
+    double rd = 0.0;
+    auto prepare_row = [&](int step) {
+      const int b = step & 1;
+#pragma unroll
+      for (int k = 0; k < kTB; ++k) tv[k] = MODE == 0 ? Dt[b][lane][k] : Dt[b][k][lane];
+      rd = 1.0 / dg[b][lane];
+#pragma unroll
+      for (int k = 0; k < kTB; ++k) tv[k] *= rd;
+    };
     if (wv == 0) {
       xl[0][lane] = 0.0;
       xl[1][lane] = 0.0;
-      // y (and sub) of the first block; later blocks are prefetched one step ahead
-      const int row = blk(0) * kTB + lane;
-      yv = row < n ? y[row] : 0.0;
-      sv = (sub && row < n) ? sub[row] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kYAhead; ++q) read_y(q, yq[q], sq[q]);
     } else if (tile_wave) {
       if (set < nbk) load_tiles(set);
     } else {
-      fetch_partial(0);
+      finish_partial(0, ld_dev(&pz[(size_t)blk(0) * kTB + lane]));
     }
     __syncthreads();
-    // step 0 has no earlier blocks: only its diagonal tile
-    if (tile_wave && set == 0 && role == 1) red2[0][lane] = 0.0;
-    if (tile_wave && set == 0 && role == 2) diag_to_lds(0);
+    // step 0 has no earlier blocks: only its diagonal tile; the tiles of the set's next step (2) are
+    // loaded as soon as the registers are free
+    if (tile_wave && set == 0 && role == 1) {
+      red2[0][lane] = 0.0;
+      if (2 < nbk) load_tiles(2);
+    }
+    if (tile_wave && set == 0 && role == 2) {
+      diag_to_lds(0);
+      if (2 < nbk) load_tiles(2);
+    }
     __syncthreads();
+    if (wv == 0) prepare_row(0);
+    // Every tile is loaded as soon as its wavefront has used the previous one, two steps before it is
+    // needed: the helpers keep the memory system busy, and one step is not always enough for a load
+    // to return.  Phase 1: the product with the block solved last (role 0 of this step's set), the
+    // next step's diagonal tile to LDS (role 2 of the other set), the next partial's first read.
+    // Phase 2: the substitution and publication of this step's block, then the next step's row of the
+    // diagonal tile into registers (wavefront 0); the next step's product with the block of this
+    // step's predecessor (role 1 of the other set); the next partial completed (wavefront 7).
     for (int step = 0; step < nbk; ++step) {
       const int i = blk(step);
       const int cur = step & 1;
       const bool in_set = tile_wave && set == cur;      // tiles of this step
       const bool in_next = tile_wave && set != cur;     // tiles of the next step
-      double rd = 0.0;
-      if (wv == 0) {
-        // this lane's equation divided by its diagonal entry, the diagonal entry itself dropped:
-        // each unknown is then final when its turn comes, and one FMA per step updates every lane
-        // (lanes already solved, and the pivot lane, multiply a zero)
-#pragma unroll
-        for (int k = 0; k < kTB; ++k) tv[k] = MODE == 0 ? Dt[cur][lane][k] : Dt[cur][k][lane];
-        rd = 1.0 / dg[cur][lane];
-#pragma unroll
-        for (int k = 0; k < kTB; ++k) tv[k] *= rd;
-      } else if (in_set && role == 0) {
+      if (in_set && role == 0) {
         // the tile next to the diagonal times the block solved last
         red[1][lane] = tile_times(xl[(step + 1) & 1]);
+        if (step + 2 < nbk) load_tiles(step + 2);
+      } else if (in_next && role == 2 && step + 1 < nbk) {
+        diag_to_lds(step + 1);
+        if (step + 3 < nbk) load_tiles(step + 3);
+      } else if (wv == 7 && step + 1 < nbk) {
+        pnext = ld_dev(&pz[(size_t)blk(step + 1) * kTB + lane]);  // completed in the second phase
       }
       __syncthreads();
       if (wv == 0) {
+        const double yv = yq[0], sv = sq[0];
         double r = (yv * ysc - pzs[cur][lane] - (red[1][lane] + red2[cur][lane])) * rd;
         if (MODE == 0) {
 #pragma unroll
@@ -239,7 +277,7 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
         }
         xl[cur][lane] = r;
         const int row = i * kTB + lane;
-        st_dev(&z[row], r);  // padded length: nbk * 64
+        st_dev(&z[row], canon(r));  // padded length: nbk * 64; the value is its own ready state
         const double o = r - coef * sv;
         if (row < n) out[row] = o;
         if (partial) {
@@ -248,23 +286,19 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
           for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
           if (lane == 0) partial[i] = q;
         }
-        stores_done();
-        if (lane == 0) __hip_atomic_store(&xflag[i], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (step + 1 < nbk) {
-          const int rn = blk(step + 1) * kTB + lane;
-          yv = rn < n ? y[rn] : 0.0;
-          sv = (sub && rn < n) ? sub[rn] : 0.0;
+#pragma unroll
+        for (int q = 0; q + 1 < kYAhead; ++q) {
+          yq[q] = yq[q + 1];
+          sq[q] = sq[q + 1];
         }
-      } else if (in_set) {
-        if (step + 2 < nbk) load_tiles(step + 2);
-      } else if (in_next) {
-        // next step: its tile two blocks from the diagonal times the block of step - 1, its diagonal tile to LDS
-        if (step + 1 < nbk) {
-          if (role == 1) two_back(step + 1);
-          else if (role == 2) diag_to_lds(step + 1);
-        }
+        read_y(step + kYAhead, yq[kYAhead - 1], sq[kYAhead - 1]);
+        if (step + 1 < nbk) prepare_row(step + 1);
+      } else if (in_next && role == 1 && step + 1 < nbk) {
+        // next step: its tile two blocks from the diagonal times the block of step - 1
+        two_back(step + 1);
+        if (step + 3 < nbk) load_tiles(step + 3);
       } else if (wv == 7) {
-        if (step + 1 < nbk) fetch_partial(step + 1);
+        if (step + 1 < nbk) finish_partial(step + 1, pnext);
       }
       __syncthreads();
     }
@@ -279,29 +313,37 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
   double accT[8];              // MODE 1: columns wv*8 .. +7, rows lane
 #pragma unroll
   for (int q = 0; q < 8; ++q) accT[q] = 0.0;
-  // the tile multiplying the block this one waits for last: load this thread's 8 values first
-  double tl[8];
-  {
-    const bool has = jstop >= 0 && jstop < nbk;
-    const double* T = MODE == 0 ? tile_ptr(Rt, i, has ? jstop : i) : tile_ptr(Rt, has ? jstop : i, i);
+  // this thread's 8 values of the tile that multiplies block jb: R(i, jb) columns wv*8 .. +7 at row
+  // lane (mode 0), R(jb, i) rows wv*8 .. +7 at column lane (mode 1, the transposed tile's rows)
+  auto load_tile = [&](int jb, double* t) {
+    const double* T = MODE == 0 ? tile_ptr(Rt, i, jb) : tile_ptr(Rt, jb, i);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) tl[q] = has ? T[(wv * 8 + q) * kTB + lane] : 0.0;
-  }
-  // Blocks of x become ready in chain order.  Per round, wavefront 0 polls the
-  // flags of up to kBatch upcoming blocks in one round trip, loads every ready
-  // block once into LDS, and all eight wavefronts then stream those tiles.
+    for (int q = 0; q < 8; ++q) t[q] = T[(wv * 8 + q) * kTB + lane];
+  };
+  auto in_range = [&](int jb) { return MODE == 0 ? jb >= jstop : jb <= jstop; };
+  // Blocks of x become ready in chain order.  Per round, wavefront 0 reads the
+  // next kBatch upcoming blocks in one round trip and stages every ready one in
+  // LDS; all eight wavefronts then multiply them.  The tile of the next block
+  // in chain order is always in flight into registers while this one is used,
+  // so a block that arrives meets its tile already loaded.
   int j = MODE == 0 ? nbk - 1 : 0;
-  while (MODE == 0 ? j >= jstop : j <= jstop) {
+  double tc[8];
+  if (in_range(j)) load_tile(j, tc);
+  while (in_range(j)) {
     if (wv == 0) {
       const int cnt = min(kBatch, MODE == 0 ? j - jstop + 1 : jstop - j + 1);
       int ready = 0;
       int spins = 0;
+      double xv[kBatch];
       while (true) {
-        int ok = 0;  // lanes past cnt count as not ready, so ~bal has a set bit at or below cnt
-        if (lane < cnt) ok = ld_flag(&xflag[j + d * -lane]) == epoch;
-        const unsigned long long bal = __ballot(ok);
-        ready = __builtin_ctzll(~bal);  // leading run of ready blocks in chain order
-        if (ready > cnt) ready = cnt;
+        // one round trip reads the next cnt blocks; a block is ready once all 64 of its slots are filled
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+          xv[b] = b < cnt ? ld_dev(&z[(size_t)(j - d * b) * kTB + lane]) : __longlong_as_double((long long)kEmpty);
+        ready = 0;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+          if (ready == b && __ballot(filled(xv[b])) == ~0ull) ready = b + 1;  // leading run in chain order
         if (ready > 0) break;
         __builtin_amdgcn_s_sleep(1);
         if ((++spins & 1023) == 0 && ld_flag(&sync[kTrsvErr]) != 0) {
@@ -314,36 +356,28 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
           break;
         }
       }
-      double xv[kBatch];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) xv[b] = b < ready ? ld_dev(&z[(size_t)(j - d * b) * kTB + lane]) : 0.0;
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) xs[b][lane] = xv[b];
+      for (int b = 0; b < kBatch; ++b) xs[b][lane] = b < ready ? xv[b] : 0.0;
       if (lane == 0) nready_sh = ready;
     }
     __syncthreads();
     const int ready = nready_sh;
     for (int b = 0; b < ready; ++b) {
       const int jb = j - d * b;
+      double tn[8];
+      const bool more = in_range(jb - d);
+      if (more) load_tile(jb - d, tn);  // the next block's tile, in flight during this product
       if (MODE == 0) {
-        if (jb == jstop) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) acc += tl[q] * xs[b][wv * 8 + q];
-        } else {
-          const double* T = tile_ptr(Rt, i, jb);
-#pragma unroll
-          for (int c = wv * 8; c < wv * 8 + 8; ++c) acc += T[c * kTB + lane] * xs[b][c];
-        }
+        for (int q = 0; q < 8; ++q) acc += tc[q] * xs[b][wv * 8 + q];
       } else {
         const double zl = xs[b][lane];
-        if (jb == jstop) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) accT[q] += tl[q] * zl;
-        } else {
-          const double* T = tile_ptr(Rt, jb, i);
+        for (int q = 0; q < 8; ++q) accT[q] += tc[q] * zl;
+      }
+      if (more) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) accT[q] += T[(wv * 8 + q) * kTB + lane] * zl;
-        }
+        for (int q = 0; q < 8; ++q) tc[q] = tn[q];
       }
     }
     __syncthreads();
@@ -367,9 +401,7 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
     if (MODE == 0)
       v = ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) +
           ((red[4][lane] + red[5][lane]) + (red[6][lane] + red[7][lane]));
-    st_dev(&pz[(size_t)i * kTB + lane], v);
-    stores_done();
-    if (lane == 0) __hip_atomic_store(&pflag[i], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    st_dev(&pz[(size_t)i * kTB + lane], canon(v));  // the value is its own ready state
   }
 }
 
@@ -394,21 +426,20 @@ void check_trsv_error(Problem& P) {
 void launch_trsv(Problem& P, const double* y, double* x, bool transpose, const double* sub_vec,
                  const LsqrState* st, int yscale_sel, int sub_sel, double* red_partials) {
   const int nbk = (int)((P.n + kTB - 1) / kTB);
-  RFM_CHECK((int64_t)kXFlags + 2 * (int64_t)nbk <= (int64_t)P.d_sync.n, RFM_EINVAL,
-            "triangular solve: too many blocks");
+  RFM_CHECK((int64_t)kTrsvErr < (int64_t)P.d_sync.n, RFM_EINVAL, "triangular solve: no sync words");
   P.d_trsv.resize((size_t)2 * nbk * kTB);
   double* z = P.d_trsv.p;                     // published blocks of x, nbk * 64
   double* pz = P.d_trsv.p + (size_t)nbk * kTB;  // helper partials, nbk * 64
   const double nn = (double)P.n;
+  const int64_t nz = 2 * (int64_t)nbk * kTB;  // z and pz are contiguous
+  hipLaunchKernelGGL(k_trsv_clear, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, P.stream, z, nz);
   ProfScope ps(P.prof, P.stream, "trsv", nn * nn, 8.0 * (nn * (nn + 1) / 2 + 3 * nn));
-  int32_t epoch = (int32_t)(++P.trsv_epoch & 0x7fffffff);
-  if (epoch == 0) epoch = (int32_t)(++P.trsv_epoch & 0x7fffffff);
   if (transpose)
     hipLaunchKernelGGL(k_trsv<1>, dim3(nbk + 1), dim3(512), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, pz, x,
-                       sub_vec, st, yscale_sel, sub_sel, red_partials, P.d_sync.p, epoch);
+                       sub_vec, st, yscale_sel, sub_sel, red_partials, P.d_sync.p);
   else
     hipLaunchKernelGGL(k_trsv<0>, dim3(nbk + 1), dim3(512), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, pz, x,
-                       sub_vec, st, yscale_sel, sub_sel, red_partials, P.d_sync.p, epoch);
+                       sub_vec, st, yscale_sel, sub_sel, red_partials, P.d_sync.p);
   RFM_HIP(hipGetLastError());
 }
 

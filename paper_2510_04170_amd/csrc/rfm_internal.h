@@ -304,7 +304,6 @@ struct Problem {
   int64_t ws_elems = 0;
   bool have_B = false, have_R = false;
   int verbose = 0;  // progress lines on stderr from long stages (set by rfm_solve from its options)
-  uint32_t trsv_epoch = 0;
   uint32_t barrier_epoch = 0;
 
   // device: work vectors
@@ -328,8 +327,9 @@ struct Problem {
 void launch_assemble(Problem& P, const double* u, double c);
 void launch_row_eval(Problem& P, const double* u, const double* du, double* out_ab);
 void launch_phi(Problem& P, const double* ab, double alpha, const double* D, double* out_sumsq);
+// field values out [npts][ncomp], or with grad its gradient out [npts][ncomp][dim]
 void launch_eval_points(Problem& P, const double* u, int64_t npts, const double* x, const int32_t* owner,
-                        double* out);
+                        double* out, bool grad = false);
 void launch_jmul(Problem& P, const double* J, const double* x, double* y, const double* u_prev,
                  const LsqrState* st, double* red_partials);
 void launch_jtmul(Problem& P, const double* J, const double* y, double* x, const LsqrState* st);
@@ -404,7 +404,8 @@ void launch_diff_norm2(Problem& P, int64_t n, const double* a, const double* b, 
 // C-ABI bodies (solver.cpp)
 rfm_status api_solve(Problem& P, const rfm_solve_opts* opts, double* u_inout, rfm_solve_stats* stats);
 rfm_status api_residual(Problem& P, const double* u, double* F, double* norm);
-rfm_status api_eval(Problem& P, const double* u, int64_t npts, const double* x, const int32_t* owner, double* out);
+rfm_status api_eval(Problem& P, const double* u, int64_t npts, const double* x, const int32_t* owner, int what,
+                    double* out);
 rfm_status api_linesearch(Problem& P, const double* u, const double* du, int gs_iters, double* alpha, double* phi);
 
 // utilities

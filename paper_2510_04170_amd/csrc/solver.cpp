@@ -39,7 +39,8 @@ struct Driver {
   // search), for the rest of the solve
   int lsqr_prec = RFM_PREC_F64;
 
-  Driver(Problem& p, const rfm_solve_opts& opts) : P(p), o(opts), lsqr_prec(opts.lsqr_prec) {
+  Driver(Problem& p, const rfm_solve_opts& opts)
+      : P(p), o(opts), jac_index(opts.jac_index0), lsqr_prec(opts.lsqr_prec) {
     ab = P.d_lsab.p;
     P.verbose = opts.verbose;
   }
@@ -195,6 +196,15 @@ struct Driver {
     return best_a;
   }
 
+  // one outer step: the directions it computed and its Flag (1: fresh J, D, R for the next one)
+  void log_outer(int inner, bool flag) {
+    if (st.outer_iters < RFM_MAX_STEPS) {
+      st.inner_steps[st.outer_iters] = inner;
+      st.flags[st.outer_iters] = flag ? 1 : 0;
+    }
+    ++st.outer_iters;
+  }
+
   void log_step(double alpha, double resn) {
     if (st.nsteps < RFM_MAX_STEPS) {
       st.alphas[st.nsteps] = alpha;
@@ -219,7 +229,7 @@ struct Driver {
       }
       double phi1 = 0.0;
       const double alpha = step(u, F, du, y, phi0, &phi1);
-      ++st.outer_iters;
+      log_outer(1, true);
       if (alpha == 0.0) {
         log_step(0.0, phi0);
         st.final_resnorm = phi0;
@@ -272,12 +282,14 @@ struct Driver {
           break;
         }
       }
-      ++st.outer_iters;
+      const int inner = std::min(i + 1, o.m_max);
       if (stalled && i == 0 && fresh) {
+        log_outer(inner, true);
         st.final_resnorm = phi_u;
         return RFM_ESTALL;
       }
       if (stalled) flag = true;
+      log_outer(inner, flag);
       const double phi_new = phiz;
       const bool done = std::fabs(phi_new - phi_u) < o.outer_tol || phi_new == 0.0;
       RFM_HIP(hipMemcpyAsync(u, z, P.n * sizeof(double), hipMemcpyDeviceToDevice, P.stream));
@@ -310,6 +322,7 @@ void check_opts(const rfm_solve_opts& o) {
             "the count sketch is formed in FP64 (its entries are signed copies of D J)");
   RFM_CHECK(o.lsqr_prec == RFM_PREC_F64 || o.lsqr_prec == RFM_PREC_F32, RFM_EINVAL,
             "opts.lsqr_prec must be F64 or F32");
+  RFM_CHECK(o.jac_index0 >= 0, RFM_EINVAL, "opts.jac_index0 must be >= 0");
 }
 
 }  // namespace
@@ -340,6 +353,7 @@ void rfm_solve_opts_default(rfm_solve_opts* o) {
   o->sketch_kind = RFM_SKETCH_GAUSSIAN;
   o->verbose = 0;
   o->sketch_rows_per_pass = 0;
+  o->jac_index0 = 0;
 }
 
 }  // extern "C"
@@ -379,8 +393,11 @@ rfm_status api_residual(Problem& P, const double* u, double* F, double* norm) {
   return RFM_OK;
 }
 
-rfm_status api_eval(Problem& P, const double* u, int64_t npts, const double* x, const int32_t* owner, double* out) {
+rfm_status api_eval(Problem& P, const double* u, int64_t npts, const double* x, const int32_t* owner, int what,
+                    double* out) {
   RFM_CHECK(npts >= 0 && (npts == 0 || (x && owner && out)), RFM_EINVAL, "rfm_eval: bad arguments");
+  RFM_CHECK(what == RFM_EVAL_VALUE || what == RFM_EVAL_GRAD, RFM_EINVAL, "rfm_eval: what must be VALUE or GRAD");
+  const int64_t per = what == RFM_EVAL_GRAD ? (int64_t)P.ncomp * P.dim : P.ncomp;
   if (npts == 0) return RFM_OK;
   copy_in(P, P.d_u.p, u, P.n);
   // owners are checked on the host before any device work
@@ -394,12 +411,12 @@ rfm_status api_eval(Problem& P, const double* u, int64_t npts, const double* x, 
   DBuf<double> dx, dout;
   DBuf<int32_t> dow;
   dx.resize((size_t)npts * P.dim);
-  dout.resize((size_t)npts * P.ncomp);
+  dout.resize((size_t)(npts * per));
   dow.resize(npts);
   copy_in(P, dx.p, x, (size_t)npts * P.dim);
   RFM_HIP(hipMemcpyAsync(dow.p, own.data(), npts * 4, hipMemcpyHostToDevice, P.stream));
-  launch_eval_points(P, P.d_u.p, npts, dx.p, dow.p, dout.p);
-  copy_out(P, out, dout.p, (size_t)npts * P.ncomp);
+  launch_eval_points(P, P.d_u.p, npts, dx.p, dow.p, dout.p, what == RFM_EVAL_GRAD);
+  copy_out(P, out, dout.p, (size_t)(npts * per));
   RFM_HIP(hipStreamSynchronize(P.stream));
   return RFM_OK;
 }

@@ -119,6 +119,33 @@ void project(Problem& P, const rfm_solve_opts& o, const double* values, double* 
   RFM_HIP(hipStreamSynchronize(Q.stream));
 }
 
+// network inputs at the PDE points: (encoded params, x) per point, X [npde][nparam + dim]; with lo and hi
+// each parameter is mapped affinely from [lo_j, hi_j] to [-1, 1]
+void warm_inputs(const Problem& P, const double* params, const double* lo, const double* hi, int nparam,
+                 float* X) {
+  RFM_CHECK((lo == nullptr) == (hi == nullptr), RFM_EINVAL, "parameter ranges: give both lo and hi, or neither");
+  std::vector<double> enc(nparam);
+  for (int j = 0; j < nparam; ++j) {
+    RFM_CHECK(std::isfinite(params[j]), RFM_ENUMERIC, "non-finite parameter");
+    if (lo) {
+      RFM_CHECK(std::isfinite(lo[j]) && std::isfinite(hi[j]) && hi[j] > lo[j], RFM_EINVAL,
+                "parameter ranges need finite lo < hi");
+      enc[j] = 2.0 * (params[j] - lo[j]) / (hi[j] - lo[j]) - 1.0;
+    } else {
+      enc[j] = params[j];
+    }
+  }
+  const int in_dim = nparam + P.dim;
+  int64_t k = 0;
+  for (const auto& g : P.groups) {
+    if (g.kind != RFM_PDE) continue;
+    for (int64_t q = 0; q < g.npts; ++q, ++k) {
+      for (int j = 0; j < nparam; ++j) X[k * in_dim + j] = (float)enc[j];
+      for (int a = 0; a < P.dim; ++a) X[k * in_dim + nparam + a] = (float)P.px[(g.pt0 + q) * P.dim + a];
+    }
+  }
+}
+
 }  // namespace
 
 }  // namespace rfm
@@ -161,10 +188,30 @@ rfm_status rfm_project(rfm_problem* p, const rfm_solve_opts* opts, const double*
   });
 }
 
-rfm_status rfm_warm_start(rfm_problem* p, rfm_mlp* net, const rfm_solve_opts* opts, const double* params,
-                          int32_t nparam, double* u_out, double* info) {
+rfm_status rfm_warm_inputs(rfm_problem* p, const double* params, const double* param_lo, const double* param_hi,
+                           int32_t nparam, float* X) {
   return guarded([&] {
-    RFM_CHECK(p && net && opts && u_out && (params || nparam == 0), RFM_EINVAL, "rfm_warm_start: NULL argument");
+    RFM_CHECK(p && X && nparam >= 0 && (params || nparam == 0), RFM_EINVAL, "rfm_warm_inputs: bad argument");
+    Problem& P = problem_of(p);
+    check(rfm_finalize(p));
+    const int64_t npde = pde_points(P);
+    std::vector<float> h((size_t)npde * (nparam + P.dim));
+    warm_inputs(P, params, param_lo, param_hi, nparam, h.data());
+    if (is_device_ptr(X)) {
+      RFM_HIP(hipSetDevice(P.device));
+      RFM_HIP(hipMemcpy(X, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+      std::copy(h.begin(), h.end(), X);
+    }
+  });
+}
+
+rfm_status rfm_warm_start(rfm_problem* p, rfm_mlp* net, const rfm_solve_opts* opts, const double* params,
+                          const double* param_lo, const double* param_hi, int32_t nparam, double* u_out,
+                          double* info) {
+  return guarded([&] {
+    RFM_CHECK(p && net && opts && u_out && nparam >= 0 && (params || nparam == 0), RFM_EINVAL,
+              "rfm_warm_start: NULL argument");
     Problem& P = problem_of(p);
     RFM_HIP(hipSetDevice(P.device));
     check(rfm_finalize(p));
@@ -173,14 +220,7 @@ rfm_status rfm_warm_start(rfm_problem* p, rfm_mlp* net, const rfm_solve_opts* op
     RFM_CHECK(npde > 0, RFM_EINVAL, "rfm_warm_start: the problem has no PDE points");
     // the network's shape must match (params, x) -> ncomp values
     std::vector<float> X((size_t)npde * in_dim);
-    int64_t k = 0;
-    for (const auto& g : P.groups) {
-      if (g.kind != RFM_PDE) continue;
-      for (int64_t q = 0; q < g.npts; ++q, ++k) {
-        for (int j = 0; j < nparam; ++j) X[k * in_dim + j] = (float)params[j];
-        for (int a = 0; a < P.dim; ++a) X[k * in_dim + nparam + a] = (float)P.px[(g.pt0 + q) * P.dim + a];
-      }
-    }
+    warm_inputs(P, params, param_lo, param_hi, nparam, X.data());
     mlp_check_shape(net, in_dim, P.ncomp);
     std::vector<float> Y((size_t)npde * P.ncomp);
     check(rfm_mlp_predict(net, X.data(), npde, Y.data()));

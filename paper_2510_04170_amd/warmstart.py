@@ -12,8 +12,9 @@ The family is the Gray-Scott workload with F ~ U(0.02, 0.06),
 k ~ U(0.04, 0.07) and the amplitude a ~ U(0.3, 0.7) of u*.  All members share
 partition, features and points, so one problem object serves every member
 (its operator and data are replaced per member) and the projection factor is
-formed once.  Network inputs are (F, k, a) mapped affinely to [-1, 1] and
-the point x; outputs the two field values.
+formed once.  Network inputs are (F, k, a) mapped affinely to [-1, 1] over the
+family's ranges (by the library, rfm_warm_inputs) and the point x; outputs the
+two field values.
 """
 from __future__ import annotations
 
@@ -29,12 +30,9 @@ import rfm_workloads as W
 from . import RFM_OK, RFM_ESTALL, RfmMLP, default_opts, from_description
 
 KEYS = ("F", "k", "amp")
-
-
-def normalise(draw) -> np.ndarray:
-    """(F, k, a) -> [-1, 1]^3 over the family's ranges."""
-    return np.array([2.0 * (v - W.GS_FAMILY[key][0]) / (W.GS_FAMILY[key][1] - W.GS_FAMILY[key][0]) - 1.0
-                     for v, key in zip(draw, KEYS)])
+# the family's parameter ranges, handed to the library, which encodes each draw onto [-1, 1]
+LO = np.array([W.GS_FAMILY[key][0] for key in KEYS])
+HI = np.array([W.GS_FAMILY[key][1] for key in KEYS])
 
 
 class Family:
@@ -46,14 +44,16 @@ class Family:
         self.lp = from_description(self.base)
         self.x, self.owner = self.lp.pde_points()
 
+    def close(self):
+        self.lp.close()
+
     def member(self, draw):
         desc = W.gray_scott_member(*draw, **self.kw)
         self.lp.update_from(desc)
         return desc
 
     def inputs(self, draw) -> np.ndarray:
-        p = normalise(draw)
-        return np.concatenate([np.repeat(p[None, :], len(self.x), 0), self.x], axis=1)
+        return self.lp.warm_inputs(np.asarray(draw, float), LO, HI)
 
 
 def relerr(lp, desc, u) -> list:
@@ -83,7 +83,7 @@ def compare(fam: Family, net: RfmMLP, draws, opts):
         t0 = time.perf_counter()
         u0, st0, rc0 = fam.lp.solve(None, opts)
         t1 = time.perf_counter()
-        uw, info = fam.lp.warm_start(net, normalise(d), opts)
+        uw, info = fam.lp.warm_start(net, np.asarray(d, float), opts, LO, HI)
         t2 = time.perf_counter()
         uw, stw, rcw = fam.lp.solve(uw, opts)
         t3 = time.perf_counter()
@@ -107,17 +107,25 @@ def run(n_train=48, n_test=4, steps=6000, batch=4096, lr=3e-3, lr_final=1e-4, wi
     fam = Family(**sizes)
     train_draws = [W.gray_scott_family_draw(100 + i) for i in range(n_train)]
     test_draws = [W.gray_scott_family_draw(1000 + i) for i in range(n_test)]
-    t0 = time.perf_counter()
-    X, Y = collect(fam, train_draws, opts)
-    t1 = time.perf_counter()
-    net = RfmMLP(3 + 3, width, depth, 2, seed=seed + 1)
-    log = net.train(X, Y, steps=steps, batch=batch, lr=lr, lr_final=lr_final, seed=seed + 7)
-    t2 = time.perf_counter()
-    rows = compare(fam, net, test_draws, opts)
+    net = None
+    try:
+        t0 = time.perf_counter()
+        X, Y = collect(fam, train_draws, opts)
+        t1 = time.perf_counter()
+        net = RfmMLP(3 + 3, width, depth, 2, seed=seed + 1)
+        log = net.train(X, Y, steps=steps, batch=batch, lr=lr, lr_final=lr_final, seed=seed + 7)
+        t2 = time.perf_counter()
+        rows = compare(fam, net, test_draws, opts)
+        n_fam, m_fam = fam.lp.n, fam.lp.m
+    finally:
+        # release the device memory now rather than at interpreter exit
+        if net is not None:
+            net.close()
+        fam.close()
     mean = lambda key, sub: float(np.mean([r[sub][key] for r in rows]))
     return dict(
         family=dict(sizes={k: list(v) if isinstance(v, tuple) else v for k, v in sizes.items()},
-                    n=fam.lp.n, m=fam.lp.m, npde=len(fam.x), train_draws=n_train, test_draws=n_test),
+                    n=n_fam, m=m_fam, npde=len(fam.x), train_draws=n_train, test_draws=n_test),
         network=dict(layers=[6] + [width] * depth + [2], steps=steps, batch=batch, lr=lr, lr_final=lr_final,
                      samples=len(X),
                      loss_first=float(log[0]) if len(log) else None, loss_last=float(log[-1]) if len(log) else None),
