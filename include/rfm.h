@@ -279,6 +279,20 @@ rfm_status rfm_get_jacobian_rows(rfm_problem* p, int64_t r0, int64_t nrows, doub
 rfm_status rfm_jmul(rfm_problem* p, const double* x, double* y);
 rfm_status rfm_jtmul(rfm_problem* p, const double* y, double* x);
 
+/* x = (D J)^T y as rfm_jtmul, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * this call allocates nothing.  y [m] and x [n] must be device pointers; the work is
+ * queued on the problem's stream and the call returns without waiting for it.  The
+ * problem must be finalized with a Jacobian assembled (rfm_stage_assemble or a solve),
+ * else RFM_EINVAL.  The per-tile partial sums go to a fixed device array of
+ * 8,388,608 doubles (64 MiB) that the library holds on every GPU it runs on until the
+ * process ends: a Jacobian needing more partials (one per stored value of a tile's
+ * row, about nnz(J)/60) is refused with RFM_EINVAL.  Every call on one GPU shares
+ * that array and nothing carries over between calls (each call writes every partial
+ * it reads), so calls whose work overlaps on one GPU -- two streams, two threads --
+ * race and must be serialised by the caller. */
+rfm_status rfm_jtmul_noalloc(rfm_problem* p, const double* y, double* x);
+
 /* Sketch B = S (D J) / sqrt(s) with s = ceil(gamma n) rows (Sec. 4.1, with a
  * Gaussian-like S in place of the count sketch), kept as the current B in FP64.
  *   prec RFM_PREC_F64: S[i][r] ~ N(0,1) from Philox4x64-10 (Salmon et al.,

@@ -126,6 +126,7 @@ _SIGS = {
     "rfm_get_jacobian_rows": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
     "rfm_jmul": (C.c_int, [_P, _D, _D]),
     "rfm_jtmul": (C.c_int, [_P, _D, _D]),
+    "rfm_jtmul_noalloc": (C.c_int, [_P, _D, _D]),
     "rfm_stage_sketch": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64, C.c_int32, C.c_int32]),
     "rfm_sketch_table": (C.c_int, [C.c_int32, _D]),
     "rfm_stage_count_sketch": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64]),
@@ -459,6 +460,13 @@ class RfmProblem:
         x = np.zeros(self.n)
         _check(lib().rfm_jtmul(self.h, y.ctypes.data, x.ctypes.data))
         return x
+
+    def jtmul_noalloc(self, y, x):
+        """x = (D J)^T y into the device tensor x from the device tensor y, without allocating (queued on
+        the problem's stream; the caller synchronises)."""
+        if not (hasattr(y, "data_ptr") and hasattr(x, "data_ptr")):
+            raise ValueError("jtmul_noalloc takes device tensors")
+        _check(lib().rfm_jtmul_noalloc(self.h, _ptr(y)[0], _ptr(x)[0]))
 
     def stage_sketch(self, gamma: float, seed: int, jac_index: int, prec: int = RFM_PREC_F64, pieces: int = 0):
         _check(lib().rfm_stage_sketch(self.h, gamma, seed, jac_index, prec, pieces))

@@ -514,6 +514,7 @@ rfm_status rfm_create(rfm_problem** out, int32_t dim, int32_t ncomp, int32_t dev
     RFM_HIP(hipGetDeviceCount(&ndev));
     RFM_CHECK(device >= 0 && device < ndev, RFM_EINVAL, "rfm_create: no such device");
     RFM_HIP(hipSetDevice(device));
+    (void)noalloc_scratch(device);  // device address of the fixed scratch of rfm_jtmul_noalloc, once per device
     auto* P = new Problem();
     P->dim = dim;
     P->ncomp = ncomp;
@@ -917,6 +918,22 @@ rfm_status rfm_jtmul(rfm_problem* p, const double* y, double* x) {
     launch_jtmul(P, P.d_J.p, dy, dx, nullptr);
     copy_out(P, x, dx, P.n);
     RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
+rfm_status rfm_jtmul_noalloc(rfm_problem* p, const double* y, double* x) {
+  return guarded([&] {
+    RFM_CHECK(p != nullptr, RFM_EINVAL, "rfm_jtmul_noalloc: NULL problem");
+    Problem& P = *reinterpret_cast<Problem*>(p);
+    RFM_CHECK(P.finalized && P.have_J, RFM_EINVAL,
+              "rfm_jtmul_noalloc: the problem needs rfm_finalize and an assembled Jacobian first");
+    RFM_CHECK(y && x && is_device_ptr(y) && is_device_ptr(x), RFM_EINVAL,
+              "rfm_jtmul_noalloc: y and x must be device pointers");
+    RFM_CHECK((size_t)P.npart <= noalloc_scratch_doubles(), RFM_EINVAL,
+              "rfm_jtmul_noalloc: the Jacobian's tile partials (" + std::to_string(P.npart) +
+                  " values) exceed the fixed scratch (" + std::to_string(noalloc_scratch_doubles()) + " values)");
+    RFM_HIP(hipSetDevice(P.device));
+    launch_jtmul_noalloc(P, y, x, noalloc_scratch(P.device));
   });
 }
 

@@ -6,6 +6,7 @@
 // (feature j on lane j mod 64), so every value of the row is produced and
 // written by consecutive lanes and the row's reductions (field values, the
 // maximum for the scale, the dot products) are wavefront reductions.
+#include <mutex>
 
 #include "rfm_internal.h"
 
@@ -1466,6 +1467,43 @@ void launch_jtmul(Problem& P, const double* J, const double* y, double* x, const
 
 void launch_jtmul(Problem& P, const float* J, const double* y, double* x, const LsqrState* st) {
   jtmul_impl(P, J, y, x, st);
+}
+
+// ---------------------------------------------------------------------------
+// J^T y without allocation (rfm_jtmul_noalloc): the tile partials live in a fixed device array instead
+// of the problem's buffer.  Every GPU the library runs on holds its own copy of the array (64 MiB) until
+// the process ends; its device address is looked up once per device, with that device current, and
+// only that address is handed to kernels (the array's name is a host-side stand-in).
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+constexpr size_t kNoallocDoubles = (size_t)8 << 20;  // 64 MiB of partial sums
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+static std::mutex g_scratch_mu;
+static double* g_scratch[kMaxDevices] = {};
+
+size_t noalloc_scratch_doubles() { return kNoallocDoubles; }
+
+double* noalloc_scratch(int device) {
+  RFM_CHECK(device >= 0 && device < kMaxDevices, RFM_EINVAL, "device index out of range for the fixed scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    int cur = -1;
+    RFM_HIP(hipGetDevice(&cur));
+    RFM_CHECK(cur == device, RFM_EINVAL, "internal: the scratch is looked up with its device current");
+    double* ptr = nullptr;
+    RFM_HIP(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+    RFM_CHECK(ptr != nullptr, RFM_EDEVICE, "no device address for the fixed scratch");
+    g_scratch[device] = ptr;
+  }
+  return g_scratch[device];
+}
+
+void launch_jtmul_noalloc(Problem& P, const double* y, double* x, double* part) {
+  hipLaunchKernelGGL(k_jtmul_tiles<double>, dim3((unsigned)(P.ntiles * Vec16<double>::K)), dim3(kWave), 0,
+                     P.stream, P.d_tiles.p, P.d_J.p, y, nullptr, part);
+  hipLaunchKernelGGL(k_jtmul_reduce, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, P.stream, P.d_tiles.p,
+                     P.d_cb_ptr.p, P.d_cb_tile.p, P.d_cb_off.p, P.J, P.n, part, nullptr, x);
+  RFM_HIP(hipGetLastError());
 }
 
 void launch_jacobian_rows(Problem& P, int64_t r0, int64_t nrows, double* out) {

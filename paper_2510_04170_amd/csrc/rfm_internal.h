@@ -338,6 +338,11 @@ void launch_jmul(Problem& P, const float* J, const double* x, double* y, const d
                  double* red_partials);
 void launch_jtmul(Problem& P, const float* J, const double* y, double* x, const LsqrState* st);
 void launch_jacobian_rows(Problem& P, int64_t r0, int64_t nrows, double* out);
+// rfm_jtmul_noalloc: the fixed device scratch (looked up once per device, with the device current), its
+// size in doubles, and J^T y with the tile partials in `part`
+double* noalloc_scratch(int device);
+size_t noalloc_scratch_doubles();
+void launch_jtmul_noalloc(Problem& P, const double* y, double* x, double* part);
 void launch_reduce_sum(Problem& P, const double* partials, int nparts, double* out);
 void launch_residual_from_ab(Problem& P, const double* ab, double* F, double* out_sumsq);
 int reduce_blocks_rows(const Problem& P);
