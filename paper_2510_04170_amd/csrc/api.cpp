@@ -317,6 +317,8 @@ static void finalize(Problem& P) {
     }
   }
   P.ntiles = (int)P.tiles_h.size();
+  P.max_tile_w = 0;
+  for (const auto& t : P.tiles_h) P.max_tile_w = std::max(P.max_tile_w, t.wA + t.wB);
   P.nvals = voff;
   P.npart = poff;
 

@@ -1241,24 +1241,26 @@ __global__ void __launch_bounds__(256) k_jmul(const TileDesc* __restrict__ tiles
   }
 }
 
-// part[tile slot + p] = sum_{rows} J[r,p] y[r] * yscale.  One wavefront per (tile, 16-byte column
-// slice of 64 lanes): each lane sums its slice over the tile's rows, reading one 16-byte piece per row,
-// with y of row r broadcast from lane r; no cross-lane work.  Tiles off the vector path are done by the
-// first wavefront of the tile with the plain loop.
+// part[tile slot + p] = sum_{rows} J[r,p] y[r] * yscale.  nk wavefronts per tile, nk = the widest
+// row's count of 64-lane 16-byte column slices, so that every slice of every tile has a wavefront of its
+// own at any row width: on the vector path (width and offset multiples of the 16-byte vector) wavefront
+// k sums slice k over the tile's rows, reading one 16-byte piece per row, with y of row r broadcast from
+// lane r, and no cross-lane work; off it, wavefront k takes columns k * 64 + lane, stepping by nk * 64.
 template <typename T>
 __global__ void __launch_bounds__(kWave) k_jtmul_tiles(const TileDesc* __restrict__ tiles,
                                                        const T* __restrict__ Jv, const double* __restrict__ y,
-                                                       const LsqrState* __restrict__ st, double* __restrict__ part) {
+                                                       const LsqrState* __restrict__ st, double* __restrict__ part,
+                                                       int nk) {
   if (st && st->done) return;
-  constexpr int V = Vec16<T>::N, NK = Vec16<T>::K;
-  const int t = blockIdx.x / NK, k = blockIdx.x % NK;
+  constexpr int V = Vec16<T>::N;
+  const int t = blockIdx.x / nk, k = blockIdx.x % nk;
   const int lane = threadIdx.x;
   const TileDesc td = tiles[t];
   const int w = td.wA + td.wB;
   const double ysc = st ? st->inv_beta : 1.0;
   const T* tile = Jv + td.val_off;
   const double yl = lane < td.nrows ? y[td.row0 + lane] * ysc : 0.0;  // lane r holds row r's y
-  if (tile_vector_path<T>(td, w)) {
+  if (w % V == 0 && td.val_off % V == 0) {
     const int pos = (k * kWave + lane) * V;
     if (k * kWave * V >= w) return;  // this slice lies past the row
     double acc[V];
@@ -1280,18 +1282,25 @@ __global__ void __launch_bounds__(kWave) k_jtmul_tiles(const TileDesc* __restric
       for (int v = 0; v < V; ++v) part[td.part_off + pos + v] = acc[v];
     }
   } else {
-    if (k != 0) return;
+    if (k * kWave >= w) return;  // uniform over the workgroup
     // lanes leave the column loop at different times: y goes through LDS, not through lane exchanges
     __shared__ double ys[kTileRows];
     ys[lane] = yl;
     __syncthreads();
-    for (int p = lane; p < w; p += kWave) {
+    for (int p = k * kWave + lane; p < w; p += nk * kWave) {
       double acc = 0.0;
       const T* col = tile + p;
       for (int rr = 0; rr < td.nrows; ++rr) acc += (double)col[(int64_t)rr * w] * ys[rr];
       part[td.part_off + p] = acc;
     }
   }
+}
+
+// wavefronts per tile of k_jtmul_tiles: 16-byte column slices of 64 lanes in the widest row
+template <typename T>
+static int jtmul_slices(const Problem& P) {
+  const int per = kWave * Vec16<T>::N;
+  return std::max(1, (P.max_tile_w + per - 1) / per);
 }
 
 // x[j] = sum over the tiles touching column block j / J, in tile order
@@ -1454,8 +1463,9 @@ template <typename T>
 static void jtmul_impl(Problem& P, const T* J, const double* y, double* x, const LsqrState* st) {
   ProfScope ps(P.prof, P.stream, sizeof(T) == 8 ? "jtmul" : "jtmul_f32", 2.0 * P.nvals,
                sizeof(T) * (double)P.nvals + 8.0 * (P.m + P.n));
-  hipLaunchKernelGGL(k_jtmul_tiles<T>, dim3((unsigned)(P.ntiles * Vec16<T>::K)), dim3(kWave), 0, P.stream,
-                     P.d_tiles.p, J, y, st, P.d_part.p);
+  const int nk = jtmul_slices<T>(P);
+  hipLaunchKernelGGL(k_jtmul_tiles<T>, dim3((unsigned)(P.ntiles * nk)), dim3(kWave), 0, P.stream, P.d_tiles.p, J, y,
+                     st, P.d_part.p, nk);
   hipLaunchKernelGGL(k_jtmul_reduce, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, P.stream, P.d_tiles.p,
                      P.d_cb_ptr.p, P.d_cb_tile.p, P.d_cb_off.p, P.J, P.n, P.d_part.p, st, x);
   RFM_HIP(hipGetLastError());
@@ -1499,8 +1509,9 @@ double* noalloc_scratch(int device) {
 }
 
 void launch_jtmul_noalloc(Problem& P, const double* y, double* x, double* part) {
-  hipLaunchKernelGGL(k_jtmul_tiles<double>, dim3((unsigned)(P.ntiles * Vec16<double>::K)), dim3(kWave), 0,
-                     P.stream, P.d_tiles.p, P.d_J.p, y, nullptr, part);
+  const int nk = jtmul_slices<double>(P);
+  hipLaunchKernelGGL(k_jtmul_tiles<double>, dim3((unsigned)(P.ntiles * nk)), dim3(kWave), 0, P.stream,
+                     P.d_tiles.p, P.d_J.p, y, nullptr, part, nk);
   hipLaunchKernelGGL(k_jtmul_reduce, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, P.stream, P.d_tiles.p,
                      P.d_cb_ptr.p, P.d_cb_tile.p, P.d_cb_off.p, P.J, P.n, part, nullptr, x);
   RFM_HIP(hipGetLastError());

@@ -251,7 +251,7 @@ struct Problem {
   // layout
   std::vector<TileDesc> tiles_h;
   int64_t nvals = 0, npart = 0;
-  int ntiles = 0;
+  int ntiles = 0, max_tile_w = 0;  // tile count, widest tile row
   std::vector<int32_t> cb_ptr_h, cb_tile_h, cb_off_h;  // column block -> contributing tiles
   std::vector<int64_t> sk_ptr_h, sk_off_h;  // column block -> its rows: d_J offset of each row's segment
   std::vector<int32_t> sk_row_h;            // ... and the row index
