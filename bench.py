@@ -52,13 +52,21 @@ PEAK_FP8_TFLOPS = 5000.0     # MI355X dense FP8 matrix
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
 
-# HBM bytes per launch of the QR's trailing-update products on the Gray-Scott workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, scaled by 2.0 and 1.0: what the
-# same counters read for an elementwise copy of 1 GiB); valid only while the kernels are unchanged,
-# so a kernel without counters taken on its current code reports null
+# HBM bytes per launch on the Gray-Scott workload, from two rocprofv3 --pmc runs of
+# `bench.py --profile-stages 1 --copy-calibration-mib 1024` (FETCH_SIZE, WRITE_SIZE in KiB per dispatch,
+# scaled by 2.0 and 1.0: what the same counters read for an elementwise copy of 1 GiB; FETCH_SIZE counts a
+# 128-byte read request as 64 bytes here, and the read-request counters by size agree with the scaled
+# figure within 0.5% for the products and the triangular solves).  A library stage spanning two kernels
+# (J^T y: tile products, then their reduction) adds both.  Valid only while the kernels are unchanged, so
+# a kernel without counters taken on its current code reports null.
 TRAFFIC_BYTES = {
-    "qr_gemm_tn": (6439910.3 * 2.0 + 276686.2 * 1.0) * 1024.0,
-    "qr_gemm_nn": (6164443.1 * 2.0 + 4851457.7 * 1.0) * 1024.0,
+    "qr_gemm_tn": (6309084.9 * 2.0 + 276686.2 * 1.0) * 1024.0,
+    "qr_gemm_nn": (6164425.4 * 2.0 + 4851457.7 * 1.0) * 1024.0,
+    "jmul": (411221.0 * 2.0 + 1525.9) * 1024.0,
+    "jmul_f32": (207244.5 * 2.0 + 1525.1) * 1024.0,
+    "jtmul": (444242.0 * 2.0 + 14187.7 + 8024.8 * 2.0 + 267.7) * 1024.0,
+    "jtmul_f32": (233541.3 * 2.0 + 14188.1 + 8024.8 * 2.0 + 267.7) * 1024.0,
+    "trsv": ((2576535.5 + 2581650.6) / 2 * 2.0 + (818.3 + 829.8) / 2) * 1024.0,
 }
 
 METRIC = "Newton solves/s at relL2<=1e-6; sketch-GEMM TFLOP/s; LSQR SpMV HBM GB/s"
@@ -317,6 +325,17 @@ def main() -> None:
     print(f"[bench] problem uploaded in {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
     n, m, nnz = lp.n, lp.m, lp.nnz
     s_rows = 2 * n
+    if a.copy_calibration_mib > 0:
+        dev = torch.device("cuda", 0)
+        nb = a.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads nb bytes, writes nb bytes
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 elementwise copies of {nb} bytes (read {nb}, write {nb} each)",
+              file=sys.stderr, flush=True)
+        del src, dst
     if a.pieces_study:
         plist = range(1, 7) if a.sketch_prec == "bf16" else range(2, 13, 2)
         res = pieces_study(lp, a.sketch_prec, plist)
@@ -340,16 +359,6 @@ def main() -> None:
     u = torch.zeros(n, dtype=torch.float64, device=dev)
     print(f"[bench] workload ready: m={m} n={n} nnz(J)={nnz}; timed form {a.form}; warmup {a.warmup}",
           file=sys.stderr, flush=True)
-    if a.copy_calibration_mib > 0:
-        nb = a.copy_calibration_mib << 20
-        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads nb bytes, writes nb bytes
-        torch.cuda.synchronize()
-        print(f"[bench] copy calibration: 3 elementwise copies of {nb} bytes (read {nb}, write {nb} each)",
-              file=sys.stderr, flush=True)
-        del src, dst
     for k in range(a.warmup):
         u.zero_()
         _, st, rc = lp.solve(u, forms[a.form])
@@ -436,9 +445,12 @@ def main() -> None:
         if not rec or rec["seconds"] <= 0:
             return None
         gbs = rec["bytes"] / rec["seconds"] / 1e9
+        tb = TRAFFIC_BYTES.get(name) if a.workload == "gray-scott" else None
         return {"GB_s": gbs, "frac_of_hbm_peak": gbs / PEAK_HBM_GBS, "launches": rec["launches"],
                 "us_per_launch": 1e6 * rec["seconds"] / rec["launches"], "bytes_per_launch": rec["bytes"] / rec["launches"],
-                "alg_bytes_formula": f"nnz*{bj} + vectors (m+n)*8 (+ m*8 for the fused LSQR update)"}
+                "alg_bytes_formula": (f"nnz*{bj} + vectors (m+n)*8 (+ m*8 for the fused LSQR update)" if name != "trsv"
+                                      else "n(n+1)/2*8 + vectors"),
+                "traffic_bytes_per_launch": tb}
 
     lsqr_spmv = {"jmul_f64": spmv(kern_f64, "jmul", 8), "jtmul_f64": spmv(kern_f64, "jtmul", 8),
                  "jmul_f32": spmv(kern_mixed, "jmul_f32", 4), "jtmul_f32": spmv(kern_mixed, "jtmul_f32", 4),
