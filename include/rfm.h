@@ -208,8 +208,8 @@ typedef struct {
                               unless B, R and the QR workspace would take more than 60% of the
                               device memory; then, or with a value > 0 (rounded down to a multiple
                               of 128, at most 98,304), B is produced that many rows at a time and
-                              each block folded into R (rfm_stage_sketch_qr_streamed).  Gaussian
-                              sketches only. */
+                              each block folded into R (rfm_stage_sketch_qr_streamed,
+                              rfm_stage_count_sketch_qr_streamed): either sketch kind. */
   int32_t jac_index0;      /* index of the solve's first Jacobian evaluation (key word 1 of the
                               sketch generator; later evaluations count up from it), so that a
                               solve can be resumed from an iterate of another one; default 0 */
@@ -358,6 +358,13 @@ rfm_status rfm_stage_qr(rfm_problem* p);
  * R's tiled storage.  RFM_ESINGULAR as rfm_stage_qr. */
 rfm_status rfm_stage_sketch_qr_streamed(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index,
                                         int32_t prec, int32_t pieces, int64_t rows_per_pass);
+
+/* The same for the count sketch of rfm_stage_count_sketch (Sec. 4.1): each pass
+ * clears its block of B's rows and sums into it the signed rows of D J whose
+ * bucket falls in the block, in ascending row order as the whole sketch does.
+ * Arguments, memory and errors as rfm_stage_sketch_qr_streamed. */
+rfm_status rfm_stage_count_sketch_qr_streamed(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index,
+                                              int64_t rows_per_pass);
 
 /* Columns [c0, c0 + ncols) of R, column-major [ncols][n] (zeros below the diagonal). */
 rfm_status rfm_get_r_cols(rfm_problem* p, int64_t c0, int64_t ncols, double* out);

@@ -138,6 +138,7 @@ _SIGS = {
     "rfm_stage_qr": (C.c_int, [_P]),
     "rfm_stage_sketch_qr_streamed": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64, C.c_int32, C.c_int32,
                                                C.c_int64]),
+    "rfm_stage_count_sketch_qr_streamed": (C.c_int, [_P, C.c_double, C.c_uint64, C.c_uint64, C.c_int64]),
     "rfm_get_r_cols": (C.c_int, [_P, C.c_int64, C.c_int64, _D]),
     "rfm_r_solve": (C.c_int, [_P, _D, _D]),
     "rfm_rt_solve": (C.c_int, [_P, _D, _D]),
@@ -503,6 +504,9 @@ class RfmProblem:
     def stage_sketch_qr_streamed(self, gamma: float, seed: int, jac_index: int, prec: int = RFM_PREC_F64,
                                  pieces: int = 0, rows_per_pass: int = 0):
         _check(lib().rfm_stage_sketch_qr_streamed(self.h, gamma, seed, jac_index, prec, pieces, rows_per_pass))
+
+    def stage_count_sketch_qr_streamed(self, gamma: float, seed: int, jac_index: int, rows_per_pass: int = 0):
+        _check(lib().rfm_stage_count_sketch_qr_streamed(self.h, gamma, seed, jac_index, rows_per_pass))
 
     def get_r_cols(self, c0: int, ncols: int) -> np.ndarray:
         out = np.zeros((ncols, self.n))

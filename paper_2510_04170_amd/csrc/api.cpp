@@ -1003,6 +1003,25 @@ rfm_status rfm_stage_sketch_qr_streamed(rfm_problem* p, double gamma, uint64_t s
   });
 }
 
+rfm_status rfm_stage_count_sketch_qr_streamed(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index,
+                                              int64_t rows_per_pass) {
+  return guarded([&] {
+    Problem& P = ready(p);
+    RFM_CHECK(P.have_J, RFM_EINVAL, "no Jacobian assembled");
+    RFM_CHECK(gamma > 1.0 && std::isfinite(gamma), RFM_EINVAL, "gamma must be > 1");
+    RFM_CHECK(rows_per_pass >= 0 && (rows_per_pass == 0 || rows_per_pass >= 128), RFM_EINVAL,
+              "rows_per_pass must be 0 or at least 128");
+    const int64_t s = (int64_t)std::ceil(gamma * (double)P.n);
+    RFM_CHECK(s >= P.n && s < (int64_t)INT32_MAX, RFM_EINVAL, "sketch size out of range");
+    P.s = s;
+    P.have_B = false;
+    P.have_R = false;
+    streamed_count_sketch_qr(P, seed, jac_index, rows_per_pass);
+    P.have_R = true;
+    RFM_HIP(hipStreamSynchronize(P.stream));
+  });
+}
+
 rfm_status rfm_get_r_cols(rfm_problem* p, int64_t c0, int64_t ncols, double* out) {
   return guarded([&] {
     Problem& P = ready(p);

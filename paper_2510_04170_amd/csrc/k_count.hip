@@ -8,8 +8,11 @@
 // Determinism without atomics: on the host, the rows that touch each column
 // block are grouped by bucket (sorted by bucket, then row); each group ("run")
 // is summed in that fixed order by one wavefront, its lanes over the block's J
-// columns, and written once.  B is cleared first, since most of it stays zero.
+// columns, and written once.  Runs are kept in bucket order, so any range of
+// B's rows is a contiguous range of runs: the streamed QR asks for B a block of
+// rows at a time, and each block is cleared and then filled by its own runs.
 #include <algorithm>
+#include <chrono>
 
 #include "rfm_internal.h"
 
@@ -23,20 +26,31 @@ struct RunDesc {
   int32_t e0, e1;  // entries [e0, e1) of the run
 };
 
+// rows r0 .. r0 + nr - 1 of B (bucket b to out[c ldo + b - r0]) from runs [0, nruns) of that range
 __global__ void __launch_bounds__(256) k_count_sketch(const RunDesc* __restrict__ runs, int64_t nruns,
                                                       const int64_t* __restrict__ eoff,
                                                       const double* __restrict__ esign,
-                                                      const double* __restrict__ Jv, int J, int64_t s,
-                                                      double* __restrict__ B) {
+                                                      const double* __restrict__ Jv, int J, int64_t r0, int64_t ldo,
+                                                      double* __restrict__ out) {
   const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (k >= nruns) return;
   const int lane = threadIdx.x % 64;
   const RunDesc rd = runs[k];
-  double* bcol = B + (int64_t)rd.blk * J * s + rd.bucket;
+  double* bcol = out + (int64_t)rd.blk * J * ldo + (rd.bucket - r0);
   for (int c = lane; c < J; c += 64) {
     double acc = 0.0;
     for (int e = rd.e0; e < rd.e1; ++e) acc += esign[e] * Jv[eoff[e] + c];
-    bcol[(int64_t)c * s] = acc;
+    bcol[(int64_t)c * ldo] = acc;
+  }
+}
+
+// out[c ldo + i] = 0 for i < nr, c < n
+__global__ void k_zero_rows(double* __restrict__ out, int64_t ldo, int64_t nr, int64_t n) {
+  const int64_t tot = nr * n;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += st) {
+    const int64_t c = q / nr, i = q - c * nr;
+    out[c * ldo + i] = 0.0;
   }
 }
 
@@ -75,9 +89,8 @@ void count_sketch_hash(int64_t r, int64_t s, uint64_t seed, uint64_t jac, int64_
   *sigma = (c[1] & 1ull) ? -1.0 : 1.0;
 }
 
-void launch_count_sketch(Problem& P, uint64_t seed, uint64_t jac_index) {
+void prepare_count_sketch(Problem& P, uint64_t seed, uint64_t jac_index) {
   const int64_t s = P.s;
-  const int J = P.J;
   const int nblk = P.geom.nbox * P.ncomp;
   RFM_CHECK(s >= 1 && s < (int64_t)INT32_MAX, RFM_EINVAL, "count sketch: sketch size out of range");
   // hash of every row
@@ -116,6 +129,10 @@ void launch_count_sketch(Problem& P, uint64_t seed, uint64_t jac_index) {
     }
   }
   RFM_CHECK(eoff.size() < (size_t)INT32_MAX, RFM_EINVAL, "count sketch: too many entries");
+  // bucket order (each run writes its own entries of B, so the order changes no value)
+  std::stable_sort(runs.begin(), runs.end(), [](const RunDesc& a, const RunDesc& b) { return a.bucket < b.bucket; });
+  P.cs_run_bucket.resize(runs.size());
+  for (size_t k = 0; k < runs.size(); ++k) P.cs_run_bucket[k] = runs[k].bucket;
   DBuf<int64_t>& d_eoff = P.d_cs_eoff;
   DBuf<double>& d_esign = P.d_cs_sign;
   DBuf<char>& d_runs = P.d_cs_runs;
@@ -127,20 +144,39 @@ void launch_count_sketch(Problem& P, uint64_t seed, uint64_t jac_index) {
     RFM_HIP(hipMemcpyAsync(d_esign.p, esign.data(), esign.size() * 8, hipMemcpyHostToDevice, P.stream));
     RFM_HIP(hipMemcpyAsync(d_runs.p, runs.data(), runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, P.stream));
   }
-  const size_t need = (size_t)s * P.n;
-  P.d_B.resize(need);
-  // algorithmic work: one signed add per stored Jacobian value; bytes: D J read once, B cleared
-  // once and its touched entries written once
-  ProfScope ps(P.prof, P.stream, "sketch_count", (double)P.nvals, 8.0 * (2.0 * (double)P.nvals + (double)need));
-  hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, P.stream, P.d_B.p, (int64_t)need);
-  const int64_t nruns = (int64_t)runs.size();
-  if (nruns)
-    hipLaunchKernelGGL(k_count_sketch, dim3((unsigned)((nruns + 3) / 4)), dim3(256), 0, P.stream,
-                       reinterpret_cast<const RunDesc*>(d_runs.p), nruns, d_eoff.p, d_esign.p, P.d_J.p, J, s,
-                       P.d_B.p);
-  RFM_HIP(hipGetLastError());
   // the host vectors above must outlive the asynchronous copies
   RFM_HIP(hipStreamSynchronize(P.stream));
+}
+
+void launch_count_sketch_rows(Problem& P, int64_t r0, int64_t nr, double* out, int64_t ldo) {
+  RFM_CHECK(r0 >= 0 && nr >= 0 && r0 + nr <= P.s && ldo >= nr, RFM_EINVAL, "count sketch: row range out of range");
+  const auto lo = std::lower_bound(P.cs_run_bucket.begin(), P.cs_run_bucket.end(), (int32_t)r0);
+  const auto hi = std::lower_bound(P.cs_run_bucket.begin(), P.cs_run_bucket.end(), (int32_t)(r0 + nr));
+  const int64_t k0 = lo - P.cs_run_bucket.begin(), nruns = hi - lo;
+  // algorithmic work: one signed add per stored Jacobian value (this range's share of them); bytes: those
+  // values read once and written once into their buckets, the block cleared once
+  const double share = (double)P.nvals * (double)nr / (double)P.s;
+  ProfScope ps(P.prof, P.stream, "sketch_count", share, 8.0 * (2.0 * share + (double)nr * P.n));
+  hipLaunchKernelGGL(k_zero_rows, dim3(4096), dim3(256), 0, P.stream, out, ldo, nr, P.n);
+  if (nruns)
+    hipLaunchKernelGGL(k_count_sketch, dim3((unsigned)((nruns + 3) / 4)), dim3(256), 0, P.stream,
+                       reinterpret_cast<const RunDesc*>(P.d_cs_runs.p) + k0, nruns, P.d_cs_eoff.p, P.d_cs_sign.p,
+                       P.d_J.p, P.J, r0, ldo, out);
+  RFM_HIP(hipGetLastError());
+}
+
+void launch_count_sketch(Problem& P, uint64_t seed, uint64_t jac_index) {
+  prepare_count_sketch(P, seed, jac_index);
+  P.d_B.resize((size_t)P.s * P.n);
+  launch_count_sketch_rows(P, 0, P.s, P.d_B.p, P.s);
+}
+
+double streamed_count_sketch_qr(Problem& P, uint64_t seed, uint64_t jac_index, int64_t rows_per_pass) {
+  const auto t0 = std::chrono::steady_clock::now();
+  prepare_count_sketch(P, seed, jac_index);
+  const double t_prep = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  auto rows = [&](int64_t r0, int64_t nr, double* out, int64_t ldo) { launch_count_sketch_rows(P, r0, nr, out, ldo); };
+  return t_prep + qr_factor_streamed(P, rows, qr_stream_rows(P, rows_per_pass));
 }
 
 }  // namespace rfm

@@ -283,6 +283,7 @@ struct Problem {
   DBuf<int64_t> d_cs_eoff;                // count sketch: d_J offsets of the grouped rows
   DBuf<double> d_cs_sign;                 //               their signs
   DBuf<char> d_cs_runs;                   //               runs of equal bucket
+  std::vector<int32_t> cs_run_bucket;     //               bucket of each run (ascending)
   DBuf<int32_t> d_pexp;                   // exponent E of each (chunk of 4 slots, column)
   int pan_prec = -1, pan_pieces = 0;
   bool have_tables = false;
@@ -358,7 +359,13 @@ void mlp_check_shape(rfm_mlp* net, int in_dim, int out_dim);
 
 // count sketch (k_count.hip)
 void count_sketch_hash(int64_t r, int64_t s, uint64_t seed, uint64_t jac, int64_t* h, double* sigma);
-void launch_count_sketch(Problem& P, uint64_t seed, uint64_t jac_index);
+void launch_count_sketch(Problem& P, uint64_t seed, uint64_t jac_index);  // all of B into d_B
+// hash the rows and upload the runs for (seed, jac_index); then rows r0 .. r0 + nr - 1 of B, cleared and
+// summed, to out[c ldo + i] (as launch_sketch_rows)
+void prepare_count_sketch(Problem& P, uint64_t seed, uint64_t jac_index);
+void launch_count_sketch_rows(Problem& P, int64_t r0, int64_t nr, double* out, int64_t ldo);
+// the count sketch streamed into qr_factor_streamed; returns the sketch seconds (hashing included)
+double streamed_count_sketch_qr(Problem& P, uint64_t seed, uint64_t jac_index, int64_t rows_per_pass);
 
 // low-precision forms (k_lowp.hip)
 void sketch_table(int prec, double* out);

@@ -62,12 +62,13 @@ struct Driver {
     P.s = (int64_t)std::ceil(o.sketch_factor * (double)P.n);
     if (o.sketch_rows_per_pass > 0 || qr_should_stream(P)) {
       // B is produced and folded into R a block of rows at a time
-      RFM_CHECK(o.sketch_kind == RFM_SKETCH_GAUSSIAN, RFM_EINVAL,
-                "the sketch is too large to hold and only the Gaussian sketch is streamed");
       P.have_B = false;
       P.have_R = false;
-      const double t_sk = streamed_sketch_qr(P, o.sketch_seed, (uint64_t)jac_index, o.sketch_prec, o.sketch_pieces,
-                                             std::max(0, o.sketch_rows_per_pass));
+      const int64_t rpp = std::max(0, o.sketch_rows_per_pass);
+      const double t_sk =
+          o.sketch_kind == RFM_SKETCH_COUNT
+              ? streamed_count_sketch_qr(P, o.sketch_seed, (uint64_t)jac_index, rpp)
+              : streamed_sketch_qr(P, o.sketch_seed, (uint64_t)jac_index, o.sketch_prec, o.sketch_pieces, rpp);
       P.have_R = true;
       double t3 = now();
       st.t_assemble += t1 - t0;

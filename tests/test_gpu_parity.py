@@ -238,6 +238,22 @@ def test_streamed_qr_matches_the_qr_of_the_whole_sketch(case):
     assert _relerr(Rs, O.qr_r(B)) < max(1e-12, 1e-15 * np.linalg.cond(B))
 
 
+def test_streamed_count_sketch_qr_matches_the_qr_of_the_whole_sketch(case):
+    """The count sketch produced 256 rows at a time (each pass clears its block and sums the buckets that
+    fall in it) and folded into R gives the factor of the whole count-sketched B."""
+    lp, DJ = case["lp"], case["DJ"]
+    lp.stage_assemble(case["u"], 100.0)
+    lp.stage_count_sketch(2.0, 1, 3)
+    B = lp.get_sketch_cols(0, lp.n)
+    lp.stage_count_sketch_qr_streamed(2.0, 1, 3, 256)
+    Rs = lp.get_r_cols(0, lp.n)
+    assert np.array_equal(np.tril(Rs, -1), np.zeros_like(Rs))
+    assert np.all(np.diag(Rs) > 0)
+    G = B.T @ B
+    assert np.abs(Rs.T @ Rs - G).max() < 1e-12 * np.abs(G).max()
+    assert _relerr(Rs, O.qr_r(B)) < max(1e-12, 1e-15 * np.linalg.cond(B))
+
+
 def test_triangular_solves(case):
     lp = case["lp"]
     lp.stage_assemble(case["u"], 100.0)
@@ -539,18 +555,20 @@ def test_pointwise_terms_can_change_after_finalize():
     lp.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "bf16", "count"])
 def test_streamed_solve_matches_the_plain_solve(prec):
-    """A whole solve with the sketch streamed 384 rows per pass follows the solve that holds B step for
-    step down to the discretisation floor: the same inner steps, preconditioner refreshes and merits
-    (1e-6 relative) until ||D F|| is within 1e-3 of its final value, and the same error against u*
-    there.  The steps after that are decided by rounding (a different summation order in the streamed
-    QR is enough to change them), so the two need not end on the same iterate."""
+    """A whole solve with the sketch streamed 384 rows per pass (Gaussian FP64 or BF16, or the count
+    sketch, whose passes clear their block and sum only the buckets that fall in it) follows the solve
+    that holds B step for step down to the discretisation floor: the same inner steps, preconditioner
+    refreshes and merits (1e-6 relative) until ||D F|| is within 1e-3 of its final value, and the same
+    error against u* there.  The steps after that are decided by rounding (a different summation order
+    in the streamed QR is enough to change them), so the two need not end on the same iterate."""
     _announce(f"streamed solve {prec}")
     prob = W.helmholtz_cosh(nsub=(2, 1, 1), J=300, q=8, test_per_dim=3)
     lp = R.from_description(prob)
-    p = R.RFM_PREC_F64 if prec == "f64" else R.RFM_PREC_BF16
-    o = dict(method=R.RFM_AMIPN, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5, sketch_prec=p)
+    p = R.RFM_PREC_BF16 if prec == "bf16" else R.RFM_PREC_F64
+    kind = R.RFM_SKETCH_COUNT if prec == "count" else R.RFM_SKETCH_GAUSSIAN
+    o = dict(method=R.RFM_AMIPN, sketch_factor=2.0, lsqr_tol=1e-10, m_max=5, sketch_prec=p, sketch_kind=kind)
     u1, st1, rc1 = lp.solve(None, R.default_opts(**o))
     u2, st2, rc2 = lp.solve(None, R.default_opts(sketch_rows_per_pass=384, **o))
     (k1, j1), (k2, j2) = _to_floor(st1), _to_floor(st2)
