@@ -167,29 +167,36 @@ def test_streamed_lowp_sketch_gives_the_same_r(case, fmt):
 
 
 def test_lsqr_on_fp32_jacobian(case):
+    """LSQR on the FP32 copy of D J (products summed in FP64) against the oracle's LSQR on the same rounded
+    matrix.  Where u32 kappa(R) <= 1e-2 the FP32 operator is a small perturbation: both converge, within 5
+    iterations of each other, to steps whose error against the FP64 least-squares step is within 10x of
+    each other.  Where it is larger, rounding D J to FP32 perturbs D J R^-1 by about u32 kappa(D J), so the
+    operator is noise in its small singular directions (the solver then falls back to FP64): there both
+    sides are measured against the least-squares step of the rounded matrix itself, the problem they
+    actually solve, after the same iteration limit."""
     lp, DJ, DF = case["lp"], case["DJ"], case["DF"]
     lp.stage_assemble(case["u"], 100.0)
     lp.stage_sketch(2.0, 1, 0, R.RFM_PREC_F64, 0)
     lp.stage_qr()
     Rg = lp.get_r_cols(0, lp.n)
     kap = np.linalg.cond(Rg)
-    if 2.0 ** -24 * kap > 1e-2:
-        # rounding D J to FP32 perturbs D J R^-1 by about u32 kappa(D J): here the
-        # FP32 operator is noise in the small singular directions and LSQR on it
-        # is not expected to converge (the solver then falls back to FP64)
-        pytest.skip(f"u32 * kappa(R) = {2.0 ** -24 * kap:.1e}: FP32 operator not usable")
+    usable = 2.0 ** -24 * kap <= 1e-2
     y, it, istop = lp.stage_lsqr(-DF, 1e-10, 500, R.RFM_PREC_F32)
     DJ32 = L.round_f32(DJ)
     ro = O.lsqr(lambda v: DJ32 @ O.r_solve(Rg, v), lambda w: O.rt_solve(Rg, DJ32.T @ w), -DF, lp.n, 1e-10, 500)
-    assert istop in (1, 2)
-    assert abs(it - ro.iters) <= 5
     du_g = lp.r_solve(y)
     du_o = O.r_solve(Rg, ro.x)
-    du_ls = np.linalg.lstsq(DJ, -DF, rcond=None)[0]
+    A = DJ if usable else DJ32
+    du_ls = np.linalg.lstsq(A, -DF, rcond=None)[0]
     nF = np.linalg.norm(DF)
-    err_g = np.linalg.norm(DJ @ (du_g - du_ls)) / nF
-    err_o = np.linalg.norm(DJ @ (du_o - du_ls)) / nF
-    print(f"{case['name']} FP32-J LSQR: step error vs FP64 lstsq: gpu {err_g:.3e} oracle {err_o:.3e}")
+    err_g = np.linalg.norm(A @ (du_g - du_ls)) / nF
+    err_o = np.linalg.norm(A @ (du_o - du_ls)) / nF
+    print(f"{case['name']} FP32-J LSQR (u32 kappa(R) = {2.0 ** -24 * kap:.1e}): iterations gpu {it} "
+          f"(stop {istop}) oracle {ro.iters}; step error vs {'FP64' if usable else 'FP32-matrix'} lstsq: "
+          f"gpu {err_g:.3e} oracle {err_o:.3e}")
+    if usable:
+        assert istop in (1, 2)
+        assert abs(it - ro.iters) <= 5
     assert err_g <= max(10 * err_o, 1e-9)
 
 
