@@ -64,8 +64,8 @@ TRAFFIC_BYTES = {
     "qr_gemm_nn": (6164425.4 * 2.0 + 4851457.7 * 1.0) * 1024.0,
     "jmul": (411221.0 * 2.0 + 1525.9) * 1024.0,
     "jmul_f32": (207244.5 * 2.0 + 1525.1) * 1024.0,
-    "jtmul": (444242.0 * 2.0 + 14187.7 + 8024.8 * 2.0 + 267.7) * 1024.0,
-    "jtmul_f32": (233541.3 * 2.0 + 14188.1 + 8024.8 * 2.0 + 267.7) * 1024.0,
+    "jtmul": (441649.0 * 2.0 + 14187.7 + 8024.8 * 2.0 + 267.7) * 1024.0,
+    "jtmul_f32": (232479.4 * 2.0 + 14187.9 + 8024.8 * 2.0 + 267.7) * 1024.0,
     "trsv": ((2576535.5 + 2581650.6) / 2 * 2.0 + (818.3 + 829.8) / 2) * 1024.0,
 }
 
