@@ -8,8 +8,10 @@ raises instead of falling back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from typing import Optional, Tuple
 
 import numpy as np
@@ -221,6 +223,20 @@ def _f32(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float32)
 
 
+# Handles still open when the interpreter exits are closed by an exit hook, while the HIP runtime is
+# still up (finalizers that run later, during interpreter teardown, would destroy them after it).
+_open_handles: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_handles():
+    for obj in list(_open_handles):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
 class RfmMLP:
     """An rfm_mlp handle: in_dim -> width (tanh) x depth -> out_dim."""
 
@@ -229,6 +245,7 @@ class RfmMLP:
         h = _P()
         _check(lib().rfm_mlp_create(C.byref(h), in_dim, width, depth, out_dim, seed, device, stream))
         self.h = h
+        _open_handles.add(self)
         self.in_dim, self.width, self.depth, self.out_dim = in_dim, width, depth, out_dim
 
     def close(self):
@@ -298,6 +315,7 @@ class RfmProblem:
         h = _P()
         _check(lib().rfm_create(C.byref(h), dim, ncomp, device, stream))
         self.h = h
+        _open_handles.add(self)
         self.dim, self.ncomp = dim, ncomp
         self.J = 0
 
