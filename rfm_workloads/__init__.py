@@ -369,6 +369,24 @@ def config1(nsub=(2, 2), J=200, q=20, seed=0, R=1.0, test_per_dim=None, pou="a")
                   seed=seed, test_per_dim=test_per_dim, pou=pou)
 
 
+def jet_line(x: np.ndarray) -> Jet:
+    X = x[:, 0]
+    pi = math.pi
+    val = np.sin(pi * X) + 0.5 * X
+    g = pi * np.cos(pi * X) + 0.5
+    lap = -pi * pi * np.sin(pi * X)
+    return val[:, None], g[:, None, None], lap[:, None], lap[:, None]
+
+
+def line_1d(nsub=(4,), J=16, q=40, seed=0, R=4.0, test_per_dim=None) -> Problem:
+    """1-D  -u'' + u^3 = f on [0, 1], u* = sin(pi x) + x / 2, Dirichlet at both ends: the degenerate
+    dimension (faces and interfaces are single points), for edge-case tests."""
+    lin = [(0, 0, -1.0, D_LAPLACE)]
+    poly = [(0, 1.0, (3,))]
+    return _build("poisson_cubic_1d", 1, 1, (0.0,), (1.0,), nsub, J, R, q, q, jet_line, lin, poly,
+                  seed=seed, test_per_dim=test_per_dim)
+
+
 GS_F, GS_K = 0.04, 0.06
 
 

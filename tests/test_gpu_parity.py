@@ -84,6 +84,11 @@ CASES = {
     "quasilinear_smooth": lambda: _with_neumann(W.quasilinear(nsub=(2, 2, 1), J=40, q=6, pou="b", test_per_dim=3)),
     # two components with the smooth partition, J = 30
     "grayscott_smooth": lambda: W.config2(nsub=(2, 2, 1), J=30, q=4, pou="b", test_per_dim=3),
+    # one dimension: boundary faces and interfaces are single points; 4 boxes, J = 16, weights and biases
+    # in [-4, 4] (m = 168, n = 64, kappa(D J) 1e8)
+    "line_1d": lambda: W.line_1d(nsub=(4,), J=16, q=40, R=4.0, test_per_dim=20),
+    # one box: no continuity rows at all; Gray-Scott pair, J = 40
+    "grayscott_one_box": lambda: W.config2(nsub=(1, 1, 1), J=40, q=5, test_per_dim=3),
 }
 
 

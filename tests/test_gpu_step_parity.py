@@ -85,6 +85,9 @@ CASES = {
     "ball_coarse": lambda: W.diffusion_reaction_ball(J=80, q=8, nbdy=600, test_per_dim=3),
     # more than 512 features per box: the register-free assembly and two sketch slabs
     "helmholtz_cosh_wide": lambda: W.helmholtz_cosh(nsub=(2, 1, 1), J=600, q=10, test_per_dim=3),
+    # one dimension (single-point faces and interfaces) and one box (no continuity rows)
+    "line_1d": lambda: W.line_1d(nsub=(4,), J=16, q=40, R=4.0, test_per_dim=20),
+    "grayscott_one_box": lambda: W.config2(nsub=(1, 1, 1), J=40, q=5, test_per_dim=3),
 }
 
 GAMMA, ETA, M_MAX = 2.0, 1e-10, 3

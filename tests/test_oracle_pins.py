@@ -821,3 +821,24 @@ def test_paper_allen_cahn_moving_hole_data_and_geometry():
     jv, jg, jl, jls = W.jet_ac_paper(g.x)
     assert np.abs(jg - grad).max() < 1e-6
     assert np.abs(jls[:, 0] - sec[:, 0, :2].sum(-1)).max() < 1e-4
+
+
+def test_one_dimensional_workload_by_manufactured_solution():
+    """The 1-D workload (single-point faces and interfaces): u*'s derivatives against central differences
+    of u* itself, the data f = -u*'' + u*^3 at the PDE points, and exact Newton reaching u*."""
+    x = np.linspace(0.05, 0.95, 9)[:, None]
+    v, g, lap, _ = W.jet_line(x)
+    h = 1e-4
+    vp, vm = W.jet_line(x + h)[0], W.jet_line(x - h)[0]
+    assert np.allclose((vp - vm) / (2 * h), g[:, :, 0], atol=1e-7)
+    assert np.allclose((vp - 2 * v + vm) / h ** 2, lap, atol=1e-5)
+    prob = W.line_1d()
+    pde = [gr for gr in prob.groups if gr.kind == W.KIND_PDE]
+    for gr in pde:
+        vv, _, ll, _ = W.jet_line(gr.x)
+        assert np.allclose(gr.data, -ll + vv ** 3, rtol=1e-13, atol=1e-13)
+    # two end points and three interface points (C0 and C1 rows each): m = 4 * 40 + 2 + 3 * 2
+    assert sum(gr.x.shape[0] for gr in prob.groups if gr.kind != W.KIND_PDE) == 2 + 3
+    assert O.row_table(prob)[1] == 4 * 40 + 2 + 3 * 2
+    u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
+    assert st.status == "ok" and O.rel_l2(prob, u)[0] < 1e-3
