@@ -840,5 +840,6 @@ def test_one_dimensional_workload_by_manufactured_solution():
     # two end points and three interface points (C0 and C1 rows each): m = 4 * 40 + 2 + 3 * 2
     assert sum(gr.x.shape[0] for gr in prob.groups if gr.kind != W.KIND_PDE) == 2 + 3
     assert O.row_table(prob)[1] == 4 * 40 + 2 + 3 * 2
+    # exact Newton gets to the discretisation's floor (4.2e-5), where its line search can end the solve
     u, st = O.ipn(prob, opts=O.Opts(mode="exact"))
-    assert st.status == "ok" and O.rel_l2(prob, u)[0] < 1e-3
+    assert st.status in ("ok", "stall") and O.rel_l2(prob, u)[0] < 1e-4
