@@ -1464,6 +1464,7 @@ void qr_factor(Problem& P) {
   hipLaunchKernelGGL(k_extract_r, dim3(nbt, nbt), dim3(256), 0, P.stream, B, s, (int)n, P.d_R.p, P.d_sync.p);
   RFM_HIP(hipGetLastError());
   E.check_flags();
+  prepare_trsv(P);
 }
 
 int64_t qr_stream_rows(const Problem& P, int64_t want) {
@@ -1558,6 +1559,7 @@ double qr_factor_streamed(Problem& P, const std::function<void(int64_t, int64_t,
   hipLaunchKernelGGL(k_r_apply_signs, dim3(nbt, nbt), dim3(256), 0, P.stream, P.d_R.p, (int)n, P.d_tau.p);
   RFM_HIP(hipGetLastError());
   E.check_flags();
+  prepare_trsv(P);
   return t_sketch;
 }
 

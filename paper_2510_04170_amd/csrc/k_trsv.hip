@@ -9,15 +9,17 @@
 //    solved in LDS, so no step of the chain waits for another workgroup's
 //    stores: per block it applies the kLook = 2 tiles next to the diagonal,
 //    subtracts the helpers' partial sum for the block, solves the 64 x 64
-//    diagonal tile by substitution in LDS and publishes the block.  Its eight wavefronts: 0 solves and publishes, with its row of the
-//    diagonal tile in registers (the substitution is the chain's longest part);
-//    1-3 and 4-6 are two sets that hold the two off-diagonal tiles and the
-//    diagonal tile of even and odd steps in registers, each set loading its next
-//    step two steps ahead.  Only the product with the block solved last is left
-//    between two substitutions: the product with the block before it and the
-//    diagonal tile's copy to LDS are done a step early.  Wavefront 7 fetches the
-//    helper partial of the next step (alone, so that its reads do not wait
-//    behind tile loads).
+//    diagonal tile by substitution and publishes the block.  It reads those
+//    three tiles from a copy made once per R (k_trsv_tiles): the diagonal tile
+//    with each row already divided by its pivot, each tile laid out so that a
+//    lane's 64 values arrive in 16-byte loads.  Its eight wavefronts: 1-3 and
+//    4-6 are two sets that hold the two off-diagonal tiles and the diagonal
+//    tile of even and odd steps in registers; the diagonal tile's wavefront
+//    substitutes and publishes its set's blocks.  Only the product with the
+//    block solved last is left between two substitutions: the product with the
+//    block before it is done a step early.  Wavefront 7 fetches the helper
+//    partial of the next step (alone, so that its reads do not wait behind tile
+//    loads); wavefront 0 reads y (and sub) ahead and writes the output.
 //  * Ticket t >= 1 is the helper of block t-th in chain order: it streams the
 //    rest of that block's row (R) or column (R^T) of tiles as the solver
 //    publishes the blocks they multiply, and publishes the partial sum.  It
@@ -46,6 +48,7 @@ namespace rfm {
 namespace {
 
 constexpr int kTB = 64;
+constexpr int kTT = kTB * kTB;
 constexpr int kSpinLimit = 1 << 26;
 constexpr int kLook = 2;   // off-diagonal tiles next to the diagonal applied by the solver
 constexpr int kBatch = 8;  // helper: upcoming blocks read per round trip
@@ -87,7 +90,8 @@ __device__ __forceinline__ double bcast(double v, int k) {
 // mode 0: R x = y   (chain from the last block up)
 // mode 1: R^T x = y (chain from the first block down)
 template <int MODE>
-__global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int n, int nbk,
+__global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, const double* __restrict__ tiles,
+                                              int n, int nbk,
                                               const double* __restrict__ y, double* __restrict__ z,
                                               double* __restrict__ pz, double* __restrict__ out,
                                               const double* __restrict__ sub, const LsqrState* __restrict__ st,
@@ -95,13 +99,13 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
                                               int32_t* __restrict__ sync) {
   if (st && st->done) return;
   __shared__ int tk_sh;
-  __shared__ double Dt[2][kTB][kTB + 1];  // solver: diagonal tiles of even and odd steps, [row][col], diagonal zeroed
-  __shared__ double dg[2][kTB];           // solver: their diagonals
   __shared__ double xs[kBatch][kTB];    // helper: ready blocks of x
   __shared__ double red[8][kTB];
   __shared__ double xl[kLook][kTB];     // solver: the last kLook solved blocks (by step parity)
   __shared__ double pzs[2][kTB];        // solver: helper partials of this and the next step
   __shared__ double red2[2][kTB];       // solver: product with the block two steps back
+  __shared__ double ysl[2][kTB];        // solver: y of this step's and the next step's block
+  __shared__ double ssl[2][kTB];        // solver: sub of the same blocks
   __shared__ int nready_sh;
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   if (tid == 0) {
@@ -122,31 +126,28 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
       coef = sub_sel == 1 ? st->beta * st->inv_alpha : 0.0;
     }
     // wavefronts 1-3 (even steps) and 4-6 (odd steps): role 0 the tile next to the diagonal, 1 the
-    // one after, 2 the diagonal tile; lane l holds row l of the tile as the solve sees it (R, or R^T
-    // in mode 1).  Wavefront 0 keeps row (mode 0) or column (mode 1) `lane` of the current diagonal
-    // tile in the same registers.
+    // one after, 2 the diagonal tile, each from the solver's copy (zero where the tile would lie past
+    // R's edge); lane l holds row l of the tile as the solve sees it (R, or R^T in mode 1).  The
+    // diagonal tile's row comes divided by its pivot, the pivot itself dropped: each unknown is then
+    // final when its turn comes, and one FMA per step updates every lane (lanes already solved, and
+    // the pivot lane, multiply a zero).  Role 2 substitutes and publishes its set's blocks.
     const int set = (wv - 1) / 3, role = (wv - 1) % 3;
     const bool tile_wave = wv >= 1 && wv <= 6;
+    const double* Tm = tiles + (size_t)MODE * nbk * 3 * kTT;  // [block][role 2, 0, 1][64 x 64]
+    const double* rdv = tiles + (size_t)2 * nbk * 3 * kTT;   // [block][64]: 1 / pivot
     double tv[kTB];
+    double rd = 0.0;  // role 2: 1 / pivot of row `lane`
     auto load_tiles = [&](int step) {
       const int i = blk(step);
-      if (role < 2) {
-        const int ij = i + (role == 0 ? d : 2 * d);
-        const bool has = ij >= 0 && ij < nbk;
-        if (MODE == 0) {
-          const double* T = tile_ptr(Rt, i, has ? ij : i);
+      // element k of lane l at (k / 2) * 128 + 2 l + k % 2: 16-byte loads, 1 KB per wavefront each
+      const double* T = Tm + ((size_t)i * 3 + (role == 2 ? 0 : role + 1)) * kTT + 2 * lane;
 #pragma unroll
-          for (int c = 0; c < kTB; ++c) tv[c] = has ? T[c * kTB + lane] : 0.0;
-        } else {
-          const double* T = tile_ptr(Rt, has ? ij : i, i);
-#pragma unroll
-          for (int r = 0; r < kTB; ++r) tv[r] = has ? T[lane * kTB + r] : 0.0;
-        }
-      } else {
-        const double* T = tile_ptr(Rt, i, i);
-#pragma unroll
-        for (int c = 0; c < kTB; ++c) tv[c] = T[c * kTB + lane];
+      for (int k = 0; k < kTB; k += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(T + k * kTB);
+        tv[k] = v.x;
+        tv[k + 1] = v.y;
       }
+      if (role == 2) rd = rdv[(size_t)i * kTB + lane];
     };
     // wavefront 7: the helper partial of `step`, a value that is its own ready state; pv holds the
     // first read (issued a phase earlier), re-read until all 64 slots are filled
@@ -184,71 +185,55 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
       }
       return (a0 + a1) + (a2 + a3);
     };
-    auto two_back = [&](int step) {  // role 1 of the set of `step`: its tile times the block of step - 2
-      red2[step & 1][lane] = tile_times(xl[step & 1]);
-    };
-    auto diag_to_lds = [&](int step) {  // role 2 of the set of `step`: tile without its diagonal, and the diagonal
-      double d = 0.0;
-#pragma unroll
-      for (int c = 0; c < kTB; ++c) {
-        Dt[step & 1][lane][c] = c == lane ? 0.0 : tv[c];
-        d = c == lane ? tv[c] : d;
-      }
-      dg[step & 1][lane] = d;
-    };
-    // wavefront 0: y (and sub) of the next kYAhead blocks in a register queue, each read kYAhead steps
-    // before its block is solved (the helpers keep the memory system busy, so one step is not always
-    // enough for a read to return)
-    constexpr int kYAhead = 4;
-    double yq[kYAhead], sq[kYAhead];
+    // wavefront 0: y (and sub) of each block read two steps before its solve and put in LDS a step
+    // before it, for the substituting wavefront (y) and for the block's output (sub), which it writes
+    // (with its share of ||out||^2) a step after the solve.  The values in flight stay in the same
+    // two registers from one step to the next: a queue shifted through registers would make every
+    // wavefront wait at the end of each step for all of its own loads in flight, the tile loads too.
+    double yn = 0.0, sn = 0.0;
     auto read_y = [&](int step, double& yv, double& sv) {
       const int row = step < nbk ? blk(step) * kTB + lane : n;
       yv = row < n ? y[row] : 0.0;
       sv = (sub && row < n) ? sub[row] : 0.0;
     };
-    // wavefront 0: the row (mode 0) or column (mode 1) `lane` of a step's diagonal tile from LDS into
-    // registers, divided by its diagonal entry, the entry itself dropped: each unknown is then final
-    // when its turn comes, and one FMA per step updates every lane (lanes already solved, and the
-    // pivot lane, multiply a zero)
-    double rd = 0.0;
-    auto prepare_row = [&](int step) {
-      const int b = step & 1;
+    auto emit = [&](int step, double r, double sv) {
+      const int i = blk(step);
+      const int row = i * kTB + lane;
+      const double o = r - coef * sv;
+      if (row < n) out[row] = o;
+      if (partial) {
+        double q = row < n ? o * o : 0.0;
 #pragma unroll
-      for (int k = 0; k < kTB; ++k) tv[k] = MODE == 0 ? Dt[b][lane][k] : Dt[b][k][lane];
-      rd = 1.0 / dg[b][lane];
-#pragma unroll
-      for (int k = 0; k < kTB; ++k) tv[k] *= rd;
+        for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
+        if (lane == 0) partial[i] = q;
+      }
     };
+    // prologue: each set's first tiles (the set of step 0 has no tile two blocks back: that product is
+    // zero, and its wavefront loads step 2's tile at once)
     if (wv == 0) {
       xl[0][lane] = 0.0;
       xl[1][lane] = 0.0;
-#pragma unroll
-      for (int q = 0; q < kYAhead; ++q) read_y(q, yq[q], sq[q]);
+      read_y(0, yn, sn);
+      ysl[0][lane] = yn;
+      ssl[0][lane] = sn;
+      read_y(1, yn, sn);
     } else if (tile_wave) {
-      if (set < nbk) load_tiles(set);
+      if (set == 0 && role == 1) {
+        red2[0][lane] = 0.0;
+        if (2 < nbk) load_tiles(2);
+      } else if (set < nbk) {
+        load_tiles(set);
+      }
     } else {
       finish_partial(0, ld_dev(&pz[(size_t)blk(0) * kTB + lane]));
     }
     __syncthreads();
-    // step 0 has no earlier blocks: only its diagonal tile; the tiles of the set's next step (2) are
-    // loaded as soon as the registers are free
-    if (tile_wave && set == 0 && role == 1) {
-      red2[0][lane] = 0.0;
-      if (2 < nbk) load_tiles(2);
-    }
-    if (tile_wave && set == 0 && role == 2) {
-      diag_to_lds(0);
-      if (2 < nbk) load_tiles(2);
-    }
-    __syncthreads();
-    if (wv == 0) prepare_row(0);
-    // Every tile is loaded as soon as its wavefront has used the previous one, two steps before it is
-    // needed: the helpers keep the memory system busy, and one step is not always enough for a load
-    // to return.  Phase 1: the product with the block solved last (role 0 of this step's set), the
-    // next step's diagonal tile to LDS (role 2 of the other set), the next partial's first read.
-    // Phase 2: the substitution and publication of this step's block, then the next step's row of the
-    // diagonal tile into registers (wavefront 0); the next step's product with the block of this
-    // step's predecessor (role 1 of the other set); the next partial completed (wavefront 7).
+    // Each tile is loaded as soon as its wavefront has used the previous one.  Phase 1: the product
+    // with the block solved last (role 0 of this step's set), the other set's diagonal tile for the
+    // next step (its role 2), the next partial's first read, the last block's output and the next
+    // step's y and sub (wavefront 0).  Phase 2: the substitution and publication of this step's block
+    // (role 2 of its set); the next step's product with the block of this step's predecessor (role 1
+    // of the other set); the next partial completed (wavefront 7).
     for (int step = 0; step < nbk; ++step) {
       const int i = blk(step);
       const int cur = step & 1;
@@ -258,16 +243,19 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
         // the tile next to the diagonal times the block solved last
         red[1][lane] = tile_times(xl[(step + 1) & 1]);
         if (step + 2 < nbk) load_tiles(step + 2);
-      } else if (in_next && role == 2 && step + 1 < nbk) {
-        diag_to_lds(step + 1);
-        if (step + 3 < nbk) load_tiles(step + 3);
-      } else if (wv == 7 && step + 1 < nbk) {
-        pnext = ld_dev(&pz[(size_t)blk(step + 1) * kTB + lane]);  // completed in the second phase
+      } else if (in_next && role == 2) {
+        if (step >= 1 && step + 1 < nbk) load_tiles(step + 1);
+      } else if (wv == 7) {
+        if (step + 1 < nbk) pnext = ld_dev(&pz[(size_t)blk(step + 1) * kTB + lane]);  // completed in phase 2
+      } else if (wv == 0) {
+        if (step >= 1) emit(step - 1, xl[(step + 1) & 1][lane], ssl[(step + 1) & 1][lane]);
+        ysl[(step + 1) & 1][lane] = yn;  // y and sub of the next step (past the last block: zeros)
+        ssl[(step + 1) & 1][lane] = sn;
+        read_y(step + 2, yn, sn);
       }
       __syncthreads();
-      if (wv == 0) {
-        const double yv = yq[0], sv = sq[0];
-        double r = (yv * ysc - pzs[cur][lane] - (red[1][lane] + red2[cur][lane])) * rd;
+      if (in_set && role == 2) {
+        double r = (ysl[cur][lane] * ysc - pzs[cur][lane] - (red[1][lane] + red2[cur][lane])) * rd;
         if (MODE == 0) {
 #pragma unroll
           for (int k = kTB - 1; k >= 0; --k) r = fma(-tv[k], bcast(r, k), r);
@@ -276,32 +264,17 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
           for (int k = 0; k < kTB; ++k) r = fma(-tv[k], bcast(r, k), r);
         }
         xl[cur][lane] = r;
-        const int row = i * kTB + lane;
-        st_dev(&z[row], canon(r));  // padded length: nbk * 64; the value is its own ready state
-        const double o = r - coef * sv;
-        if (row < n) out[row] = o;
-        if (partial) {
-          double q = row < n ? o * o : 0.0;
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
-          if (lane == 0) partial[i] = q;
-        }
-#pragma unroll
-        for (int q = 0; q + 1 < kYAhead; ++q) {
-          yq[q] = yq[q + 1];
-          sq[q] = sq[q + 1];
-        }
-        read_y(step + kYAhead, yq[kYAhead - 1], sq[kYAhead - 1]);
-        if (step + 1 < nbk) prepare_row(step + 1);
+        st_dev(&z[(size_t)i * kTB + lane], canon(r));  // padded length: nbk * 64; the value is its own ready state
       } else if (in_next && role == 1 && step + 1 < nbk) {
         // next step: its tile two blocks from the diagonal times the block of step - 1
-        two_back(step + 1);
+        red2[(step + 1) & 1][lane] = tile_times(xl[(step + 1) & 1]);
         if (step + 3 < nbk) load_tiles(step + 3);
       } else if (wv == 7) {
         if (step + 1 < nbk) finish_partial(step + 1, pnext);
       }
       __syncthreads();
     }
+    if (wv == 0) emit(nbk - 1, xl[(nbk - 1) & 1][lane], ssl[(nbk - 1) & 1][lane]);
     return;
   }
 
@@ -405,6 +378,36 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, int
   }
 }
 
+// The solver's copies of the tiles on and next to the diagonal, one workgroup per block i and mode:
+// the diagonal tile with each row (mode 0; column, mode 1) divided by its pivot and the pivot dropped,
+// then the tiles one and two blocks from the diagonal on the side solved first (zero past R's edge),
+// each with lane l's 64 values (row l of the tile as the solve sees it) in 16-byte pairs, pair p of
+// lane l at p * 128 + 2 l; after both modes, 1 / pivot of the block's 64 rows.
+__global__ void __launch_bounds__(256) k_trsv_tiles(const double* __restrict__ Rt, int nbk, double* __restrict__ tiles) {
+  const int i = blockIdx.x, mode = blockIdx.y;
+  __shared__ double A[kTB][kTB + 1];  // [row][column] of the source tile
+  __shared__ double rds[kTB];
+  double* dst = tiles + ((size_t)mode * nbk + i) * 3 * kTT;
+  for (int slot = 0; slot < 3; ++slot) {
+    const int j = slot == 0 ? i : (mode == 0 ? i + slot : i - slot);
+    const bool has = j >= 0 && j < nbk;
+    const int jj = has ? j : i;  // an in-bounds stand-in for a tile past the edge, read as zero
+    const double* T = mode == 0 ? tile_ptr(Rt, i, jj) : tile_ptr(Rt, jj, i);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTT; e += 256) A[e % kTB][e / kTB] = has ? T[e] : 0.0;
+    __syncthreads();
+    if (slot == 0 && threadIdx.x < kTB) rds[threadIdx.x] = 1.0 / A[threadIdx.x][threadIdx.x];
+    __syncthreads();
+    for (int o = threadIdx.x; o < kTT; o += 256) {
+      const int k = 2 * (o / (2 * kTB)) + (o & 1), l = (o % (2 * kTB)) / 2;
+      double v = mode == 0 ? A[l][k] : A[k][l];
+      if (slot == 0) v = (k == l ? 0.0 : v) * rds[l];
+      dst[(size_t)slot * kTT + o] = v;
+    }
+  }
+  if (mode == 0 && threadIdx.x < kTB) tiles[(size_t)2 * nbk * 3 * kTT + (size_t)i * kTB + threadIdx.x] = rds[threadIdx.x];
+}
+
 }  // namespace
 
 int trsv_block() { return kTB; }
@@ -421,12 +424,25 @@ void check_trsv_error(Problem& P) {
   }
 }
 
+static size_t trsv_tiles_size(int64_t n) {
+  const size_t nbk = (size_t)((n + kTB - 1) / kTB);
+  return 2 * nbk * 3 * kTT + nbk * kTB;
+}
+
+void prepare_trsv(Problem& P) {
+  const int nbk = (int)((P.n + kTB - 1) / kTB);
+  P.d_trsv_tiles.resize(trsv_tiles_size(P.n));
+  hipLaunchKernelGGL(k_trsv_tiles, dim3(nbk, 2), dim3(256), 0, P.stream, P.d_R.p, nbk, P.d_trsv_tiles.p);
+  RFM_HIP(hipGetLastError());
+}
+
 // x = R^{-1} (y * yscale) or R^{-T} (y * yscale); with st != null the scale and the
 // subtraction coefficient come from the LSQR state.  sub_vec may alias x.
 void launch_trsv(Problem& P, const double* y, double* x, bool transpose, const double* sub_vec,
                  const LsqrState* st, int yscale_sel, int sub_sel, double* red_partials) {
   const int nbk = (int)((P.n + kTB - 1) / kTB);
   RFM_CHECK((int64_t)kTrsvErr < (int64_t)P.d_sync.n, RFM_EINVAL, "triangular solve: no sync words");
+  RFM_CHECK(P.d_trsv_tiles.n >= trsv_tiles_size(P.n), RFM_EINVAL, "triangular solve: R has not been prepared");
   P.d_trsv.resize((size_t)2 * nbk * kTB);
   double* z = P.d_trsv.p;                     // published blocks of x, nbk * 64
   double* pz = P.d_trsv.p + (size_t)nbk * kTB;  // helper partials, nbk * 64
@@ -435,10 +451,10 @@ void launch_trsv(Problem& P, const double* y, double* x, bool transpose, const d
   hipLaunchKernelGGL(k_trsv_clear, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, P.stream, z, nz);
   ProfScope ps(P.prof, P.stream, "trsv", nn * nn, 8.0 * (nn * (nn + 1) / 2 + 3 * nn));
   if (transpose)
-    hipLaunchKernelGGL(k_trsv<1>, dim3(nbk + 1), dim3(512), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, pz, x,
+    hipLaunchKernelGGL(k_trsv<1>, dim3(nbk + 1), dim3(512), 0, P.stream, P.d_R.p, P.d_trsv_tiles.p, (int)P.n, nbk, y, z, pz, x,
                        sub_vec, st, yscale_sel, sub_sel, red_partials, P.d_sync.p);
   else
-    hipLaunchKernelGGL(k_trsv<0>, dim3(nbk + 1), dim3(512), 0, P.stream, P.d_R.p, (int)P.n, nbk, y, z, pz, x,
+    hipLaunchKernelGGL(k_trsv<0>, dim3(nbk + 1), dim3(512), 0, P.stream, P.d_R.p, P.d_trsv_tiles.p, (int)P.n, nbk, y, z, pz, x,
                        sub_vec, st, yscale_sel, sub_sel, red_partials, P.d_sync.p);
   RFM_HIP(hipGetLastError());
 }

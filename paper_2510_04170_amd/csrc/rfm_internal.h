@@ -300,6 +300,7 @@ struct Problem {
   DBuf<double> d_tau;     // Householder scalars
   DBuf<double> d_R;       // R in tiled upper storage for the triangular solves
   DBuf<double> d_trsv;    // triangular solves: published blocks of x, then the helpers' partial sums
+  DBuf<double> d_trsv_tiles;  // triangular solves: the tiles next to the diagonal in the solver's layout (from R)
   DBuf<double> d_ws;      // QR workspace
   DBuf<int32_t> d_sync;   // grid-barrier / ticket / flag words
   int64_t ws_elems = 0;
@@ -401,6 +402,8 @@ void launch_trsv(Problem& P, const double* y, double* x, bool transpose, const d
                  const LsqrState* st, int yscale_sel, int sub_sel, double* red_partials);
 int trsv_block();
 void check_trsv_error(Problem& P);
+// the solver's copies of the tiles on and next to R's diagonal; after every change of d_R
+void prepare_trsv(Problem& P);
 
 // k_lsqr.hip
 // prec: RFM_PREC_F64 multiplies by d_J, RFM_PREC_F32 by d_J32
