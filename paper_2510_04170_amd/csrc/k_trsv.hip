@@ -100,7 +100,6 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, con
   if (st && st->done) return;
   __shared__ int tk_sh;
   __shared__ double xs[kBatch][kTB];    // helper: ready blocks of x
-  __shared__ double trc[MODE == 1 ? 8 : 1][8][kTB + 1];  // helper, mode 1: column partials being summed
   __shared__ double red[8][kTB];
   __shared__ double xl[kLook][kTB];     // solver: the last kLook solved blocks (by step parity)
   __shared__ double pzs[2][kTB];        // solver: helper partials of this and the next step
@@ -357,22 +356,17 @@ __global__ void __launch_bounds__(512) k_trsv(const double* __restrict__ Rt, con
     __syncthreads();
     j -= d * ready;
   }
-  // combine: red[wv][row] (mode 0) or red[0][column] (mode 1: each column's 64 lane partials through
-  // LDS, eight to a lane, then three shuffle stages instead of six)
+  // combine: red[wv][row] (mode 0) or red[0][column] (mode 1)
   if (MODE == 0) {
     red[wv][lane] = acc;
   } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) trc[wv][q][lane] = accT[q];
-    __syncthreads();
-    const int q = lane / 8, p = lane % 8;
-    double v = 0.0;
+    for (int q = 0; q < 8; ++q) {
+      double v = accT[q];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v += trc[wv][q][p * 8 + k];
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
-    if (p == 0) red[0][wv * 8 + q] = v;
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == q) red[0][wv * 8 + q] = v;
+    }
   }
   __syncthreads();
   if (wv == 0) {
