@@ -66,7 +66,7 @@ TRAFFIC_BYTES = {
     "jmul_f32": (207244.5 * 2.0 + 1525.1) * 1024.0,
     "jtmul": (441649.0 * 2.0 + 14187.7 + 8024.8 * 2.0 + 267.7) * 1024.0,
     "jtmul_f32": (232479.4 * 2.0 + 14187.9 + 8024.8 * 2.0 + 267.7) * 1024.0,
-    "trsv": ((2576535.5 + 2581650.6) / 2 * 2.0 + (818.3 + 829.8) / 2) * 1024.0,
+    "trsv": ((2576417.4 + 2581714.9) / 2 * 2.0 + (818.3 + 829.3) / 2) * 1024.0,
 }
 
 METRIC = "Newton solves/s at relL2<=1e-6; sketch-GEMM TFLOP/s; LSQR SpMV HBM GB/s"
