@@ -344,8 +344,11 @@ rfm_status rfm_get_sketch_cols(rfm_problem* p, int64_t c0, int64_t ncols, double
 int64_t rfm_sketch_rows(const rfm_problem* p);
 
 /* Thin QR of the current sketch (Alg. 1 step 2): keeps R [n][n] upper
- * triangular with a positive diagonal.  RFM_ESINGULAR if a diagonal entry is
- * zero or not finite. */
+ * triangular with a positive diagonal, in 64 x 64 tiles of its upper triangle
+ * (n (n + 64) / 2 doubles, rounded up to whole tiles), and beside it the tiles
+ * on and next to the diagonal in the triangular solves' own layout (385 n
+ * doubles, n rounded up to a multiple of 64).  RFM_ESINGULAR if a diagonal
+ * entry is zero or not finite. */
 rfm_status rfm_stage_qr(rfm_problem* p);
 
 /* Sketch and QR without holding B (for sketches larger than the device memory
@@ -355,7 +358,7 @@ rfm_status rfm_stage_qr(rfm_problem* p);
  * folded into R by the QR of [R; B_k] (R starts at 0).  R is the factor of the
  * whole B (up to rounding), with a positive diagonal; B is not kept.  Memory:
  * (512 + rows_per_pass) x n doubles for the block and R's 512 rows in work, and
- * R's tiled storage.  RFM_ESINGULAR as rfm_stage_qr. */
+ * R's storage as rfm_stage_qr.  RFM_ESINGULAR as rfm_stage_qr. */
 rfm_status rfm_stage_sketch_qr_streamed(rfm_problem* p, double gamma, uint64_t seed, uint64_t jac_index,
                                         int32_t prec, int32_t pieces, int64_t rows_per_pass);
 
